@@ -1,0 +1,442 @@
+/*
+ * FP64 CPU oracle for the SsNAL-EN elastic-net solver (test infrastructure).
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg use
+ * this file.  It is a plain, slow, literal transcription of the method in
+ * the paper (Boschi, Reimherr, Chiaromonte, "An Efficient Semi-smooth Newton
+ * Augmented Lagrangian Method for Elastic Net"):
+ *   - no blocking, no fusion, no Sherman-Morrison-Woodbury branch: the Newton
+ *     system is always the dense m x m one;
+ *   - A^T y is recomputed from scratch every Newton iteration;
+ *   - plain loops, left-to-right sums, no BLAS.
+ * It is pinned by tests that do not use it (closed forms, brute force,
+ * KKT certificates, duality gaps, a coordinate-descent cross-check).
+ *
+ * Readings of points the paper leaves open (each also listed in the design
+ * notes of the repository):
+ *   - grad h*(y) = y + b (Sec. 3.2, eq. grad_phy; the KKT display of Sec. 3
+ *     writes y - b, which contradicts h*(y) = 1/2||y||^2 + b^T y).
+ *   - a tie |t_i| = sigma*lambda1 is inactive (eq. Q_def uses ">").
+ *   - inner stop: kkt1 <= tol; outer stop: kkt1 <= tol, kkt3 <= tol and the
+ *     primal natural residual eta(x) <= tol.
+ *   - line search: backtracking s = delta^k, delta = 0.5, at most 31 trials;
+ *     if none passes, the inner loop ends (eq. line_search gives only mu).
+ *   - the multiplier update x - sigma (A^T y + z) is evaluated as
+ *     prox_{sigma p}(x - sigma A^T y), its value by the Moreau decomposition
+ *     (Sec. 2.2); this keeps exact zeros in x.
+ *   - sigma0 defaults to 2.5 / mean_j ||a_j||^2 (= 5e-3 when the columns have
+ *     squared norm m = 500, the setting of Sec. 4.1), factor 5, capped 1e8.
+ */
+#include "oracle_en.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define COL(A, lda, j) ((A) + (int64_t)(j) * (lda))
+
+/* ---------------------------------------------------------------------- */
+/* Proximal operators and conjugate (Sec. 2.1 Prop. 1; Sec. 2.2 eq. prox_elastic) */
+
+/* prox_{sigma p}(t) = soft(t, sigma*lambda1) / (1 + sigma*lambda2)
+ * (eq. prox_elastic, left).  Pinned: 1-D numeric argmin of eq. prox_op. */
+double orc_prox_sp(double t, double sigma, double l1, double l2) {
+  double thr = sigma * l1;
+  double den = 1.0 + sigma * l2;
+  if (t > thr) return (t - thr) / den;
+  if (t < -thr) return (t + thr) / den;
+  return 0.0;
+}
+
+/* prox_{p^* / sigma}(v / sigma) as a function of v (eq. prox_elastic, right).
+ * Pinned: Moreau decomposition v = prox_{sigma p}(v) + sigma*prox_{p^* / sigma}(v/sigma)
+ * and a 1-D numeric argmin of the conjugate's prox. */
+double orc_prox_pstar(double v, double sigma, double l1, double l2) {
+  double thr = sigma * l1;
+  double den = 1.0 + sigma * l2;
+  if (v >= thr) return (v * l2 + l1) / den;
+  if (v <= -thr) return (v * l2 - l1) / den;
+  return v / sigma;
+}
+
+/* p*(z) of the elastic-net penalty (Prop. 1, eq. p_star).
+ * Pinned: numeric sup_x (z x - p(x)) in 1-D. */
+double orc_pstar(const double* z, int64_t n, double l1, double l2) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double zi = z[i], e = 0.0;
+    if (zi >= l1) e = (zi - l1) * (zi - l1);
+    else if (zi <= -l1) e = (zi + l1) * (zi + l1);
+    s += e;
+  }
+  return s / (2.0 * l2);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Dense products (plain dot products, left to right) */
+
+void orc_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* v, double* w) {
+  for (int64_t j = 0; j < n; ++j) {
+    const double* a = COL(A, lda, j);
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += a[i] * v[i];
+    w[j] = s;
+  }
+}
+
+void orc_gemv_n(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, double* out) {
+  for (int64_t i = 0; i < m; ++i) out[i] = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    double xj = x[j];
+    if (xj == 0.0) continue; /* adds +-0 only: skipping it changes no value */
+    const double* a = COL(A, lda, j);
+    for (int64_t i = 0; i < m; ++i) out[i] += a[i] * xj;
+  }
+}
+
+static double dot(const double* a, const double* b, int64_t k) {
+  double s = 0.0;
+  for (int64_t i = 0; i < k; ++i) s += a[i] * b[i];
+  return s;
+}
+
+static double nrm2(const double* a, int64_t k) { return sqrt(dot(a, a, k)); }
+
+/* ---------------------------------------------------------------------- */
+/* Objectives and certificates */
+
+/* F(x), eq. objective_function.  Pinned jointly with the dual objective:
+ * zero duality gap at closed-form / brute-force minimisers, weak duality
+ * everywhere else. */
+double orc_primal_obj(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                      const double* x, double l1, double l2) {
+  double* r = (double*)malloc(sizeof(double) * (size_t)m);
+  orc_gemv_n(A, lda, m, n, x, r);
+  for (int64_t i = 0; i < m; ++i) r[i] -= b[i];
+  double f = 0.5 * dot(r, r, m);
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t j = 0; j < n; ++j) { s1 += fabs(x[j]); s2 += x[j] * x[j]; }
+  free(r);
+  return f + l1 * s1 + 0.5 * l2 * s2;
+}
+
+/* Dual objective of (D): -h*(y) - p*(z) with z = -A^T y (the constraint
+ * A^T y + z = 0), h*(y) = 1/2||y||^2 + b^T y (Sec. 3).  Every y is feasible
+ * for lambda2 > 0 because p* is finite (Prop. 1). */
+double orc_dual_obj(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                    const double* y, double l1, double l2) {
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  orc_gemv_t(A, lda, m, n, y, z);
+  for (int64_t j = 0; j < n; ++j) z[j] = -z[j];
+  double hs = 0.5 * dot(y, y, m) + dot(b, y, m);
+  double ps = orc_pstar(z, n, l1, l2);
+  free(z);
+  return -hs - ps;
+}
+
+/* Relative primal natural residual
+ *   eta(x) = ||x - prox_p(x - A^T(Ax - b))|| / (1 + ||x|| + ||Ax - b||),
+ * prox_p(v) = soft(v, lambda1)/(1 + lambda2).  It is zero exactly at the
+ * minimiser (fixed point of the proximal-gradient map); this is the relative
+ * KKT residual the solver is gated on (the paper's own residuals are
+ * eq. kkt_res, which the solve reports too). */
+double orc_eta(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+               const double* x, double l1, double l2) {
+  double* r = (double*)malloc(sizeof(double) * (size_t)m);
+  double* g = (double*)malloc(sizeof(double) * (size_t)n);
+  orc_gemv_n(A, lda, m, n, x, r);
+  for (int64_t i = 0; i < m; ++i) r[i] -= b[i];
+  orc_gemv_t(A, lda, m, n, r, g);
+  double num = 0.0, xx = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    double p = orc_prox_sp(x[j] - g[j], 1.0, l1, l2);
+    double e = x[j] - p;
+    num += e * e;
+    xx += x[j] * x[j];
+  }
+  double den = 1.0 + sqrt(xx) + nrm2(r, m);
+  free(r);
+  free(g);
+  return sqrt(num) / den;
+}
+
+/* psi(y) of Prop. 2 (1):
+ *   h*(y) + (1+sigma*lambda2)/(2 sigma) ||prox_{sigma p}(x - sigma A^T y)||^2 - ||x||^2/(2 sigma).
+ * Pinned: equals min_z L_sigma(y, z, x) computed by 1-D minimisation. */
+double orc_psi(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+               const double* x, const double* y, double sigma, double l1, double l2) {
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  orc_gemv_t(A, lda, m, n, y, w);
+  double pp = 0.0, xx = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    double p = orc_prox_sp(fma(-sigma, w[j], x[j]), sigma, l1, l2);
+    pp += p * p;
+    xx += x[j] * x[j];
+  }
+  free(w);
+  return 0.5 * dot(y, y, m) + dot(b, y, m) + (1.0 + sigma * l2) / (2.0 * sigma) * pp -
+         xx / (2.0 * sigma);
+}
+
+/* grad psi(y) = y + b - A prox_{sigma p}(x - sigma A^T y)  (eq. grad_phy).
+ * Pinned: central differences of psi. */
+void orc_grad_psi(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                  const double* x, const double* y, double sigma, double l1, double l2,
+                  double* g) {
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u = (double*)malloc(sizeof(double) * (size_t)m);
+  orc_gemv_t(A, lda, m, n, y, w);
+  for (int64_t j = 0; j < n; ++j) w[j] = orc_prox_sp(fma(-sigma, w[j], x[j]), sigma, l1, l2);
+  orc_gemv_n(A, lda, m, n, w, u);
+  for (int64_t i = 0; i < m; ++i) g[i] = y[i] + b[i] - u[i];
+  free(w);
+  free(u);
+}
+
+/* Active set and prox at t = x - sigma*w (w = A^T y):
+ *   J = { i : |t_i| > sigma*lambda1 }   (eq. Q_def, strict; a tie is inactive)
+ *   uJ = prox_{sigma p}(t)_J            (eq. prox_elastic)
+ * t_i is fma(-sigma, w_i, x_i) (one rounding) and the threshold is the
+ * rounded product sigma*lambda1; the GPU takes the same decisions the same
+ * way, so J is compared bit for bit.  Returns r = |J| (indices ascending). */
+int64_t orc_active_prox(const double* x, const double* w, int64_t n, double sigma, double l1,
+                        double l2, int32_t* J, double* uJ) {
+  double thr = sigma * l1;
+  double den = 1.0 + sigma * l2;
+  int64_t r = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = fma(-sigma, w[i], x[i]);
+    if (t > thr) { J[r] = (int32_t)i; uJ[r] = (t - thr) / den; ++r; }
+    else if (t < -thr) { J[r] = (int32_t)i; uJ[r] = (t + thr) / den; ++r; }
+  }
+  return r;
+}
+
+/* V = I_m + kappa A_J A_J^T  (eq. AJ_system), kappa = sigma/(1+sigma*lambda2).
+ * V is m x m, row-major, both triangles filled. */
+void orc_newton_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                       double kappa, double* V) {
+  /* gather A_J as m rows of length r so each entry is one contiguous dot */
+  double* AJ = (double*)malloc(sizeof(double) * (size_t)(m * (r > 0 ? r : 1)));
+  for (int64_t k = 0; k < r; ++k) {
+    const double* a = COL(A, lda, J[k]);
+    for (int64_t i = 0; i < m; ++i) AJ[i * r + k] = a[i];
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t l = 0; l <= i; ++l) {
+      double s = dot(AJ + i * r, AJ + l * r, r);
+      double v = kappa * s + (i == l ? 1.0 : 0.0);
+      V[i * m + l] = v;
+      V[l * m + i] = v;
+    }
+  }
+  free(AJ);
+}
+
+/* In-place Cholesky V = L L^T (row-major, L in the lower triangle, the
+ * strict upper triangle zeroed).  Textbook Cholesky-Banachiewicz.
+ * Returns 0, or -(k+1) if the k-th pivot is not positive. */
+int orc_cholesky(double* V, int64_t m) {
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t j = 0; j <= i; ++j) {
+      double s = V[i * m + j];
+      for (int64_t k = 0; k < j; ++k) s -= V[i * m + k] * V[j * m + k];
+      if (i == j) {
+        if (!(s > 0.0)) return -(int)(i + 1);
+        V[i * m + i] = sqrt(s);
+      } else {
+        V[i * m + j] = s / V[j * m + j];
+      }
+    }
+    for (int64_t j = i + 1; j < m; ++j) V[i * m + j] = 0.0;
+  }
+  return 0;
+}
+
+/* Newton direction d = -V^{-1} g with V = I + kappa A_J A_J^T (eq. AJ_system),
+ * dense Cholesky and two triangular solves.  Returns 0 or the Cholesky error. */
+int orc_newton_direction(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                         double kappa, const double* g, double* d) {
+  double* V = (double*)malloc(sizeof(double) * (size_t)(m * m));
+  orc_newton_matrix(A, lda, m, J, r, kappa, V);
+  int rc = orc_cholesky(V, m);
+  if (rc == 0) {
+    /* L c = -g */
+    for (int64_t i = 0; i < m; ++i) {
+      double s = -g[i];
+      for (int64_t k = 0; k < i; ++k) s -= V[i * m + k] * d[k];
+      d[i] = s / V[i * m + i];
+    }
+    /* L^T d = c */
+    for (int64_t i = m - 1; i >= 0; --i) {
+      double s = d[i];
+      for (int64_t k = i + 1; k < m; ++k) s -= V[k * m + i] * d[k];
+      d[i] = s / V[i * m + i];
+    }
+  }
+  free(V);
+  return rc;
+}
+
+/* Armijo quantity for eq. line_search:  psi(y + s d) - psi(y).
+ * With t = x - sigma A^T y, wd = A^T d, u = prox(t), t(s) = t - s sigma wd,
+ * gd = <grad psi(y), d>, dd = ||d||^2, the identity
+ *   psi(y+sd) - psi(y) = s gd + s^2/2 dd
+ *        + sum_i [ (1+sigma l2)/(2 sigma) (prox(t_i(s))^2 - u_i^2) + s wd_i u_i ]
+ * holds exactly (expand Prop. 2 (1) and eq. grad_phy).  A summand whose
+ * t_i and t_i(s) lie on the same active side equals s^2 kappa wd_i^2 / 2,
+ * which is used in that case; it keeps the difference accurate when it is
+ * far below the size of psi itself (near convergence). */
+double orc_ls_delta(const double* t, const double* wd, int64_t n, double s, double sigma,
+                    double l1, double l2, double gd, double dd) {
+  double thr = sigma * l1;
+  double den = 1.0 + sigma * l2;
+  double kappa = sigma / den;
+  double ss = s * sigma;
+  double e = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t0 = t[i];
+    double t1 = fma(-ss, wd[i], t0);
+    double ei;
+    if ((t0 > thr && t1 > thr) || (t0 < -thr && t1 < -thr)) {
+      ei = 0.5 * s * s * kappa * wd[i] * wd[i];
+    } else {
+      double u0 = orc_prox_sp(t0, sigma, l1, l2);
+      double u1 = orc_prox_sp(t1, sigma, l1, l2);
+      ei = den / (2.0 * sigma) * (u1 * u1 - u0 * u0) + s * wd[i] * u0;
+    }
+    e += ei;
+  }
+  return s * gd + 0.5 * s * s * dd + e;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The solve: Algorithm 1 (augmented Lagrangian outer loop, semi-smooth
+ * Newton inner loop), with Prop. 2, eq. grad_phy, eq. Q_def, eq. AJ_system,
+ * eq. line_search, eq. kkt_res and the settings of Sec. 4.1. */
+int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                 double l1, double l2, const double* x0, double tol, const orc_opts* o,
+                 double* x_out, orc_info* info, double* trace, int32_t trace_cap,
+                 int32_t* trace_rows) {
+  if (m < 1 || n < 1 || lda < m || !(l1 >= 0.0) || !(l2 > 0.0) || !(tol > 0.0)) return -1;
+  orc_opts opt = {0};
+  if (o) opt = *o;
+  if (!(opt.sigma_factor > 0.0)) opt.sigma_factor = 5.0;
+  if (!(opt.sigma_max > 0.0)) opt.sigma_max = 1e8;
+  if (!(opt.mu > 0.0)) opt.mu = 0.2;
+  if (!(opt.delta > 0.0)) opt.delta = 0.5;
+  if (opt.max_outer <= 0) opt.max_outer = 100;
+  if (opt.max_inner <= 0) opt.max_inner = 50;
+  if (opt.max_backtrack <= 0) opt.max_backtrack = 30;
+  if (!(opt.sigma0 > 0.0)) {
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) { const double* a = COL(A, lda, j); s += dot(a, a, m); }
+    double mean = s / (double)n;
+    opt.sigma0 = 2.5 / (mean > 0.0 ? mean : 1.0);
+  }
+
+  double* x = x_out;
+  double* y = (double*)calloc((size_t)m, sizeof(double));
+  double* g = (double*)calloc((size_t)m, sizeof(double));
+  double* d = (double*)calloc((size_t)m, sizeof(double));
+  double* Au = (double*)calloc((size_t)m, sizeof(double));
+  double* w = (double*)calloc((size_t)n, sizeof(double));
+  double* t = (double*)calloc((size_t)n, sizeof(double));
+  double* u = (double*)calloc((size_t)n, sizeof(double));
+  double* wd = (double*)calloc((size_t)n, sizeof(double));
+  int32_t* J = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  double* uJ = (double*)calloc((size_t)n, sizeof(double));
+
+  /* x0 (or 0); y0 = A x0 - b, the KKT-consistent dual start */
+  for (int64_t j = 0; j < n; ++j) x[j] = x0 ? x0[j] : 0.0;
+  orc_gemv_n(A, lda, m, n, x, y);
+  for (int64_t i = 0; i < m; ++i) y[i] -= b[i];
+
+  double normb = nrm2(b, m);
+  double sigma = opt.sigma0;
+  double kkt1 = INFINITY, kkt3 = INFINITY, eta = INFINITY;
+  int status = 1, stalled = 0, newton = 0, outer = 0, outer_done = 0, rows = 0;
+  int64_t r = 0;
+
+  for (outer = 0; outer < opt.max_outer; ++outer) {
+    double den = 1.0 + sigma * l2;
+    double kappa = sigma / den;
+    /* ---- semi-smooth Newton on psi (Algorithm 1, lower half) ---- */
+    for (int inner = 0;; ++inner) {
+      orc_gemv_t(A, lda, m, n, y, w); /* fresh A^T y */
+      r = orc_active_prox(x, w, n, sigma, l1, l2, J, uJ);
+      for (int64_t i = 0; i < n; ++i) { t[i] = fma(-sigma, w[i], x[i]); u[i] = 0.0; }
+      for (int64_t k = 0; k < r; ++k) u[J[k]] = uJ[k];
+      orc_gemv_n(A, lda, m, n, u, Au);
+      for (int64_t i = 0; i < m; ++i) g[i] = y[i] + b[i] - Au[i]; /* eq. grad_phy */
+      kkt1 = nrm2(g, m) / (1.0 + normb);                          /* eq. kkt_res */
+      if (kkt1 <= tol || inner >= opt.max_inner) break;
+      if (orc_newton_direction(A, lda, m, J, r, kappa, g, d) != 0) { stalled = 1; break; }
+      orc_gemv_t(A, lda, m, n, d, wd);
+      double gd = dot(g, d, m), dd = dot(d, d, m);
+      double s = 1.0;
+      int ok = 0;
+      for (int k = 0; k <= opt.max_backtrack; ++k) {
+        if (orc_ls_delta(t, wd, n, s, sigma, l1, l2, gd, dd) <= opt.mu * s * gd) { ok = 1; break; }
+        s *= opt.delta;
+      }
+      if (trace && rows < trace_cap) {
+        double* row = trace + (int64_t)rows * ORC_TRACE_COLS;
+        row[0] = outer; row[1] = inner; row[2] = (double)r; row[3] = sigma;
+        row[4] = ok ? s : 0.0; row[5] = kkt1;
+        ++rows;
+      }
+      if (!ok) { stalled = 1; break; }
+      for (int64_t i = 0; i < m; ++i) y[i] += s * d[i];
+      ++newton;
+    }
+    /* ---- multiplier update (Algorithm 1, step (2)) ---- */
+    /* z = prox_{p^* / sigma}(x/sigma - A^T y) (Prop. 2 (2)), from the final inner iterate */
+    double zz = 0.0, xu = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double zi = orc_prox_pstar(t[i], sigma, l1, l2);
+      zz += zi * zi;
+      double e = x[i] - u[i];
+      xu += e * e;
+    }
+    /* A^T y + z = (x - u)/sigma by the Moreau decomposition */
+    kkt3 = sqrt(xu) / sigma / (1.0 + nrm2(y, m) + sqrt(zz)); /* eq. kkt_res */
+    for (int64_t i = 0; i < n; ++i) x[i] = u[i];           /* x - sigma(A^T y + z) */
+    ++outer_done;
+    if (kkt1 <= tol && kkt3 <= tol) {
+      eta = orc_eta(A, lda, b, m, n, x, l1, l2);
+      if (eta <= tol) { status = 0; break; }
+    }
+    if (stalled) break;
+    sigma = sigma * opt.sigma_factor;
+    if (sigma > opt.sigma_max) sigma = opt.sigma_max;
+  }
+  if (status != 0) {
+    eta = orc_eta(A, lda, b, m, n, x, l1, l2);
+    if (stalled) status = 2;
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->outer_iters = outer_done;
+    info->newton_iters = newton;
+    info->r_final = (int32_t)r;
+    int64_t nnz = 0;
+    for (int64_t j = 0; j < n; ++j) nnz += (x[j] != 0.0);
+    info->nnz = nnz;
+    info->eta = eta;
+    info->kkt1 = kkt1;
+    info->kkt3 = kkt3;
+    info->primal_obj = orc_primal_obj(A, lda, b, m, n, x, l1, l2);
+    double* res = (double*)malloc(sizeof(double) * (size_t)m);
+    orc_gemv_n(A, lda, m, n, x, res);
+    for (int64_t i = 0; i < m; ++i) res[i] -= b[i];
+    info->dual_obj = orc_dual_obj(A, lda, b, m, n, res, l1, l2);
+    free(res);
+    info->rel_gap = (info->primal_obj - info->dual_obj) / (1.0 + fabs(info->primal_obj));
+    info->sigma_final = sigma;
+  }
+  if (trace_rows) *trace_rows = rows;
+  free(y); free(g); free(d); free(Au); free(w); free(t); free(u); free(wd); free(J); free(uJ);
+  return status;
+}

@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Primitives (prox pair, conjugate, psi, grad psi, Newton matrix, Cholesky,
+line-search increment) are checked against numeric 1-D optimisation, finite
+differences, the Moreau identity and library routines; the whole solve is
+checked against closed forms, brute-force enumeration, KKT certificates,
+duality gaps, a coordinate-descent solver and invariances.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from tests import pinlib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RNG = np.random.default_rng(20200606)
+
+
+# ---------------------------------------------------------------- primitives
+
+def test_fig1_values(orc):
+    """Prox pair and conjugate at the Fig. 1 setting (lambda1=lambda2=sigma=1)."""
+    tab = np.loadtxt(os.path.join(HERE, "golden", "fig1_prox_en.txt"))
+    for v, psp, pps, pv, psv in tab:
+        assert orc.prox_sp(v, 1.0, 1.0, 1.0) == pytest.approx(psp, abs=1e-15)
+        assert orc.prox_pstar(v, 1.0, 1.0, 1.0) == pytest.approx(pps, abs=1e-15)
+        assert orc.pstar(np.array([v]), 1.0, 1.0) == pytest.approx(psv, abs=1e-15)
+        assert pinlib.en_penalty(np.array([v]), 1.0, 1.0) == pytest.approx(pv, abs=1e-15)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_prox_sp_is_argmin(orc, case):
+    """eq. prox_elastic (left) against the definition eq. prox_op, minimised numerically."""
+    g = np.random.default_rng(100 + case)
+    sigma, l1, l2 = g.uniform(0.05, 5), g.uniform(0.0, 2), g.uniform(0.01, 3)
+    t = g.uniform(-4, 4) * max(1.0, sigma * l1)
+    f = lambda u: l1 * abs(u) + 0.5 * l2 * u * u + (u - t) ** 2 / (2 * sigma)
+    u_num = pinlib.argmin_1d(f, -abs(t) - 1, abs(t) + 1)
+    # a numeric argmin is accurate to ~sqrt(eps) relative (the objective is flat there)
+    assert orc.prox_sp(t, sigma, l1, l2) == pytest.approx(u_num, abs=1e-6 * (1 + abs(u_num)))
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_pstar_is_sup(orc, case):
+    """Prop. 1 against sup_x (z x - p(x)) computed numerically."""
+    g = np.random.default_rng(200 + case)
+    l1, l2 = g.uniform(0.01, 2), g.uniform(0.05, 3)
+    z = g.uniform(-5, 5)
+    f = lambda x: -(z * x - l1 * abs(x) - 0.5 * l2 * x * x)
+    xs = pinlib.argmin_1d(f, -50, 50)
+    assert orc.pstar(np.array([z]), l1, l2) == pytest.approx(-f(xs), abs=1e-9)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_prox_pstar_moreau_and_argmin(orc, case):
+    """eq. prox_elastic (right): Moreau decomposition and the prox definition of p*/sigma."""
+    g = np.random.default_rng(300 + case)
+    sigma, l1, l2 = g.uniform(0.05, 5), g.uniform(0.01, 2), g.uniform(0.05, 3)
+    v = g.uniform(-4, 4) * max(1.0, sigma * l1)
+    a = orc.prox_sp(v, sigma, l1, l2)
+    c = orc.prox_pstar(v, sigma, l1, l2)
+    assert a + sigma * c == pytest.approx(v, rel=1e-14, abs=1e-14)
+    # prox_{p*/sigma}(v/sigma) = argmin_z p*(z)/sigma + |z - v/sigma|^2 / 2
+    f = lambda z: orc.pstar(np.array([z]), l1, l2) / sigma + 0.5 * (z - v / sigma) ** 2
+    z_num = pinlib.argmin_1d(f, -abs(v / sigma) - 5, abs(v / sigma) + 5)
+    assert c == pytest.approx(z_num, abs=1e-6 * (1 + abs(z_num)))
+
+
+def _small_problem(seed, m=12, n=40):
+    g = np.random.default_rng(seed)
+    A, b, l1, l2 = pinlib.gaussian_problem(m, n, seed, k=4, c_lam=0.4)
+    x = np.zeros(n)
+    idx = g.choice(n, 6, replace=False)
+    x[idx] = g.standard_normal(6)
+    y = g.standard_normal(m)
+    sigma = g.uniform(0.3, 3.0)
+    return A, b, l1, l2, x, y, sigma
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_psi_is_min_over_z(orc, seed):
+    """Prop. 2 (1): psi(y) = min_z L_sigma(y, z | x), minimised coordinate-wise."""
+    A, b, l1, l2, x, y, sigma = _small_problem(seed)
+    w = A.T @ y
+    total = 0.5 * y @ y + b @ y
+    for i in range(A.shape[1]):
+        f = lambda z: (orc.pstar(np.array([z]), l1, l2) - x[i] * (w[i] + z)
+                       + 0.5 * sigma * (w[i] + z) ** 2)
+        c = -w[i] + x[i] / sigma
+        zi = pinlib.argmin_1d(f, c - 20, c + 20)
+        total += f(zi)
+    assert orc.psi(A.T, b, x, y, sigma, l1, l2) == pytest.approx(total, rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", [4, 5, 6])
+def test_grad_psi_finite_differences(orc, seed):
+    """eq. grad_phy against central differences of psi (psi is C^1)."""
+    A, b, l1, l2, x, y, sigma = _small_problem(seed)
+    g = orc.grad_psi(A.T, b, x, y, sigma, l1, l2)
+    h = 1e-6
+    fd = np.array([(orc.psi(A.T, b, x, y + h * e, sigma, l1, l2)
+                    - orc.psi(A.T, b, x, y - h * e, sigma, l1, l2)) / (2 * h)
+                   for e in np.eye(A.shape[0])])
+    assert np.max(np.abs(fd - g)) <= 1e-6 * (1 + np.max(np.abs(g)))
+
+
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_newton_matrix_is_generalized_hessian(orc, seed):
+    """eq. Q_def / eq. AJ_system: V e_k equals the derivative of grad psi along
+    e_k wherever the active set is locally constant."""
+    A, b, l1, l2, x, y, sigma = _small_problem(seed)
+    m = A.shape[0]
+    w = A.T @ y
+    J, _ = orc.active_prox(x, w, sigma, l1, l2)
+    kappa = sigma / (1 + sigma * l2)
+    V = orc.newton_matrix(A.T, J, kappa)
+    h = 1e-7
+    for k in range(m):
+        e = np.zeros(m)
+        e[k] = h
+        Jp, _ = orc.active_prox(x, A.T @ (y + e), sigma, l1, l2)
+        Jm, _ = orc.active_prox(x, A.T @ (y - e), sigma, l1, l2)
+        if not (np.array_equal(Jp, J) and np.array_equal(Jm, J)):
+            continue
+        col = (orc.grad_psi(A.T, b, x, y + e, sigma, l1, l2)
+               - orc.grad_psi(A.T, b, x, y - e, sigma, l1, l2)) / (2 * h)
+        assert np.max(np.abs(col - V[:, k])) <= 1e-6 * (1 + np.max(np.abs(V)))
+    assert np.allclose(V, V.T)
+
+
+def test_active_set_rule_and_tie(orc):
+    """eq. Q_def: strict inequality; a tie |t| = sigma*lambda1 is inactive."""
+    sigma, l1, l2 = 0.5, 2.0, 0.3
+    thr = sigma * l1
+    x = np.array([thr, -thr, thr + 1e-9, 0.0, 3.0, -3.0])
+    w = np.zeros_like(x)
+    J, uJ = orc.active_prox(x, w, sigma, l1, l2)
+    assert J.tolist() == [2, 4, 5]
+    for j, u in zip(J, uJ):
+        assert u == orc.prox_sp(x[j], sigma, l1, l2)
+
+
+def test_cholesky_against_library(orc):
+    g = np.random.default_rng(11)
+    M = g.standard_normal((30, 50))
+    V = np.eye(30) + 0.7 * M @ M.T
+    L = orc.cholesky(V)
+    assert np.allclose(np.triu(L, 1), 0.0)
+    assert np.allclose(L, np.linalg.cholesky(V), rtol=1e-12, atol=1e-12)
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.cholesky(-np.eye(4))
+
+
+@pytest.mark.parametrize("seed", [12, 13])
+def test_newton_direction_solves_system(orc, seed):
+    A, b, l1, l2, x, y, sigma = _small_problem(seed)
+    J, _ = orc.active_prox(x, A.T @ y, sigma, l1, l2)
+    kappa = sigma / (1 + sigma * l2)
+    g = orc.grad_psi(A.T, b, x, y, sigma, l1, l2)
+    d = orc.newton_direction(A.T, J, kappa, g)
+    V = orc.newton_matrix(A.T, J, kappa)
+    assert np.linalg.norm(V @ d + g) <= 1e-12 * (1 + np.linalg.norm(g))
+    assert g @ d < 0  # descent direction
+
+
+@pytest.mark.parametrize("seed", [14, 15, 16])
+def test_ls_delta_equals_psi_difference(orc, seed):
+    """The line-search increment equals psi(y + s d) - psi(y) (Prop. 2 (1))."""
+    A, b, l1, l2, x, y, sigma = _small_problem(seed)
+    g = orc.grad_psi(A.T, b, x, y, sigma, l1, l2)
+    d = np.random.default_rng(seed).standard_normal(A.shape[0])
+    t = x - sigma * (A.T @ y)
+    wd = A.T @ d
+    for s in (1.0, 0.5, 0.125, 2.0 ** -10):
+        got = orc.ls_delta(t, wd, s, sigma, l1, l2, g @ d, d @ d)
+        ref = orc.psi(A.T, b, x, y + s * d, sigma, l1, l2) - orc.psi(A.T, b, x, y, sigma, l1, l2)
+        assert got == pytest.approx(ref, rel=1e-8, abs=1e-11)
+
+
+def test_objectives_weak_duality_and_zero_gap(orc):
+    """F and D: D(y) <= F(x) for arbitrary x, y; equality at the orthonormal closed form."""
+    A = pinlib.orthonormal_design(40, 15, 3)
+    g = np.random.default_rng(4)
+    b = g.standard_normal(40)
+    l1, l2 = 0.3, 0.4
+    for _ in range(5):
+        x, y = g.standard_normal(15), g.standard_normal(40)
+        assert orc.dual_obj(A.T, b, y, l1, l2) <= orc.primal_obj(A.T, b, x, l1, l2) + 1e-12
+    xs = pinlib.soft(A.T @ b, l1) / (1 + l2)
+    F = orc.primal_obj(A.T, b, xs, l1, l2)
+    D = orc.dual_obj(A.T, b, A @ xs - b, l1, l2)
+    assert F == pytest.approx(pinlib.primal_objective(A, b, xs, l1, l2), rel=1e-14)
+    assert abs(F - D) <= 1e-13 * (1 + F)
+    assert orc.eta(A.T, b, xs, l1, l2) <= 1e-15
+    assert orc.eta(A.T, b, xs + 1e-3 * g.standard_normal(15), l1, l2) > 1e-5
+
+
+def test_gemv_against_numpy(orc):
+    g = np.random.default_rng(5)
+    AT = g.standard_normal((301, 77))
+    v = g.standard_normal(77)
+    assert np.allclose(orc.gemv_t(AT, v), AT @ v, rtol=1e-13, atol=1e-13)
+    x = g.standard_normal(301)
+    x[::3] = 0
+    assert np.allclose(orc.gemv_n(AT, x), AT.T @ x, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- the solve
+
+def _solve(orc, A, b, l1, l2, tol=1e-12, **kw):
+    x, info, _ = orc.en_solve(np.ascontiguousarray(A.T), b, l1, l2, tol=tol, **kw)
+    return x, info
+
+
+@pytest.mark.parametrize("m,n", [(40, 10), (30, 30), (50, 12)])
+def test_orthonormal_closed_form(orc, m, n):
+    """m >= n and A^T A = I: x_i = soft(a_i^T b, lambda1)/(1 + lambda2)."""
+    A = pinlib.orthonormal_design(m, n, m + n)
+    b = np.random.default_rng(m * n).standard_normal(m) * 2
+    for l1, l2 in [(0.5, 0.25), (0.05, 1.5), (1.2, 0.01)]:
+        x, info = _solve(orc, A, b, l1, l2)
+        ref = pinlib.soft(A.T @ b, l1) / (1 + l2)
+        assert info["status"] == 0
+        assert np.max(np.abs(x - ref)) <= 1e-10
+        assert np.array_equal(x != 0, ref != 0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_small(orc, seed):
+    """Support/sign enumeration at n <= 12 (both m < n and m > n)."""
+    g = np.random.default_rng(500 + seed)
+    m, n = (8, 12) if seed % 2 == 0 else (20, 9)
+    A, b, l1, l2 = pinlib.gaussian_problem(m, n, 500 + seed, k=3, c_lam=g.uniform(0.15, 0.7),
+                                           alpha=g.uniform(0.3, 0.9))
+    xb, Fb = pinlib.brute_force_en(A, b, l1, l2)
+    x, info = _solve(orc, A, b, l1, l2)
+    assert info["status"] == 0
+    assert np.max(np.abs(x - xb)) <= 1e-9 * (1 + np.max(np.abs(xb)))
+    assert np.array_equal(x != 0, xb != 0)
+    assert info["primal_obj"] == pytest.approx(Fb, rel=1e-12)
+
+
+def test_zero_solution_threshold(orc):
+    """x* = 0 iff lambda1 >= ||A^T b||_inf (c_lambda >= 1 in the lambda recipe of Sec. 4.1)."""
+    A, b, _, _ = pinlib.gaussian_problem(30, 200, 8)
+    lmax = np.max(np.abs(A.T @ b))
+    for c, zero in [(1.0, True), (1.01, True), (0.99, False)]:
+        x, info = _solve(orc, A, b, c * lmax, 0.3)
+        assert info["status"] == 0
+        assert (np.count_nonzero(x) == 0) == zero
+
+
+def test_ridge_limit(orc):
+    """lambda1 = 0: x = A^T (A A^T + lambda2 I)^{-1} b (J = all columns)."""
+    A, b, _, _ = pinlib.gaussian_problem(20, 60, 9)
+    l2 = 0.7
+    x, info = _solve(orc, A, b, 0.0, l2)
+    ref = A.T @ np.linalg.solve(A @ A.T + l2 * np.eye(20), b)
+    assert info["status"] == 0
+    assert np.max(np.abs(x - ref)) <= 1e-10
+
+
+def test_single_feature(orc):
+    """n = 1: x = soft(a^T b, lambda1)/(|a|^2 + lambda2)."""
+    g = np.random.default_rng(10)
+    a = g.standard_normal(15) * 0.8
+    b = g.standard_normal(15)
+    for l1 in (0.0, 0.3, abs(a @ b) * 0.9, abs(a @ b) * 1.1):
+        x, info = _solve(orc, a[:, None], b, l1, 0.45)
+        ref = pinlib.soft(a @ b, l1) / (a @ a + 0.45)
+        assert info["status"] == 0
+        assert x[0] == pytest.approx(ref, abs=1e-11)
+
+
+def test_kkt_certificate_and_gap(orc):
+    """KKT of the primal (0 in A^T(Ax-b) + lambda2 x + lambda1 d|x|_1) and the
+    duality gap of the returned point, at the small benchmark workload."""
+    import datagen
+    p = datagen.make_problem("c1", seed=3)
+    A = p.AT.T
+    x, info = _solve(orc, A, p.b, p.lam1, p.lam2, tol=1e-10)
+    assert info["status"] == 0 and info["eta"] <= 1e-10
+    assert pinlib.kkt_violation(A, p.b, x, p.lam1, p.lam2) <= 1e-9
+    F = pinlib.primal_objective(A, p.b, x, p.lam1, p.lam2)
+    assert info["primal_obj"] == pytest.approx(F, rel=1e-13)
+    assert (info["primal_obj"] - info["dual_obj"]) / (1 + F) <= 1e-11
+
+
+def test_coordinate_descent_cross_check(orc):
+    """Independent cyclic coordinate descent reaches the same minimiser."""
+    A, b, l1, l2 = pinlib.gaussian_problem(60, 400, 12, k=8, c_lam=0.3)
+    x, info = _solve(orc, A, b, l1, l2)
+    xc = pinlib.coordinate_descent_en(A, b, l1, l2)
+    Fo, Fc = pinlib.primal_objective(A, b, x, l1, l2), pinlib.primal_objective(A, b, xc, l1, l2)
+    assert abs(Fo - Fc) <= 1e-12 * Fc
+    assert np.max(np.abs(x - xc)) <= 1e-7
+    assert np.array_equal(np.abs(x) > 1e-8, np.abs(xc) > 1e-8)
+
+
+@pytest.mark.parametrize("sigma0,factor", [(5e-3, 5), (0.1, 5), (1.0, 10), (2.5, 5), (10.0, 10)])
+def test_sigma_independence(orc, sigma0, factor):
+    """The minimiser does not depend on the penalty schedule (Sec. 4.1 and the
+    screening runs of the supplement use 5e-3 x5 and 1 x10)."""
+    A, b, l1, l2 = pinlib.gaussian_problem(40, 300, 13, k=5, c_lam=0.35)
+    x0, _ = _solve(orc, A, b, l1, l2)
+    x, info = _solve(orc, A, b, l1, l2, sigma0=sigma0, sigma_factor=factor)
+    assert info["status"] == 0
+    F0, F = pinlib.primal_objective(A, b, x0, l1, l2), pinlib.primal_objective(A, b, x, l1, l2)
+    assert abs(F - F0) <= 1e-12 * F0
+    assert np.max(np.abs(x - x0)) <= 1e-8
+
+
+def test_invariances(orc):
+    """Column permutation permutes x; flipping a column flips its coefficient;
+    (b, lambda1, lambda2) -> (c b, c lambda1, lambda2) scales x by c."""
+    A, b, l1, l2 = pinlib.gaussian_problem(30, 120, 14, k=4, c_lam=0.4)
+    x, _ = _solve(orc, A, b, l1, l2)
+    perm = np.random.default_rng(1).permutation(120)
+    xp, _ = _solve(orc, A[:, perm], b, l1, l2)
+    assert np.max(np.abs(xp - x[perm])) <= 1e-10
+    A2 = A.copy()
+    A2[:, 5] *= -1
+    A2[:, 17] *= -1
+    x2, _ = _solve(orc, A2, b, l1, l2)
+    x_ref = x.copy()
+    x_ref[[5, 17]] *= -1
+    assert np.max(np.abs(x2 - x_ref)) <= 1e-10
+    x3, _ = _solve(orc, A, 3.0 * b, 3.0 * l1, l2)
+    assert np.max(np.abs(x3 - 3.0 * x)) <= 1e-9
+
+
+def test_warm_start_same_point(orc):
+    """A warm start from a nearby solution reaches the same minimiser (Sec. 3.4)."""
+    A, b, l1, l2 = pinlib.gaussian_problem(40, 500, 15, k=6, c_lam=0.3)
+    x1, _ = _solve(orc, A, b, l1 * 1.1, l2 * 1.1)
+    x_cold, ic = _solve(orc, A, b, l1, l2)
+    x_warm, iw = _solve(orc, A, b, l1, l2, x0=x1)
+    assert iw["status"] == 0
+    assert np.max(np.abs(x_warm - x_cold)) <= 1e-9
+
+
+def test_status_not_converged(orc):
+    A, b, l1, l2 = pinlib.gaussian_problem(30, 200, 16)
+    x, info = _solve(orc, A, b, l1, l2, tol=1e-14, max_outer=1)
+    assert info["status"] == 1
