@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark: elastic-net solves/s at relative KKT residual <= 1e-6 on one MI355X.
+
+Workload: m=500 observations, n=100,000 features in blocks of 50 with Toeplitz
+correlation rho=0.6, 20 true nonzeros, SNR 5, alpha=0.5, lambda=0.3*lambda_max,
+tol 1e-6 (synthetic, seeded).  One step = one complete SsNAL-EN solve from a
+cold start, the design already resident in HBM.  `value` is the mixed-
+precision path (design stored in FP32, FP32 accumulation in A^T v and the
+Newton matrix, FP64 Cholesky / line search / KKT residual, FP64-accumulated
+refresh of A^T y); the plain FP64 path on the same problem is reported beside
+it.  The roofline entry is the A^T v kernel, timed live with HIP events around
+each of its launches on the solve's stream.  The CPU baseline is the FP64
+oracle on the machine's host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def _traffic_from_profile(kernel_src, store):
+    """HBM bytes per A^T v launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"gemv_t_block_toeplitz_m500_n100000_{store}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = datagen.CONFIGS["c2"]
+    t0 = time.time()
+    p64 = datagen.make_problem("c2", seed=args.seed, store="f64")
+    AT32 = p64.AT.astype(np.float32)
+    print(f"[bench] generated m={p64.m} n={p64.n} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    A64 = design_to_device(p64.AT, "f64")
+    A32 = design_to_device(AT32, "f32")
+    b = vec_to_device(p64.b)
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def run(A, steps, timing):
+        opts = binding.make_opts(timing=1 if timing else 0)
+        infos = []
+        x = torch.empty(p64.n, dtype=torch.float64, device=dev)
+        for _ in range(steps):
+            _, info = binding.ssnal_en_solve(ctx, A, b, p64.lam1, p64.lam2, tol=p64.tol, x_out=x,
+                                             opts=opts, stream=stream)
+            if info["status"] != 0:
+                raise RuntimeError(f"solve did not converge: {info}")
+            infos.append(info)
+        return infos, x
+
+    def timed(A, label):
+        run(A, args.warmup, True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos, x = run(A, args.steps, True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        print(f"[bench] {label}: {args.steps} solves in {el:.3f}s", file=sys.stderr, flush=True)
+        return el, infos, x
+
+    el32, inf32, x32 = timed(A32, "mixed f32")
+    el64, inf64, x64 = timed(A64, "fp64")
+
+    def gemv_stats(infos, s_a):
+        calls = sum(i["gemv_calls"] for i in infos)
+        ms = sum(i["gemv_ms"] for i in infos)
+        avg_s = ms / calls / 1e3
+        bytes_per_launch = float(p64.m) * p64.n * s_a
+        return avg_s, bytes_per_launch, calls / len(infos)
+
+    avg32, bpl32, calls32 = gemv_stats(inf32, 4)
+    avg64, bpl64, calls64 = gemv_stats(inf64, 8)
+    achieved = bpl32 / avg32 / 1e9
+    traffic = _traffic_from_profile(os.path.join(ROOT, "paper_2006_03970_amd", "csrc", "k_gemv.hip"), "f32")
+
+    out = {
+        "metric": "EN solves/s at KKT<=1e-6 (mixed FP32 storage)",
+        "value": args.steps / el32,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "block-Toeplitz elastic net, m=500, n=100000, rho=0.6, blocks of 50, "
+                        "k=20, snr=5, alpha=0.5, c_lambda=0.3, tol=1e-6",
+            "m": p64.m, "n": p64.n, "precision": "A in FP32 (FP32 accumulation in A^T v and "
+            "A_J A_J^T); FP64 Cholesky, line search, KKT residual, FP64-accumulated A^T y refresh",
+            "parallelism": "single GPU",
+        },
+        "fp64_solves_per_s": args.steps / el64,
+        "fp64_ms_per_step": el64 / args.steps * 1e3,
+        "mixed_over_fp64": (args.steps / el32) / (args.steps / el64),
+        "eta": {"mixed_f32": inf32[-1]["kkt_rel"], "fp64": inf64[-1]["kkt_rel"]},
+        "iterations": {"mixed_f32": [inf32[-1]["outer_iters"], inf32[-1]["newton_iters"]],
+                       "fp64": [inf64[-1]["outer_iters"], inf64[-1]["newton_iters"]]},
+        "gemv_launches_per_solve": {"mixed_f32": calls32, "fp64": calls64},
+        "gemv_gbs": {"mixed_f32": achieved, "fp64": bpl64 / avg64 / 1e9},
+        "roofline": {
+            "bound": "hbm", "kernel": "A^T v (k_gemv_t, FP32 design)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": bpl32, "avg_launch_us": avg32 * 1e6,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        if not os.path.exists(oracle.LIB_PATH):
+            oracle.build()
+        nsolve = 0
+        t = time.perf_counter()
+        while True:
+            oracle.en_solve(p64.AT, p64.b, p64.lam1, p64.lam2, tol=p64.tol)
+            nsolve += 1
+            if time.perf_counter() - t > 10.0 or nsolve >= 12:
+                break
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {
+            "value": nsolve / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsolve} complete FP64 oracle solves of the same problem (tol 1e-6), "
+                      "single thread",
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * ssnal_en.h -- C ABI of the MI355X (gfx950) SsNAL-EN elastic-net solver.
+ *
+ * Problem (Sec. 1, eq. objective_function):
+ *     min_x  1/2 ||A x - b||^2 + lambda1 ||x||_1 + lambda2/2 ||x||^2,
+ * A in R^{m x n} with n >> m, solved by the semi-smooth Newton augmented
+ * Lagrangian method of Sec. 3 (Algorithm 1): an augmented-Lagrangian outer
+ * loop on the dual (D) whose sub-problem, min_y psi(y) of Prop. 2, is solved
+ * by a semi-smooth Newton method with the reduced system eq. AJ_system (or its
+ * r x r form eq. smw_formula) and the line search eq. line_search.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are DEVICE pointers owned by the caller (e.g. torch tensors),
+ *     unless a parameter says "host".
+ *   - A is column-major with leading dimension lda >= m, stored as
+ *     ssnal_dtype: FP64, FP32 or BF16 (bfloat16 bit patterns, uint16).
+ *     Offsets are 64-bit: m*n may exceed 2^31.  The streaming kernels read
+ *     16 bytes per lane when A is 16-byte aligned and lda*sizeof(elem) is a
+ *     multiple of 16; other layouts take a slower element-wise path.
+ *     Entries of A in rows m..lda-1 are never used.
+ *   - b, x0, x_out, and every other vector are FP64, contiguous.
+ *   - Work is enqueued on `stream` (a hipStream_t; 0 = null stream).  Calls
+ *     that report results to the host return after their work completes.
+ *   - One ssnal_ctx per device and per host thread; a context is not
+ *     thread-safe.  Calls on one context serialise.
+ *   - Return value: 0 success; > 0 a result with a warning; < 0 an error, with
+ *     a message available from ssnal_last_error() (per calling thread).  The
+ *     library never aborts the process.
+ */
+#ifndef SSNAL_EN_H
+#define SSNAL_EN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage type of A */
+typedef enum { SSNAL_F64 = 0, SSNAL_F32 = 1, SSNAL_BF16 = 2 } ssnal_dtype;
+
+/* status codes */
+#define SSNAL_OK 0
+#define SSNAL_NOT_CONVERGED 1     /* max_outer reached; x_out holds the last iterate */
+#define SSNAL_LINESEARCH_STALL 2  /* no trial step passed eq. line_search and eta > tol */
+#define SSNAL_EINVAL (-1)         /* invalid argument (message says which) */
+#define SSNAL_ENONFINITE (-2)     /* NaN or Inf in b, x0 or A^T b */
+#define SSNAL_ENOMEM (-3)         /* device workspace allocation failed */
+#define SSNAL_EHIP (-4)           /* a HIP runtime call failed */
+#define SSNAL_ENUMERIC (-5)       /* Cholesky met a non-positive pivot */
+
+typedef struct ssnal_ctx ssnal_ctx;
+
+/*
+ * Solver options.  Zero (or negative) fields take the defaults, so a
+ * zero-initialised struct is the default configuration.  The defaults are
+ * the settings of Sec. 4.1 (mu = 0.2, sigma multiplied by 5 per outer
+ * iteration) with sigma0 scaled to the column norms (5e-3 at squared norm
+ * 500, the setting of Sec. 4.1).
+ */
+typedef struct {
+  double sigma0;         /* <= 0: 2.5 / mean_j ||a_j||^2 */
+  double sigma_factor;   /* <= 0: 5 */
+  double sigma_max;      /* <= 0: 1e8 */
+  double mu;             /* <= 0: 0.2, Armijo constant of eq. line_search */
+  double delta;          /* <= 0: 0.5, backtracking factor */
+  int32_t max_outer;     /* <= 0: 100 augmented-Lagrangian iterations */
+  int32_t max_inner;     /* <= 0: 50 Newton iterations per sub-problem */
+  int32_t max_backtrack; /* <= 0: 30 (trial steps 1, delta, ..., delta^30; at most 31) */
+  int32_t no_refine;     /* FP32/BF16 storage: 0 = refresh A^T y with FP64 accumulation
+                            before each multiplier update (default); 1 = never */
+  int32_t no_smw;        /* 0 = r < m uses the r x r system of eq. smw_formula (default);
+                            1 = always the m x m system of eq. AJ_system */
+  int32_t timing;        /* 1 = time every A^T v launch with HIP events (info->gemv_ms) */
+  int32_t trace_cap;     /* rows available in `trace` (0 = no trace) */
+  double* trace;         /* HOST, nullable: one row per Newton iteration:
+                            outer, inner, r, sigma, step, kkt1 (6 doubles) */
+} ssnal_en_opts;
+
+typedef struct {
+  int32_t status;        /* same code as the return value */
+  int32_t outer_iters;   /* multiplier updates performed */
+  int32_t newton_iters;  /* Newton steps taken */
+  int32_t r_final;       /* |J| at the last iterate = nonzeros of x */
+  int64_t nnz;
+  double kkt_rel;        /* eta(x) = ||x - prox_p(x - A^T(Ax-b))|| / (1+||x||+||Ax-b||),
+                            FP64 accumulation over the stored A; the gated residual */
+  double kkt1;           /* eq. kkt_res, first residual, at the last iterate */
+  double kkt3;           /* eq. kkt_res, third residual, at the last multiplier update */
+  double primal_obj;     /* F(x) */
+  double dual_obj;       /* D(Ax - b), Prop. 1 conjugate */
+  double rel_gap;        /* (F - D) / (1 + |F|) */
+  double sigma_final;
+  int32_t gemv_calls;    /* full A^T v passes over the n columns */
+  int32_t syncs;         /* device-to-host synchronisations */
+  double gemv_ms;        /* with opts.timing: summed durations of the A^T v launches */
+  double solve_ms;       /* host wall time of the call */
+} ssnal_en_info;
+
+/* Fill *opts with the defaults listed above. */
+void ssnal_en_opts_init(ssnal_en_opts* opts);
+
+/*
+ * Create a context on `device` (HIP ordinal).  The context owns the device
+ * workspace, sized lazily to the largest problem seen; it holds O(n) FP64
+ * vectors, an m x m FP64 matrix and split-K partial sums (bounded by
+ * (2048 + (m/64)^2) * 32 KiB).  Returns 0 or an error code.
+ */
+int ssnal_ctx_create(int device, ssnal_ctx** out);
+void ssnal_ctx_destroy(ssnal_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* ssnal_last_error(void);
+
+/*
+ * One elastic-net solve (Algorithm 1).
+ *   A, a_dtype, lda, m, n : the design (see conventions); m >= 1, n >= 1,
+ *                           m <= 4096 (the Newton system is dense m x m).
+ *   b                     : m responses.
+ *   lambda1 >= 0, lambda2 > 0: the penalty of eq. objective_function (unscaled;
+ *                           callers using a 1/m-scaled loss multiply by m).
+ *   x0                    : n starting coefficients (warm start) or NULL for 0.
+ *   tol > 0               : stop when kkt1 <= tol, kkt3 <= tol and eta <= tol.
+ *   x_out                 : n coefficients on return (may alias x0).
+ *   opts                  : NULL for defaults.   info: HOST, nullable.
+ * FP32/BF16 storage runs the A^T v passes and the Newton matrix with FP32
+ * accumulation and refreshes A^T y with FP64 accumulation before each
+ * multiplier update; the KKT residual, the objectives, the Cholesky factor and
+ * the line-search sums are FP64 in every mode.
+ */
+int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                   const double* b, int64_t m, int64_t n, double lambda1, double lambda2,
+                   const double* x0, double tol, hipStream_t stream, double* x_out,
+                   const ssnal_en_opts* opts, ssnal_en_info* info);
+
+/* ---------------------------------------------------------------------
+ * Building blocks of the solve, exported for verification and benchmarking.
+ * Each runs the same kernels the solve runs.
+ * --------------------------------------------------------------------- */
+
+/* w = A^T v over all n columns (the HBM pass of every Newton iteration).
+ * acc64 != 0: FP64 accumulation; else the storage's own (FP64 for F64,
+ * FP32 for F32/BF16).  v: m doubles, w: n doubles. */
+int ssnal_gemv_t(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,
+                 int64_t n, const double* v, double* w, int acc64, hipStream_t stream);
+
+/* Active set and prox at t = fma(-sigma, w, x) (eq. Q_def, eq. prox_elastic):
+ * J = {i : |t_i| > sigma*lambda1} ascending (int32, capacity n), uJ = prox_{sigma p}(t)_J.
+ * *r_out (HOST) receives |J|. */
+int ssnal_active_prox(ssnal_ctx* ctx, const double* x, const double* w, int64_t n, double sigma,
+                      double lambda1, double lambda2, int32_t* J, double* uJ, int64_t* r_out,
+                      hipStream_t stream);
+
+/* Newton matrix (eq. AJ_system / eq. smw_formula) for the active columns J (r entries):
+ * form 0: out = I_m + kappa A_J A_J^T (m x m); form 1: out = I_r / kappa + A_J^T A_J (r x r).
+ * out: N x N row-major FP64 (N = m or r), both triangles written. */
+int ssnal_newton_matrix(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                        int64_t m, const int32_t* J, int64_t r, double kappa, int form,
+                        double* out, hipStream_t stream);
+
+/* In-place FP64 Cholesky of an SPD N x N row-major matrix: on return the lower
+ * triangle holds L (V = L L^T) and the strict upper triangle is zero.
+ * Returns SSNAL_ENUMERIC for a non-positive pivot. */
+int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream);
+
+/* Newton direction d = -(I + kappa A_J A_J^T)^{-1} g (eq. AJ_system), by the
+ * m x m system (form 0), the r x r system of eq. smw_formula (form 1), or the
+ * solver's own choice (form -1: r x r when 0 < r < m). g, d: m doubles. */
+int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                           int64_t m, const int32_t* J, int64_t r, double kappa, const double* g,
+                           double* d, int form, hipStream_t stream);
+
+/* Line-search increments psi(y + s_k d) - psi(y) (Prop. 2 (1), eq. line_search)
+ * for K <= 32 trial steps s (HOST), from x, w = A^T y, wd = A^T d (n doubles
+ * each), gd = <grad psi(y), d>, dd = |d|^2.  delta_out: HOST, K doubles. */
+int ssnal_ls_delta(ssnal_ctx* ctx, const double* x, const double* w, const double* wd, int64_t n,
+                   double sigma, double lambda1, double lambda2, double gd, double dd, int K,
+                   const double* s, double* delta_out, hipStream_t stream);
+
+/* Certificates of a point x: out4 (HOST) = {eta, F(x), D(Ax-b), (F-D)/(1+|F|)},
+ * all FP64 accumulation over the stored A. */
+int ssnal_kkt(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+              int64_t m, int64_t n, const double* x, double lambda1, double lambda2, double* out4,
+              hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSNAL_EN_H */

@@ -77,6 +77,7 @@ def lib():
         L.orc_active_prox.restype = _i64
         L.orc_active_prox.argtypes = [_D, _D, _i64, _d, _d, _d, _I32, _D]
         L.orc_newton_matrix.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D]
+        L.orc_smw_matrix.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D]
         L.orc_cholesky.restype = C.c_int
         L.orc_cholesky.argtypes = [_D, _i64]
         L.orc_newton_direction.restype = C.c_int
@@ -183,6 +184,14 @@ def newton_matrix(AT, J, kappa):
     V = np.empty((m, m))
     lib().orc_newton_matrix(_dp(AT), m, m, J.ctypes.data_as(_I32), J.size, kappa, _dp(V))
     return V
+
+
+def smw_matrix(AT, J, kappa):
+    AT, m, n = _design(AT)
+    J = np.ascontiguousarray(J, dtype=np.int32)
+    W = np.empty((J.size, J.size))
+    lib().orc_smw_matrix(_dp(AT), m, m, J.ctypes.data_as(_I32), J.size, kappa, _dp(W))
+    return W
 
 
 def cholesky(V):

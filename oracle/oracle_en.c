@@ -233,6 +233,23 @@ void orc_newton_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J
   free(AJ);
 }
 
+/* W = I_r / kappa + A_J^T A_J (eq. smw_formula), r x r, row-major, both
+ * triangles.  The oracle's own solve never uses it (it always takes the
+ * m x m system); it is the reference for the r x r branch of the GPU path.
+ * Pinned: the Woodbury identity against the m x m matrix. */
+void orc_smw_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                    double kappa, double* W) {
+  for (int64_t p = 0; p < r; ++p) {
+    const double* ap = COL(A, lda, J[p]);
+    for (int64_t q = 0; q <= p; ++q) {
+      const double* aq = COL(A, lda, J[q]);
+      double v = dot(ap, aq, m) + (p == q ? 1.0 / kappa : 0.0);
+      W[p * r + q] = v;
+      W[q * r + p] = v;
+    }
+  }
+}
+
 /* In-place Cholesky V = L L^T (row-major, L in the lower triangle, the
  * strict upper triangle zeroed).  Textbook Cholesky-Banachiewicz.
  * Returns 0, or -(k+1) if the k-th pivot is not positive. */

@@ -64,6 +64,8 @@ int64_t orc_active_prox(const double* x, const double* w, int64_t n, double sigm
                         double l2, int32_t* J, double* uJ);
 void orc_newton_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
                        double kappa, double* V);
+void orc_smw_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                    double kappa, double* W);
 int orc_cholesky(double* V, int64_t m);
 int orc_newton_direction(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
                          double kappa, const double* g, double* d);

@@ -1,0 +1,257 @@
+"""ctypes binding of libssnal_en.so (declared in include/ssnal_en.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+Device arrays are torch tensors on a ROCm device; the design A is a tensor of
+shape (n, lda) (row j = column j of the column-major m x n design, entries
+lda > m ignored), dtype float64, float32 or bfloat16.  The library is loaded
+from this package directory and its absence is an error: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssnal_en.so")
+
+SSNAL_F64, SSNAL_F32, SSNAL_BF16 = 0, 1, 2
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "LINESEARCH_STALL", -1: "EINVAL", -2: "ENONFINITE",
+          -3: "ENOMEM", -4: "EHIP", -5: "ENUMERIC"}
+
+
+class SsnalError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("sigma_factor", C.c_double), ("sigma_max", C.c_double),
+                ("mu", C.c_double), ("delta", C.c_double), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32), ("max_backtrack", C.c_int32), ("no_refine", C.c_int32),
+                ("no_smw", C.c_int32), ("timing", C.c_int32), ("trace_cap", C.c_int32),
+                ("trace", C.POINTER(C.c_double))]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer_iters", C.c_int32), ("newton_iters", C.c_int32),
+                ("r_final", C.c_int32), ("nnz", C.c_int64), ("kkt_rel", C.c_double),
+                ("kkt1", C.c_double), ("kkt3", C.c_double), ("primal_obj", C.c_double),
+                ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double),
+                ("gemv_calls", C.c_int32), ("syncs", C.c_int32), ("gemv_ms", C.c_double),
+                ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = C.c_void_p
+_i64 = C.c_int64
+_d = C.c_double
+_i = C.c_int
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m "
+                               "paper_2006_03970_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        L.ssnal_last_error.restype = C.c_char_p
+        L.ssnal_en_opts_init.argtypes = [C.POINTER(Opts)]
+        L.ssnal_ctx_create.argtypes = [_i, C.POINTER(_vp)]
+        L.ssnal_ctx_destroy.argtypes = [_vp]
+        L.ssnal_en_solve.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, _d, _vp, _d, _vp, _vp,
+                                     C.POINTER(Opts), C.POINTER(Info)]
+        L.ssnal_gemv_t.argtypes = [_vp, _vp, _i, _i64, _i64, _i64, _vp, _vp, _i, _vp]
+        L.ssnal_active_prox.argtypes = [_vp, _vp, _vp, _i64, _d, _d, _d, _vp, _vp,
+                                        C.POINTER(_i64), _vp]
+        L.ssnal_newton_matrix.argtypes = [_vp, _vp, _i, _i64, _i64, _vp, _i64, _d, _i, _vp, _vp]
+        L.ssnal_cholesky.argtypes = [_vp, _vp, _i64, _vp]
+        L.ssnal_newton_direction.argtypes = [_vp, _vp, _i, _i64, _i64, _vp, _i64, _d, _vp, _vp, _i,
+                                             _vp]
+        L.ssnal_ls_delta.argtypes = [_vp, _vp, _vp, _vp, _i64, _d, _d, _d, _d, _d, _i,
+                                     C.POINTER(_d), C.POINTER(_d), _vp]
+        L.ssnal_kkt.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _d, _d, C.POINTER(_d), _vp]
+        for name in ("ssnal_ctx_create", "ssnal_en_solve", "ssnal_gemv_t", "ssnal_active_prox",
+                     "ssnal_newton_matrix", "ssnal_cholesky", "ssnal_newton_direction",
+                     "ssnal_ls_delta", "ssnal_kkt"):
+            getattr(L, name).restype = _i
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ssnal_last_error().decode()
+
+
+def _check(rc, allow_warn=False):
+    if rc < 0 or (rc > 0 and not allow_warn):
+        raise SsnalError(rc, last_error())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _dtype_code(A):
+    import torch
+    return {torch.float64: SSNAL_F64, torch.float32: SSNAL_F32, torch.bfloat16: SSNAL_BF16}[A.dtype]
+
+
+def _design(A, m):
+    """(pointer, dtype code, lda, m, n) of a (n, lda) design tensor."""
+    assert A.dim() == 2 and (A.stride(1) == 1 or A.shape[1] == 1), \
+        "A must be (n, lda) with unit inner stride"
+    n = A.shape[0]
+    lda = A.stride(0) if n > 1 else A.shape[1]
+    if A.shape[1] == 1:
+        lda = 1
+        assert n == 1 or A.stride(0) == 1, "A must be (n, lda) with lda = 1 here"
+    m = lda if m is None else m
+    return _ptr(A), _dtype_code(A), lda, m, n
+
+
+class Context:
+    """Owns one ssnal_ctx (device workspace) on a device."""
+
+    def __init__(self, device: int = 0):
+        p = _vp()
+        _check(lib().ssnal_ctx_create(device, C.byref(p)))
+        self.ptr = p
+        self.device = device
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().ssnal_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def make_opts(**kw) -> Opts:
+    o = Opts()
+    lib().ssnal_en_opts_init(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+# ---------------------------------------------------------------- entry points
+
+def ssnal_en_solve(ctx, A, b, lambda1, lambda2, x0=None, tol=1e-6, x_out=None, m=None, opts=None,
+                   stream=None, trace_cap=0):
+    """One solve.  Returns (x_out, info dict[, trace rows]).  Warnings
+    (NOT_CONVERGED, LINESEARCH_STALL) are reported in info['status']."""
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    if x_out is None:
+        x_out = torch.empty(n, dtype=torch.float64, device=A.device)
+    o = opts if opts is not None else make_opts()
+    trace = None
+    if trace_cap:
+        trace = (C.c_double * (6 * trace_cap))()
+        o.trace = C.cast(trace, C.POINTER(C.c_double))
+        o.trace_cap = trace_cap
+    info = Info()
+    rc = lib().ssnal_en_solve(ctx.ptr, pA, dt, lda, _ptr(b), m, n, float(lambda1), float(lambda2),
+                              _ptr(x0), float(tol), _stream(stream), _ptr(x_out), C.byref(o),
+                              C.byref(info))
+    _check(rc, allow_warn=True)
+    d = info.as_dict()
+    if trace_cap:
+        import numpy as np
+        rows = d["newton_iters"] + (0 if d["status"] == 0 else 1)
+        tr = np.ctypeslib.as_array(trace)[: 6 * trace_cap].reshape(trace_cap, 6)
+        nz = int(np.count_nonzero(tr[:, 3]))
+        return x_out, d, tr[:nz].copy()
+    return x_out, d
+
+
+def ssnal_gemv_t(ctx, A, v, w=None, acc64=False, m=None, stream=None):
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    if w is None:
+        w = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(lib().ssnal_gemv_t(ctx.ptr, pA, dt, lda, m, n, _ptr(v), _ptr(w), int(bool(acc64)),
+                              _stream(stream)))
+    return w
+
+
+def ssnal_active_prox(ctx, x, w, sigma, lambda1, lambda2, stream=None):
+    import torch
+    n = x.numel()
+    J = torch.empty(n, dtype=torch.int32, device=x.device)
+    uJ = torch.empty(n, dtype=torch.float64, device=x.device)
+    r = _i64(0)
+    _check(lib().ssnal_active_prox(ctx.ptr, _ptr(x), _ptr(w), n, float(sigma), float(lambda1),
+                                   float(lambda2), _ptr(J), _ptr(uJ), C.byref(r), _stream(stream)))
+    return J[: r.value], uJ[: r.value]
+
+
+def ssnal_newton_matrix(ctx, A, J, kappa, form, m=None, stream=None):
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    r = J.numel()
+    N = m if form == 0 else r
+    out = torch.empty((N, N), dtype=torch.float64, device=A.device)
+    _check(lib().ssnal_newton_matrix(ctx.ptr, pA, dt, lda, m, _ptr(J), r, float(kappa), int(form),
+                                     _ptr(out), _stream(stream)))
+    return out
+
+
+def ssnal_cholesky(ctx, V, stream=None):
+    """In place: V (N x N, FP64, contiguous) becomes L (lower, upper zeroed)."""
+    _check(lib().ssnal_cholesky(ctx.ptr, _ptr(V), V.shape[0], _stream(stream)))
+    return V
+
+
+def ssnal_newton_direction(ctx, A, J, kappa, g, form=-1, m=None, stream=None):
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    d = torch.empty(m, dtype=torch.float64, device=A.device)
+    _check(lib().ssnal_newton_direction(ctx.ptr, pA, dt, lda, m, _ptr(J), J.numel(), float(kappa),
+                                        _ptr(g), _ptr(d), int(form), _stream(stream)))
+    return d
+
+
+def ssnal_ls_delta(ctx, x, w, wd, sigma, lambda1, lambda2, gd, dd, steps, stream=None):
+    K = len(steps)
+    s = (C.c_double * K)(*[float(v) for v in steps])
+    out = (C.c_double * K)()
+    _check(lib().ssnal_ls_delta(ctx.ptr, _ptr(x), _ptr(w), _ptr(wd), x.numel(), float(sigma),
+                                float(lambda1), float(lambda2), float(gd), float(dd), K, s, out,
+                                _stream(stream)))
+    return [out[k] for k in range(K)]
+
+
+def ssnal_kkt(ctx, A, b, x, lambda1, lambda2, m=None, stream=None):
+    pA, dt, lda, m, n = _design(A, m)
+    out = (C.c_double * 4)()
+    _check(lib().ssnal_kkt(ctx.ptr, pA, dt, lda, _ptr(b), m, n, _ptr(x), float(lambda1),
+                           float(lambda2), out, _stream(stream)))
+    return {"eta": out[0], "primal_obj": out[1], "dual_obj": out[2], "rel_gap": out[3]}

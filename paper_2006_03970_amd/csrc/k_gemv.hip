@@ -1,0 +1,252 @@
+// A^T v over a column-major design: the HBM-bound pass of every Newton
+// iteration (w_d = A^T d), of the initial A^T y and of the KKT residual.
+//
+// Layout: each wave streams whole columns.  Lane l owns rows
+// [(it*64 + l)*VN, +VN) for it < ITERS, where VN elements make one 16-byte
+// load, so a wave reads 1 KiB per instruction and the matching slice of v
+// stays in registers for the whole kernel.  A wave keeps COLS columns in
+// flight (COLS*ITERS loads outstanding per lane), then reduces each column
+// across the wave.  A block owns a contiguous range of columns, so the four
+// waves of a block read neighbouring columns.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ssnal {
+
+template <int ITERS>
+struct ColsFor {
+  static constexpr int value = ITERS <= 1 ? 8 : (ITERS <= 2 ? 8 : (ITERS <= 4 ? 4 : (ITERS <= 8 ? 2 : 1)));
+};
+
+template <typename T, typename ACC, int ITERS, bool COLSQ>
+__global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t lda, int m,
+                                                int64_t ncols, const double* __restrict__ v,
+                                                double* __restrict__ w, int64_t cpb,
+                                                double* __restrict__ colsq_part) {
+  constexpr int VN = Vec16<T>::N;
+  constexpr int COLS = ColsFor<ITERS>::value;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+
+  ACC vr[ITERS][VN];
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int r0 = (it * kWave + lane) * VN;
+#pragma unroll
+    for (int q = 0; q < VN; ++q) vr[it][q] = (r0 + q < m) ? (ACC)v[r0 + q] : (ACC)0;
+  }
+
+  const int64_t c0 = (int64_t)blockIdx.x * cpb;
+  const int64_t c1 = c0 + cpb < ncols ? c0 + cpb : ncols;
+  double sq = 0.0;
+
+  for (int64_t cb = c0 + (int64_t)wid * COLS; cb < c1; cb += 4 * COLS) {
+    ACC e[COLS][ITERS][VN];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      const int64_t j = cb + c;
+      const bool ok = j < c1;
+      const T* a = A + (ok ? j : 0) * lda;
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int r0 = (it * kWave + lane) * VN;
+        if (ok && r0 < m) {
+          load16<ACC>(a + r0, e[c][it]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < VN; ++q) e[c][it][q] = (ACC)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      // rows past m inside the padded leading dimension may hold anything
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int r0 = (it * kWave + lane) * VN;
+        if (r0 + VN > m) {
+#pragma unroll
+          for (int q = 0; q < VN; ++q)
+            if (r0 + q >= m) e[c][it][q] = (ACC)0;
+        }
+      }
+      ACC acc = (ACC)0;
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it)
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc += e[c][it][q] * vr[it][q];
+      if (COLSQ) {
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it)
+#pragma unroll
+          for (int q = 0; q < VN; ++q) sq += (double)e[c][it][q] * (double)e[c][it][q];
+      }
+      const double s = (double)wave_sum(acc);
+      if (lane == 0 && cb + c < c1) w[cb + c] = s;
+    }
+  }
+  if (COLSQ) {
+    __shared__ double red[4];
+    const double t = block_sum<256>(sq, red);
+    if (threadIdx.x == 0) colsq_part[blockIdx.x] = t;
+  }
+}
+
+// Any alignment, any m, optional column index list: one element per lane.
+template <typename T, typename ACC, bool GATHER>
+__global__ __launch_bounds__(256) void k_gemv_t_gen(const T* __restrict__ A, int64_t lda, int m,
+                                                    int64_t ncols, const int32_t* __restrict__ J,
+                                                    const double* __restrict__ v,
+                                                    double* __restrict__ w) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t j = gw; j < ncols; j += nw) {
+    const int64_t col = GATHER ? (int64_t)J[j] : j;
+    const T* a = A + col * lda;
+    ACC acc = (ACC)0;
+    for (int i = lane; i < m; i += kWave) acc += load1<ACC>(a + i) * (ACC)v[i];
+    const double s = (double)wave_sum(acc);
+    if (lane == 0) w[j] = s;
+  }
+}
+
+// sum_j ||a_j||^2 for any alignment (one partial per block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsq_gen(const T* __restrict__ A, int64_t lda, int m,
+                                                   int64_t n, double* __restrict__ part) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  double sq = 0.0;
+  for (int64_t j = gw; j < n; j += nw) {
+    const T* a = A + j * lda;
+    for (int i = lane; i < m; i += kWave) {
+      const double e = load1<double>(a + i);
+      sq += e * e;
+    }
+  }
+  __shared__ double red[4];
+  const double t = block_sum<256>(sq, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+namespace {
+
+template <typename T, typename ACC, bool COLSQ>
+hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
+                       double* colsq_part, int* nparts, hipStream_t st) {
+  constexpr int VN = Vec16<T>::N;
+  const int need = (m + kWave * VN - 1) / (kWave * VN);
+  int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+  int cols = iters <= 2 ? 8 : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1));
+  const int64_t step = 4 * (int64_t)cols;
+  const int64_t nsteps = (n + step - 1) / step;
+  const int64_t maxb = 2048;
+  int64_t spb = (nsteps + maxb - 1) / maxb;
+  if (spb < 1) spb = 1;
+  const int64_t cpb = spb * step;
+  const int64_t nb = (n + cpb - 1) / cpb;
+  if (nparts) *nparts = (int)nb;
+  dim3 g((unsigned)nb), b(256);
+#define SSNAL_GEMV_CASE(IT)                                                                  \
+  case IT:                                                                                   \
+    hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ>), g, b, 0, st, A, lda, m, n, v, w, cpb, \
+                       colsq_part);                                                          \
+    break;
+  switch (iters) {
+    SSNAL_GEMV_CASE(1)
+    SSNAL_GEMV_CASE(2)
+    SSNAL_GEMV_CASE(4)
+    SSNAL_GEMV_CASE(8)
+    SSNAL_GEMV_CASE(16)
+  }
+#undef SSNAL_GEMV_CASE
+  return hipGetLastError();
+}
+
+template <typename T, typename ACC>
+hipError_t launch_gen(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
+                      double* w, hipStream_t st) {
+  int64_t nb = (n + 3) / 4;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  if (J)
+    hipLaunchKernelGGL((k_gemv_t_gen<T, ACC, true>), dim3((unsigned)nb), dim3(256), 0, st, A, lda, m,
+                       n, J, v, w);
+  else
+    hipLaunchKernelGGL((k_gemv_t_gen<T, ACC, false>), dim3((unsigned)nb), dim3(256), 0, st, A, lda,
+                       m, n, J, v, w);
+  return hipGetLastError();
+}
+
+bool fast_ok(const void* A, int dtype, int64_t lda, int m) {
+  const int es = dtype_size(dtype);
+  const int vn = 16 / es;
+  if (((uintptr_t)A) % 16 != 0) return false;
+  if (lda % vn != 0) return false;
+  return m <= 16 * kWave * vn;
+}
+
+template <typename T>
+hipError_t dispatch(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
+                    double* w, bool acc64, bool fast, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fast && !J) {
+    if (acc64) return launch_fast<T, double, false>(A, lda, m, n, v, w, nullptr, nullptr, st);
+    return launch_fast<T, float, false>(A, lda, m, n, v, w, nullptr, nullptr, st);
+  }
+  if (acc64) return launch_gen<T, double>(A, lda, m, n, J, v, w, st);
+  return launch_gen<T, float>(A, lda, m, n, J, v, w, st);
+}
+
+}  // namespace
+
+hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
+                  const double* v, double* w, bool acc64, hipStream_t st) {
+  const bool fast = fast_ok(A, dtype, lda, m);
+  switch (dtype) {
+    case kF64:
+      return dispatch<double>((const double*)A, lda, m, ncols, J, v, w, true, fast, st);
+    case kF32:
+      return dispatch<float>((const float*)A, lda, m, ncols, J, v, w, acc64, fast, st);
+    case kBF16:
+      return dispatch<uint16_t>((const uint16_t*)A, lda, m, ncols, J, v, w, acc64, fast, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n, const double* v,
+                        double* w, double* colsq_part, int* nparts, hipStream_t st) {
+  if (!fast_ok(A, dtype, lda, m)) {
+    hipError_t e = gemv_t(A, dtype, lda, m, n, nullptr, v, w, true, st);
+    if (e != hipSuccess) return e;
+    const int nb = 1024;
+    *nparts = nb;
+    switch (dtype) {
+      case kF64:
+        hipLaunchKernelGGL(k_colsq_gen<double>, dim3(nb), dim3(256), 0, st, (const double*)A, lda, m, n, colsq_part);
+        break;
+      case kF32:
+        hipLaunchKernelGGL(k_colsq_gen<float>, dim3(nb), dim3(256), 0, st, (const float*)A, lda, m, n, colsq_part);
+        break;
+      case kBF16:
+        hipLaunchKernelGGL(k_colsq_gen<uint16_t>, dim3(nb), dim3(256), 0, st, (const uint16_t*)A, lda, m, n,
+                           colsq_part);
+        break;
+    }
+    return hipGetLastError();
+  }
+  switch (dtype) {
+    case kF64:
+      return launch_fast<double, double, true>((const double*)A, lda, m, n, v, w, colsq_part, nparts, st);
+    case kF32:
+      return launch_fast<float, double, true>((const float*)A, lda, m, n, v, w, colsq_part, nparts, st);
+    case kBF16:
+      return launch_fast<uint16_t, double, true>((const uint16_t*)A, lda, m, n, v, w, colsq_part,
+                                                 nparts, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ssnal

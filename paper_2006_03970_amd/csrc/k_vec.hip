@@ -1,0 +1,607 @@
+// Passes over the n-vectors (x, A^T y, A^T d) and the gathers over the
+// active set J.  These read a few bytes per feature, next to the m bytes per
+// feature of the A^T v pass, so they are sized for few launches rather than
+// for bandwidth: 256 threads, 8 elements per thread, one block per 2048
+// features, and "last block finishes" reductions instead of extra launches.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "scal.hpp"
+
+namespace ssnal {
+
+constexpr int kNT = 256;
+constexpr int kEPT = 8;
+constexpr int kChunk = kNT * kEPT;
+
+int prox_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+
+__device__ __forceinline__ bool active(double t, double thr) { return t > thr || t < -thr; }
+
+// ------------------------------------------------------------------ compaction
+// Active set J = {i : |t_i| > sigma*lambda1} (eq. Q_def), t = x - sigma*w.
+template <bool UPDATE, bool SUPPORT>
+__global__ __launch_bounds__(kNT) void k_count(const double* __restrict__ x, double* __restrict__ w,
+                                                const double* __restrict__ wd,
+                                                const double* __restrict__ s_dev, int64_t n,
+                                                double sigma, double thr, int* __restrict__ counts) {
+  const double s = UPDATE ? *s_dev : 0.0;
+  int cnt = 0;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t i = base + k * kNT + threadIdx.x;
+    if (i < n) {
+      if (SUPPORT) {
+        cnt += (x[i] != 0.0);
+      } else {
+        double wi = w[i];
+        if (UPDATE) {
+          wi = fma(s, wd[i], wi);  // w_y += s * w_d
+          w[i] = wi;
+        }
+        cnt += active(fma(-sigma, wi, x[i]), thr);
+      }
+    }
+  }
+  __shared__ int red[kNT / kWave];
+  const int tot = block_sum<kNT>(cnt, red);
+  if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+template <bool SUPPORT>
+__global__ __launch_bounds__(kNT) void k_write(const double* __restrict__ x,
+                                                const double* __restrict__ w, int64_t n,
+                                                double sigma, double thr, double den,
+                                                const int* __restrict__ counts, int nblocks,
+                                                int32_t* __restrict__ J, double* __restrict__ uJ,
+                                                double* __restrict__ r_out) {
+  __shared__ int red[kNT / kWave];
+  __shared__ int wtot[kNT / kWave];
+  int part = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kNT) part += counts[b];
+  int off = block_sum<kNT>(part, red);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t i = base + k * kNT + threadIdx.x;
+    double t = 0.0;
+    bool act = false;
+    if (i < n) {
+      if (SUPPORT) {
+        t = x[i];
+        act = (t != 0.0);
+      } else {
+        t = fma(-sigma, w[i], x[i]);
+        act = active(t, thr);
+      }
+    }
+    const unsigned long long mask = __ballot(act);
+    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) wtot[wid] = __popcll(mask);
+    __syncthreads();
+    int wo = 0, bt = 0;
+#pragma unroll
+    for (int q = 0; q < kNT / kWave; ++q) {
+      if (q < wid) wo += wtot[q];
+      bt += wtot[q];
+    }
+    if (act) {
+      const int pos = off + wo + pre;
+      J[pos] = (int32_t)i;
+      uJ[pos] = SUPPORT ? t : prox_en(t, thr, den);
+    }
+    off += bt;
+  }
+  if ((int)blockIdx.x == nblocks - 1 && threadIdx.x == 0) *r_out = (double)off;
+}
+
+hipError_t prox_count(const double* x, double* w, const double* wd, const double* s_dev, int64_t n,
+                      ProxArgs pa, int* counts, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  if (s_dev)
+    hipLaunchKernelGGL((k_count<true, false>), dim3(nb), dim3(kNT), 0, st, x, w, wd, s_dev, n,
+                       pa.sigma, pa.thr, counts);
+  else
+    hipLaunchKernelGGL((k_count<false, false>), dim3(nb), dim3(kNT), 0, st, x, w, wd, s_dev, n,
+                       pa.sigma, pa.thr, counts);
+  return hipGetLastError();
+}
+
+hipError_t prox_write(const double* x, const double* w, int64_t n, ProxArgs pa, const int* counts,
+                      int32_t* J, double* uJ, double* r_out, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL((k_write<false>), dim3(nb), dim3(kNT), 0, st, x, w, n, pa.sigma, pa.thr, pa.den,
+                     counts, nb, J, uJ, r_out);
+  return hipGetLastError();
+}
+
+hipError_t support_count(const double* x, int64_t n, int* counts, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL((k_count<false, true>), dim3(nb), dim3(kNT), 0, st, x, (double*)nullptr,
+                     (const double*)nullptr, (const double*)nullptr, n, 0.0, 0.0, counts);
+  return hipGetLastError();
+}
+
+hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t* J, double* uJ,
+                         double* r_out, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL((k_write<true>), dim3(nb), dim3(kNT), 0, st, x, (const double*)nullptr, n, 0.0,
+                     0.0, 1.0, counts, nb, J, uJ, r_out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ A_J c
+// Chunk k of J is reduced by one block into a partial m-vector; the finisher
+// adds the partials in chunk order, so the sum is reproducible.  r may live
+// on the device (it comes from the compaction pass): the grid is sized for
+// the largest possible r and blocks past the last chunk return at once.
+__host__ __device__ __forceinline__ void chunk_plan(int64_t r, int& nc, int64_t& ck) {
+  if (r <= 0) {
+    nc = 0;
+    ck = 0;
+    return;
+  }
+  int64_t c = (r + 1023) / 1024;
+  if (c < 64) c = 64;
+  nc = (int)((r + c - 1) / c);
+  ck = (r + nc - 1) / nc;
+}
+
+// Upper bound of the chunk count for any r <= r_bound: nc(r) <= ceil(r/64)
+// while r <= 65536 and nc(r) <= 1024 beyond (nc itself is not monotone in r).
+int gather_chunks(int64_t r_bound) {
+  if (r_bound <= 0) return 0;
+  const int64_t c = (r_bound + 63) / 64;
+  return (int)(c < 1024 ? c : 1024);
+}
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A, int64_t lda, int m,
+                                                         const int32_t* __restrict__ J,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ r_dev,
+                                                         int64_t r_host, double* __restrict__ part) {
+  const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
+  int nc;
+  int64_t ck;
+  chunk_plan(r, nc, ck);
+  if ((int)blockIdx.x >= nc) return;
+  const int64_t k0 = (int64_t)blockIdx.x * ck;
+  const int64_t k1 = k0 + ck < r ? k0 + ck : r;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  int64_t k = k0;
+  for (; k + 1 < k1; k += 2) {
+    const T* a0 = A + (int64_t)J[k] * lda;
+    const T* a1 = A + (int64_t)J[k + 1] * lda;
+    const double c0 = c[k], c1 = c[k + 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int row = threadIdx.x + q * kNT;
+      if (row < m) {
+        acc[q] += load1<double>(a0 + row) * c0;
+        acc[q] += load1<double>(a1 + row) * c1;
+      }
+    }
+  }
+  if (k < k1) {
+    const T* a0 = A + (int64_t)J[k] * lda;
+    const double c0 = c[k];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int row = threadIdx.x + q * kNT;
+      if (row < m) acc[q] += load1<double>(a0 + row) * c0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int row = threadIdx.x + q * kNT;
+    if (row < m) part[(int64_t)blockIdx.x * m + row] = acc[q];
+  }
+}
+
+template <typename T>
+static hipError_t launch_gather(const T* A, int64_t lda, int m, const int32_t* J, const double* c,
+                                const double* r_dev, int64_t r_bound, double* part, hipStream_t st) {
+  const int nb = gather_chunks(r_bound);
+  if (nb == 0) return hipSuccess;
+  const int nq = (m + kNT - 1) / kNT;
+#define SSNAL_GATHER_CASE(Q)                                                                   \
+  if (nq <= Q) {                                                                               \
+    hipLaunchKernelGGL((k_gather_partial<T, Q>), dim3(nb), dim3(kNT), 0, st, A, lda, m, J, c,     \
+                       r_dev, r_bound, part);                                                  \
+    return hipGetLastError();                                                                  \
+  }
+  SSNAL_GATHER_CASE(1)
+  SSNAL_GATHER_CASE(2)
+  SSNAL_GATHER_CASE(4)
+  SSNAL_GATHER_CASE(8)
+  SSNAL_GATHER_CASE(16)
+#undef SSNAL_GATHER_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, const int32_t* J,
+                               const double* c, const double* r_dev, int64_t r_bound, double* part,
+                               hipStream_t st) {
+  switch (dtype) {
+    case kF64: return launch_gather<double>((const double*)A, lda, m, J, c, r_dev, r_bound, part, st);
+    case kF32: return launch_gather<float>((const float*)A, lda, m, J, c, r_dev, r_bound, part, st);
+    case kBF16:
+      return launch_gather<uint16_t>((const uint16_t*)A, lda, m, J, c, r_dev, r_bound, part, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict__ part,
+                                                        const double* __restrict__ r_dev,
+                                                        int64_t r_host, int m, int mode,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ g,
+                                                        double* __restrict__ out2,
+                                                        double* __restrict__ scal,
+                                                        unsigned int* counter) {
+  const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
+  int nchunks;
+  int64_t ck;
+  chunk_plan(r, nchunks, ck);
+  const int row = blockIdx.x * kNT + threadIdx.x;
+  double S = 0.0;
+  if (row < m)
+    for (int c = 0; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+  double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  if (row < m) {
+    if (mode == 0) {  // gradient of psi (eq. grad_phy) and the primal residual A u - b
+      const double gi = y[row] + b[row] - S;
+      const double rho = S - b[row];
+      g[row] = gi;
+      out2[row] = rho;
+      v1 = gi * gi;
+      v2 = rho * rho;
+      v3 = b[row] * rho;
+    } else if (mode == 1) {  // Woodbury direction d = -g + A_J w
+      out2[row] = -g[row] + S;
+    } else {  // y = A x - b
+      out2[row] = S - b[row];
+    }
+  }
+  if (mode != 0) return;
+  __shared__ double red[kNT / kWave];
+  const double s1 = block_sum<kNT>(v1, red);
+  const double s2 = block_sum<kNT>(v2, red);
+  const double s3 = block_sum<kNT>(v3, red);
+  if (threadIdx.x == 0) {
+    scal[SC_BLK + 3 * blockIdx.x + 0] = s1;
+    scal[SC_BLK + 3 * blockIdx.x + 1] = s2;
+    scal[SC_BLK + 3 * blockIdx.x + 2] = s3;
+  }
+  if (!arrive_last(counter, gridDim.x)) return;
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (unsigned int q = 0; q < gridDim.x; ++q) t += scal[SC_BLK + 3 * q + threadIdx.x];
+    scal[SC_GG + threadIdx.x] = t;
+  }
+}
+
+hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
+                         const double* y, const double* b, double* g, double* out2, double* scal,
+                         unsigned int* counter, hipStream_t st) {
+  const int nb = (m + kNT - 1) / kNT;
+  hipLaunchKernelGGL(k_gather_finish, dim3(nb), dim3(kNT), 0, st, part, r_dev, r_host, m, mode, y, b,
+                     g, out2, scal, counter);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ line search
+// Delta(s) = psi(y + s d) - psi(y) = s g^T d + s^2/2 |d|^2 + sum_i e_i(s), with
+// e_i(s) = den/(2 sigma) (prox(t_i - s sigma wd_i)^2 - prox(t_i)^2) + s wd_i prox(t_i),
+// which is s^2 kappa wd_i^2 / 2 while t_i stays on one active side
+// (Prop. 2 (1) expanded along the line; eq. line_search).  A feature that is
+// inactive for every trial step contributes nothing and is skipped; one that
+// stays active on its side for every step contributes s^2 times a common sum.
+constexpr int kLsSlots = kMaxTrials + 1;  // 32 trial sums + the common second-order sum
+
+__global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ wd, int64_t n,
+                                                     LsArgs la, const double* __restrict__ g,
+                                                     const double* __restrict__ d,
+                                                     double* __restrict__ y, int m,
+                                                     double* __restrict__ part,
+                                                     double* __restrict__ scal,
+                                                     unsigned int* counter, int select, double gd_in,
+                                                     double dd_in) {
+  const double sigma = la.sigma, thr = la.thr, den = la.den, kappa = la.kappa;
+  const int K = la.K;
+  double e[kMaxTrials];
+#pragma unroll
+  for (int k = 0; k < kMaxTrials; ++k) e[k] = 0.0;
+  double e2 = 0.0;
+  const double smax = la.s[0];
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  for (int q = 0; q < kEPT; ++q) {
+    const int64_t i = base + q * kNT + threadIdx.x;
+    if (i >= n) break;
+    const double t0 = fma(-sigma, w[i], x[i]);
+    const double wi = wd[i];
+    const double a0 = fabs(t0);
+    const double reach = smax * sigma * fabs(wi) * (1.0 + 1e-12);
+    if (a0 + reach < thr) continue;  // inactive for every trial step
+    if ((t0 > thr && t0 - reach > thr) || (t0 < -thr && t0 + reach < -thr)) {
+      e2 += 0.5 * kappa * wi * wi;  // same active side for every trial step
+      continue;
+    }
+    const double u0 = prox_en(t0, thr, den);
+#pragma unroll
+    for (int k = 0; k < kMaxTrials; ++k) {
+      if (k < K) {
+        const double s = la.s[k];
+        const double t1 = fma(-(s * sigma), wi, t0);
+        double ek;
+        if ((t0 > thr && t1 > thr) || (t0 < -thr && t1 < -thr)) {
+          ek = 0.5 * s * s * kappa * wi * wi;
+        } else {
+          const double u1 = prox_en(t1, thr, den);
+          ek = den / (2.0 * sigma) * (u1 * u1 - u0 * u0) + s * wi * u0;
+        }
+        e[k] += ek;
+      }
+    }
+  }
+  // block reduction of the 33 sums
+  __shared__ double wsum[kNT / kWave][kLsSlots];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kMaxTrials; ++k) {
+    const double v = wave_sum(e[k]);
+    if (lane == 0) wsum[wid][k] = v;
+  }
+  {
+    const double v = wave_sum(e2);
+    if (lane == 0) wsum[wid][kMaxTrials] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLsSlots) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNT / kWave; ++q) t += wsum[q][threadIdx.x];
+    part[(int64_t)blockIdx.x * kLsSlots + threadIdx.x] = t;
+  }
+  if (!arrive_last(counter, gridDim.x)) return;
+
+  __shared__ double tot[kLsSlots];
+  __shared__ double sh_s;
+  if (threadIdx.x < kLsSlots) {
+    double t = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[(int64_t)b * kLsSlots + threadIdx.x];
+    tot[threadIdx.x] = t;
+  }
+  // g^T d and |d|^2 (m-vectors), or the caller's values
+  double gd = gd_in, dd = dd_in;
+  if (select) {
+    __shared__ double red[kNT / kWave];
+    double pgd = 0.0, pdd = 0.0;
+    for (int i = threadIdx.x; i < m; i += kNT) {
+      pgd += g[i] * d[i];
+      pdd += d[i] * d[i];
+    }
+    gd = block_sum<kNT>(pgd, red);
+    dd = block_sum<kNT>(pdd, red);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc_s = 0.0;
+    int acc_k = -1;
+    for (int k = 0; k < K; ++k) {
+      const double s = la.s[k];
+      const double delta = s * gd + 0.5 * s * s * dd + s * s * tot[kMaxTrials] + tot[k];
+      scal[SC_DELTA + k] = delta;
+      if (acc_k < 0 && delta <= la.mu * s * gd) {
+        acc_k = k;
+        acc_s = s;
+      }
+    }
+    scal[SC_GD] = gd;
+    scal[SC_DD] = dd;
+    if (select) {
+      scal[SC_S] = acc_s;
+      scal[SC_LSK] = (double)acc_k;
+    }
+    sh_s = acc_s;
+  }
+  __syncthreads();
+  if (select) {
+    const double s = sh_s;
+    if (s > 0.0)
+      for (int i = threadIdx.x; i < m; i += kNT) y[i] = fma(s, d[i], y[i]);
+  }
+}
+
+hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
+                      const double* g, const double* d, double* y, int m, double* part,
+                      double* scal, unsigned int* counter, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, g, d, y, m, part,
+                     scal, counter, 1, 0.0, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
+                    double gd, double dd, double* part, double* scal, unsigned int* counter,
+                    hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la,
+                     (const double*)nullptr, (const double*)nullptr, (double*)nullptr, 0, part, scal,
+                     counter, 0, gd, dd);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ multiplier update
+// x <- x - sigma (A^T y + z) = prox_{sigma p}(x - sigma A^T y) by the Moreau
+// decomposition; z = prox_{p^*/sigma}(x/sigma - A^T y) (Prop. 2 (2)) only
+// enters the kkt3 denominator.
+__global__ __launch_bounds__(kNT) void k_outer(double* __restrict__ x, const double* __restrict__ w,
+                                                int64_t n, double sigma, double thr, double den,
+                                                double l1, double l2, const double* __restrict__ y,
+                                                int m, double* __restrict__ part,
+                                                double* __restrict__ scal, unsigned int* counter) {
+  double xu = 0.0, zz = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {
+    const int64_t i = base + q * kNT + threadIdx.x;
+    if (i < n) {
+      const double xi = x[i];
+      const double t = fma(-sigma, w[i], xi);
+      const double u = prox_en(t, thr, den);
+      double z;
+      if (t >= thr) z = (t * l2 + l1) / den;
+      else if (t <= -thr) z = (t * l2 - l1) / den;
+      else z = t / sigma;
+      const double e = xi - u;
+      xu += e * e;
+      zz += z * z;
+      x[i] = u;
+    }
+  }
+  __shared__ double red[kNT / kWave];
+  const double s1 = block_sum<kNT>(xu, red);
+  const double s2 = block_sum<kNT>(zz, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+  if (!arrive_last(counter, gridDim.x)) return;
+  double yy = 0.0;
+  for (int i = threadIdx.x; i < m; i += kNT) yy += y[i] * y[i];
+  yy = block_sum<kNT>(yy, red);
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[2 * b + threadIdx.x];
+    scal[SC_XU + threadIdx.x] = t;
+  }
+  if (threadIdx.x == 0) scal[SC_YY] = yy;
+}
+
+hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
+                        const double* y, int m, double* part, double* scal, unsigned int* counter,
+                        hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL(k_outer, dim3(nb), dim3(kNT), 0, st, x, w, n, pa.sigma, pa.thr, pa.den, l1, l2, y,
+                     m, part, scal, counter);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ eta pass
+// q = A^T rho with rho = A x - b.  Sums for the relative KKT residual
+// eta = |x - prox_p(x - q)| / (1 + |x| + |rho|), prox_p(v) = soft(v,l1)/(1+l2),
+// and for the objectives F(x) and D(rho) (p^* of Prop. 1 at -q).
+__global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
+                                              const double* __restrict__ q, int64_t n, double l1,
+                                              double den1, double* __restrict__ part,
+                                              double* __restrict__ scal, unsigned int* counter) {
+  double se = 0.0, sxx = 0.0, sx1 = 0.0, sps = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t i = base + k * kNT + threadIdx.x;
+    if (i < n) {
+      const double xi = x[i], qi = q[i];
+      const double p = prox_en(xi - qi, l1, den1);
+      const double e = xi - p;
+      se += e * e;
+      sxx += xi * xi;
+      sx1 += fabs(xi);
+      const double a = fabs(qi) - l1;
+      if (a > 0.0) sps += a * a;
+    }
+  }
+  __shared__ double red[kNT / kWave];
+  const double r0 = block_sum<kNT>(se, red);
+  const double r1 = block_sum<kNT>(sxx, red);
+  const double r2 = block_sum<kNT>(sx1, red);
+  const double r3 = block_sum<kNT>(sps, red);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x + 0] = r0;
+    part[4 * blockIdx.x + 1] = r1;
+    part[4 * blockIdx.x + 2] = r2;
+    part[4 * blockIdx.x + 3] = r3;
+  }
+  if (!arrive_last(counter, gridDim.x)) return;
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[4 * b + threadIdx.x];
+    scal[SC_ETA_E + threadIdx.x] = t;
+  }
+}
+
+hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2, double* part,
+                    double* scal, unsigned int* counter, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  const double den1 = 1.0 + l2;
+  hipLaunchKernelGGL(k_eta, dim3(nb), dim3(kNT), 0, st, x, q, n, l1, den1, part, scal, counter);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_scale_copy(const double* __restrict__ src, double alpha, double* __restrict__ dst,
+                             int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = alpha * src[i];
+}
+__global__ void k_fill(double* __restrict__ dst, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  return (unsigned)nb;
+}
+
+hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, st, src, alpha, dst, n);
+  return hipGetLastError();
+}
+hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, dst, v, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kNT) void k_nonfinite(const double* __restrict__ v, int64_t n,
+                                                    double* __restrict__ part,
+                                                    double* __restrict__ slot, unsigned int* counter) {
+  int c = 0;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t i = base + k * kNT + threadIdx.x;
+    if (i < n && !isfinite(v[i])) ++c;
+  }
+  __shared__ int red[kNT / kWave];
+  const int t = block_sum<kNT>(c, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = (double)t;
+  if (!arrive_last(counter, gridDim.x)) return;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b) s += part[b];
+    *slot = s;
+  }
+}
+
+hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, unsigned int* counter,
+                           double* part, hipStream_t st) {
+  const int nb = prox_blocks(n);
+  hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(kNT), 0, st, v, n, part, scal_slot, counter);
+  return hipGetLastError();
+}
+
+}  // namespace ssnal

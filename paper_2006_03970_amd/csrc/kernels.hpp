@@ -1,0 +1,114 @@
+// Host-side launchers of the SsNAL-EN kernels.  All pointers are device
+// pointers; every launcher enqueues on `st` and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssnal {
+
+enum DType : int { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+inline int dtype_size(int dt) { return dt == kF64 ? 8 : (dt == kF32 ? 4 : 2); }
+
+// ---- A^T v  (k_gemv.hip) -------------------------------------------------
+// w[k] = sum_i A[i, col(k)] v[i], col(k) = J ? J[k] : k, k < ncols.
+// acc64: accumulate in FP64 (always for F64 storage); else FP32.
+hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
+                  const double* v, double* w, bool acc64, hipStream_t st);
+// Same pass also accumulating sum_j ||a_j||^2 into colsq (FP64, one value).
+hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n,
+                        const double* v, double* w, double* colsq_part, int* nparts,
+                        hipStream_t st);
+
+// ---- vector passes over n  (k_vec.hip) -----------------------------------
+struct ProxArgs {
+  double sigma, thr, den;  // t = fma(-sigma, w, x); active iff |t| > thr; u = soft(t,thr)/den
+};
+// Number of blocks the prox passes use for n elements.
+int prox_blocks(int64_t n);
+// Pass 1: optional w += s*wd (s read from s_dev; skipped when s_dev == null),
+// then per-block active counts.
+hipError_t prox_count(const double* x, double* w, const double* wd, const double* s_dev, int64_t n,
+                      ProxArgs pa, int* counts, hipStream_t st);
+// Pass 2: order-preserving compaction J (ascending), uJ; r written to *r_out (as double).
+hipError_t prox_write(const double* x, const double* w, int64_t n, ProxArgs pa, const int* counts,
+                      int32_t* J, double* uJ, double* r_out, hipStream_t st);
+// Support of x0 (x0 != 0) compacted the same way (J, uJ = x0_J); r to *r_out.
+hipError_t support_count(const double* x, int64_t n, int* counts, hipStream_t st);
+hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t* J, double* uJ,
+                         double* r_out, hipStream_t st);
+
+// A_J c as per-chunk partial m-vectors: part[chunk*m + i].  r is read from
+// r_dev when non-null (the grid is sized for r_bound >= r), else r = r_bound.
+// gather_chunks(r_bound) bounds the chunk count of every r <= r_bound; the
+// partial buffer holds that many m-vectors.
+int gather_chunks(int64_t r_bound);
+hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, const int32_t* J,
+                               const double* c, const double* r_dev, int64_t r_bound, double* part,
+                               hipStream_t st);
+// Finishers over the partial sums S = sum_chunks part:
+//  mode 0 (gradient): g = y + b - S, out2 = rho = S - b; |g|^2, |rho|^2, b^T rho into scal
+//  mode 1 (Woodbury): out2 = d = -g + S
+//  mode 2 (residual): out2 = y = S - b
+hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
+                         const double* y, const double* b, double* g, double* out2, double* scal,
+                         unsigned int* counter, hipStream_t st);
+
+// Line search: for the K trial steps s_k, Delta_k = psi(y + s_k d) - psi(y);
+// the last block picks the first k with Delta_k <= mu s_k g^T d, updates
+// y += s d and writes s (0 if none) to scal.
+constexpr int kMaxTrials = 32;
+struct LsArgs {
+  double sigma, thr, den, kappa, mu;
+  int K;
+  double s[kMaxTrials];
+};
+hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
+                      const double* g, const double* d, double* y, int m, double* part,
+                      double* scal, unsigned int* counter, hipStream_t st);
+// Line-search increments only (no selection): scal[SC_DELTA + k] = Delta_k, k < K.
+hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
+                    double gd, double dd, double* part, double* scal, unsigned int* counter,
+                    hipStream_t st);
+
+// Multiplier update x <- prox(t), with |x - u|^2, |z|^2 (z the conjugate
+// prox of Prop. 2 (2)) and |y|^2 reduced into scal.
+hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
+                        const double* y, int m, double* part, double* scal, unsigned int* counter,
+                        hipStream_t st);
+// eta pass over q = A^T rho: sums of (x - prox_p(x - q))^2, x^2, |x|, and
+// (|q| - l1)_+^2 into scal.
+hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2,
+                    double* part, double* scal, unsigned int* counter, hipStream_t st);
+
+// Small helpers
+hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st);
+hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st);
+hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, unsigned int* counter,
+                           double* part, hipStream_t st);
+
+// ---- Newton matrix (k_syrk.hip) ------------------------------------------
+// form 0: out = shift*I_m + scale * A_J A_J^T   (m x m, K = r)
+// form 1: out = shift*I_r + scale * A_J^T A_J   (r x r, K = m)
+// out is N x N row-major, both triangles written.  Workspace: partial sums.
+size_t syrk_workspace_bytes(int form, int m, int64_t r);
+hipError_t syrk(const void* A, int dtype, int64_t lda, int m, const int32_t* J, int64_t r, int form,
+                double shift, double scale, double* out, void* work, hipStream_t st);
+
+// ---- Cholesky and triangular solves (k_chol.hip) --------------------------
+// In-place factor of an SPD N x N row-major matrix: lower triangle = L.
+// info_dev (int) receives 0 or k+1 for a non-positive pivot k.
+hipError_t cholesky(double* V, int N, int* info_dev, hipStream_t st);
+// Solve L L^T x = rhs for x (may alias rhs); alpha scales rhs first.
+hipError_t chol_solve(const double* L, int N, const double* rhs, double alpha, double* x,
+                      hipStream_t st);
+// Raise the dynamic LDS limits of the single-workgroup kernels (once per device).
+hipError_t chol_init();
+// Zero the strict upper triangle (for callers that want L alone).
+hipError_t zero_upper(double* V, int N, hipStream_t st);
+// Fused small path (N <= kSmallN): factor + solve in one workgroup.
+constexpr int kSmallN = 128;
+hipError_t chol_factor_solve_small(double* V, int N, const double* rhs, double alpha, double* x,
+                                   int* info_dev, hipStream_t st);
+
+}  // namespace ssnal

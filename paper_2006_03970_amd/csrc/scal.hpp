@@ -1,0 +1,33 @@
+// Slots of the small device scalar buffer that the kernels fill and the host
+// reads back at each synchronisation point (one copy per Newton iteration).
+#pragma once
+
+namespace ssnal {
+
+enum Scal : int {
+  SC_R = 0,      // |J|, written by the compaction pass
+  SC_S = 1,      // accepted line-search step (0 when no trial passed)
+  SC_LSK = 2,    // accepted trial index, -1 when none
+  SC_GD = 3,     // <grad psi, d>
+  SC_DD = 4,     // |d|^2
+  SC_GG = 5,     // |grad psi|^2
+  SC_RR = 6,     // |A x_new - b|^2
+  SC_BR = 7,     // b^T (A x_new - b)
+  SC_XU = 8,     // |x - u|^2 (multiplier update)
+  SC_ZZ = 9,     // |z|^2
+  SC_YY = 10,    // |y|^2
+  SC_ETA_E = 11, // |x - prox_p(x - A^T rho)|^2
+  SC_ETA_XX = 12,
+  SC_ETA_X1 = 13,
+  SC_ETA_PS = 14,  // sum (|q| - lambda1)_+^2, q = A^T rho
+  SC_NONFIN = 15,  // count of non-finite entries
+  SC_CHOL = 16,    // Cholesky status (0 or pivot+1), stored as double
+  SC_DELTA = 32,   // 33 slots: line-search increments Delta_k (+ second-order sum)
+  SC_BLK = 80,     // per-block partials of the m-vector finishers (<= 16 blocks x 3)
+  SC_SIZE = 160
+};
+
+// Counters of the "last block finishes" reductions, one per kernel kind.
+enum Ctr : int { CT_GATHER = 0, CT_LS = 1, CT_OUTER = 2, CT_ETA = 3, CT_NONFIN = 4, CT_SIZE = 8 };
+
+}  // namespace ssnal

@@ -1,0 +1,697 @@
+// Host orchestration of the SsNAL-EN solve (Algorithm 1) and the C ABI.
+//
+// Per Newton iteration the device runs: compaction of the active set (with
+// the pending w_y += s w_d folded in), the gradient A_J u_J, one read-back of
+// a few scalars (r, |grad psi|^2, the previous line-search outcome), the
+// Newton matrix and its Cholesky solve (m x m, or r x r when r < m), the
+// A^T d pass, and the line search, which also updates y on the device.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ssnal_en.h"
+#include "kernels.hpp"
+#include "scal.hpp"
+
+using namespace ssnal;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(SSNAL_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                 \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ssnal_ctx {
+  int device = 0;
+  DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal, ctr;
+  double* h_scal = nullptr;  // pinned, SC_SIZE doubles
+  std::vector<hipEvent_t> ev;
+  bool chol_ready = false;
+};
+
+namespace {
+
+// Grow-only allocation; contents are not preserved.
+int ensure(DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes) return 0;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return fail(SSNAL_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  size_t want = bytes < 256 ? 256 : bytes;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(SSNAL_ENOMEM, "device allocation of %zu bytes failed", want);
+  }
+  b.bytes = want;
+  return 0;
+}
+
+// m-vector slots inside ctx->mvec
+enum MV : int { MV_Y = 0, MV_G, MV_D, MV_RHO, MV_T1, MV_T2, MV_COUNT };
+
+struct Workspace {
+  double *wy, *wd, *uJ, *part, *gpart, *V, *scal;
+  double *y, *g, *d, *rho, *t1, *t2;
+  int32_t* J;
+  int* counts;
+  void* syrk;
+  unsigned int* ctr;
+  int* info;
+};
+
+int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
+  int rc;
+  const int nb = prox_blocks(n);
+  const int64_t T = (m + 63) / 64;
+  const size_t syrk_bytes = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);
+  if ((rc = ensure(c->wy, n * 8)) || (rc = ensure(c->wd, n * 8)) || (rc = ensure(c->uJ, n * 8)) ||
+      (rc = ensure(c->J, n * 4)) || (rc = ensure(c->counts, (size_t)nb * 4)) ||
+      (rc = ensure(c->part, (size_t)((nb * 33 > 2048 + nb ? nb * 33 : 2048 + nb) + 64) * 8)) ||
+      (rc = ensure(c->gpart, (size_t)(gather_chunks(n) + 1) * m * 8)) ||
+      (rc = ensure(c->V, (size_t)m * m * 8)) || (rc = ensure(c->syrk, syrk_bytes)) ||
+      (rc = ensure(c->mvec, (size_t)MV_COUNT * m * 8)))
+    return rc;
+  w.wy = (double*)c->wy.p;
+  w.wd = (double*)c->wd.p;
+  w.uJ = (double*)c->uJ.p;
+  w.J = (int32_t*)c->J.p;
+  w.counts = (int*)c->counts.p;
+  w.part = (double*)c->part.p;
+  w.gpart = (double*)c->gpart.p;
+  w.V = (double*)c->V.p;
+  w.syrk = c->syrk.p;
+  double* mv = (double*)c->mvec.p;
+  w.y = mv + MV_Y * m;
+  w.g = mv + MV_G * m;
+  w.d = mv + MV_D * m;
+  w.rho = mv + MV_RHO * m;
+  w.t1 = mv + MV_T1 * m;
+  w.t2 = mv + MV_T2 * m;
+  w.scal = (double*)c->scal.p;
+  w.ctr = (unsigned int*)c->ctr.p;
+  w.info = (int*)(w.scal + SC_CHOL);  // Cholesky status, read back with the scalars
+  return 0;
+}
+
+// Copy the scalar slots back and wait for the stream.
+int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
+  HIPCHK(hipMemcpyAsync(c->h_scal, w.scal, SC_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (syncs) ++*syncs;
+  return 0;
+}
+
+int check_args(const void* A, int dt, int64_t lda, const double* b, int64_t m, int64_t n) {
+  if (!A || !b) return fail(SSNAL_EINVAL, "A and b must be non-null device pointers");
+  if (dt < 0 || dt > 2) return fail(SSNAL_EINVAL, "a_dtype %d is not SSNAL_F64/F32/BF16", dt);
+  if (m < 1 || n < 1) return fail(SSNAL_EINVAL, "m=%lld and n=%lld must be >= 1", (long long)m, (long long)n);
+  if (m > 4096) return fail(SSNAL_EINVAL, "m=%lld exceeds 4096 (dense m x m Newton system)", (long long)m);
+  if (n > 2147483647LL) return fail(SSNAL_EINVAL, "n=%lld exceeds 2^31-1", (long long)n);
+  if (lda < m) return fail(SSNAL_EINVAL, "lda=%lld < m=%lld", (long long)lda, (long long)m);
+  return 0;
+}
+
+struct Timer {
+  ssnal_ctx* c;
+  hipStream_t st;
+  bool on;
+  int used = 0;
+  int rec_start() {
+    if (!on) return 0;
+    if ((size_t)(2 * used + 2) > c->ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev.push_back(e);
+      }
+    }
+    HIPCHK(hipEventRecord(c->ev[2 * used], st));
+    return 0;
+  }
+  int rec_stop() {
+    if (!on) return 0;
+    HIPCHK(hipEventRecord(c->ev[2 * used + 1], st));
+    ++used;
+    return 0;
+  }
+  int total_ms(double* out) {
+    double t = 0.0;
+    for (int k = 0; k < used; ++k) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+      t += ms;
+    }
+    *out = t;
+    return 0;
+  }
+};
+
+// ---------------------------------------------------------------- direction
+// d = -(I + kappa A_J A_J^T)^{-1} g  (eq. AJ_system), with the r x r form of
+// eq. smw_formula when 0 < r < m and smw is allowed.
+int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J, int64_t r,
+                     double kappa, const double* g, double* d, int form, const Workspace& w,
+                     hipStream_t st) {
+  if (r == 0) {
+    HIPCHK(vec_scale_copy(g, -1.0, d, m, st));
+    return 0;
+  }
+  if (form < 0) form = (r < m) ? 1 : 0;
+  if (form == 0) {
+    HIPCHK(syrk(A, dt, lda, m, J, r, 0, 1.0, kappa, w.V, w.syrk, st));
+    if (m <= kSmallN) {
+      HIPCHK(chol_factor_solve_small(w.V, m, g, -1.0, d, w.info, st));
+    } else {
+      HIPCHK(cholesky(w.V, m, w.info, st));
+      HIPCHK(chol_solve(w.V, m, g, -1.0, d, st));
+    }
+    return 0;
+  }
+  // (I + kappa A_J A_J^T)^{-1} = I - A_J (I/kappa + A_J^T A_J)^{-1} A_J^T
+  // d = -g + A_J q,  (I/kappa + A_J^T A_J) q = A_J^T g
+  const int N = (int)r;
+  double* v = w.t1;  // r <= m entries
+  double* q = w.t2;
+  HIPCHK(gemv_t(A, dt, lda, m, r, J, g, v, true, st));
+  HIPCHK(syrk(A, dt, lda, m, J, r, 1, 1.0 / kappa, 1.0, w.V, w.syrk, st));
+  if (N <= kSmallN) {
+    HIPCHK(chol_factor_solve_small(w.V, N, v, 1.0, q, w.info, st));
+  } else {
+    HIPCHK(cholesky(w.V, N, w.info, st));
+    HIPCHK(chol_solve(w.V, N, v, 1.0, q, st));
+  }
+  HIPCHK(gather_gemv_partial(A, dt, lda, m, J, q, nullptr, r, w.gpart, st));
+  HIPCHK(gather_finish(w.gpart, nullptr, r, m, 1, nullptr, nullptr, const_cast<double*>(g), d, w.scal, w.ctr + CT_GATHER,
+                       st));
+  return 0;
+}
+
+#pragma clang fp contract(off)
+ProxArgs prox_args(double sigma, double l1, double l2) {
+  ProxArgs pa;
+  pa.sigma = sigma;
+  const double p1 = sigma * l1;
+  const double p2 = sigma * l2;
+  pa.thr = p1;
+  pa.den = 1.0 + p2;
+  return pa;
+}
+#pragma clang fp contract(on)
+
+// Prox + gradient: J, uJ, r (device), g, rho, |g|^2 ...  (pending step folded in)
+int prox_grad(const void* A, int dt, int64_t lda, const double* b, int m, int64_t n, const double* x,
+              const ProxArgs& pa, bool pending, const Workspace& w, hipStream_t st) {
+  HIPCHK(prox_count(x, w.wy, w.wd, pending ? w.scal + SC_S : nullptr, n, pa, w.counts, st));
+  HIPCHK(prox_write(x, w.wy, n, pa, w.counts, w.J, w.uJ, w.scal + SC_R, st));
+  HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal,
+                       w.ctr + CT_GATHER, st));
+  return 0;
+}
+
+// eta, F, D from rho = A x - b (already in w.rho); q = A^T rho into w.wd.
+int certify(const void* A, int dt, int64_t lda, int m, int64_t n, const double* x, double l1,
+            double l2, const Workspace& w, hipStream_t st, Timer& tm, int* gemv_calls) {
+  if (int rc = tm.rec_start()) return rc;
+  HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.rho, w.wd, true, st));
+  if (int rc = tm.rec_stop()) return rc;
+  ++*gemv_calls;
+  HIPCHK(eta_pass(x, w.wd, n, l1, l2, w.part, w.scal, w.ctr + CT_ETA, st));
+  return 0;
+}
+
+void certificate_values(const double* hs, double l1, double l2, double* eta, double* F, double* D) {
+  const double RR = hs[SC_RR], BR = hs[SC_BR];
+  *eta = std::sqrt(hs[SC_ETA_E]) / (1.0 + std::sqrt(hs[SC_ETA_XX]) + std::sqrt(RR));
+  *F = 0.5 * RR + l1 * hs[SC_ETA_X1] + 0.5 * l2 * hs[SC_ETA_XX];
+  *D = -0.5 * RR - BR - hs[SC_ETA_PS] / (2.0 * l2);
+}
+
+int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int64_t m64,
+               int64_t n, double l1, double l2, const double* x0, double tol, hipStream_t st,
+               double* x, const ssnal_en_opts* user_opts, ssnal_en_info* info) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (int rc = check_args(A, dt, lda, b, m64, n)) return rc;
+  if (!x) return fail(SSNAL_EINVAL, "x_out must be a non-null device pointer");
+  if (!(l1 >= 0.0) || !std::isfinite(l1)) return fail(SSNAL_EINVAL, "lambda1 must be finite and >= 0");
+  if (!(l2 > 0.0) || !std::isfinite(l2)) return fail(SSNAL_EINVAL, "lambda2 must be finite and > 0");
+  if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
+  const int m = (int)m64;
+  ssnal_en_opts o;
+  ssnal_en_opts_init(&o);
+  if (user_opts) {
+    if (user_opts->sigma0 > 0) o.sigma0 = user_opts->sigma0;
+    if (user_opts->sigma_factor > 0) o.sigma_factor = user_opts->sigma_factor;
+    if (user_opts->sigma_max > 0) o.sigma_max = user_opts->sigma_max;
+    if (user_opts->mu > 0) o.mu = user_opts->mu;
+    if (user_opts->delta > 0) o.delta = user_opts->delta;
+    if (user_opts->max_outer > 0) o.max_outer = user_opts->max_outer;
+    if (user_opts->max_inner > 0) o.max_inner = user_opts->max_inner;
+    if (user_opts->max_backtrack > 0) o.max_backtrack = user_opts->max_backtrack;
+    o.no_refine = user_opts->no_refine;
+    o.no_smw = user_opts->no_smw;
+    o.timing = user_opts->timing;
+    o.trace = user_opts->trace;
+    o.trace_cap = user_opts->trace_cap;
+  }
+  if (o.max_backtrack > kMaxTrials - 1) o.max_backtrack = kMaxTrials - 1;
+  if (!(o.mu < 0.5)) return fail(SSNAL_EINVAL, "mu must lie in (0, 1/2)");
+  if (!(o.delta < 1.0)) return fail(SSNAL_EINVAL, "delta must lie in (0, 1)");
+  HIPCHK(hipSetDevice(c->device));
+  Workspace w;
+  if (int rc = prepare(c, m, n, w)) return rc;
+  const bool mixed = dt != kF64;
+  Timer tm{c, st, o.timing != 0};
+  int gemv_calls = 0, syncs = 0;
+  double* hs = c->h_scal;
+  HIPCHK(hipMemsetAsync(w.info, 0, sizeof(double), st));
+
+  // ---- start: x = x0 (or 0), y = A x0 - b, w_y = A^T y
+  if (x0) {
+    if (x0 != x) HIPCHK(hipMemcpyAsync(x, x0, n * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(nonfinite_count(x, n, w.scal + SC_NONFIN, w.ctr + CT_NONFIN, w.part, st));
+    if (int rc = readback(c, w, st, &syncs)) return rc;
+    if (hs[SC_NONFIN] != 0.0) return fail(SSNAL_ENONFINITE, "x0 holds %g non-finite entries", hs[SC_NONFIN]);
+    HIPCHK(support_count(x, n, w.counts, st));
+    HIPCHK(support_write(x, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
+    HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
+    HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 2, nullptr, b, nullptr, w.y, w.scal,
+                         w.ctr + CT_GATHER, st));
+  } else {
+    HIPCHK(hipMemsetAsync(x, 0, n * 8, st));
+    HIPCHK(vec_scale_copy(b, -1.0, w.y, m, st));
+  }
+  int nparts = 0;
+  if (int rc = tm.rec_start()) return rc;
+  HIPCHK(gemv_t_colsq(A, dt, lda, m, n, w.y, w.wy, w.part, &nparts, st));
+  if (int rc = tm.rec_stop()) return rc;
+  ++gemv_calls;
+  HIPCHK(nonfinite_count(w.wy, n, w.scal + SC_NONFIN, w.ctr + CT_NONFIN, w.part + 2048, st));
+  std::vector<double> hb(m), hpart(nparts);
+  HIPCHK(hipMemcpyAsync(hb.data(), b, m * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hpart.data(), w.part, nparts * 8, hipMemcpyDeviceToHost, st));
+  if (int rc = readback(c, w, st, &syncs)) return rc;
+  double normb2 = 0.0, colsq = 0.0;
+  for (int i = 0; i < m; ++i) normb2 += hb[i] * hb[i];
+  for (int k = 0; k < nparts; ++k) colsq += hpart[k];
+  if (!std::isfinite(normb2)) return fail(SSNAL_ENONFINITE, "b holds non-finite entries");
+  if (hs[SC_NONFIN] != 0.0)
+    return fail(SSNAL_ENONFINITE, "A^T (A x0 - b) holds %g non-finite entries (non-finite A?)",
+                hs[SC_NONFIN]);
+  const double normb = std::sqrt(normb2);
+  double sigma = o.sigma0;
+  if (!(user_opts && user_opts->sigma0 > 0)) {
+    const double mean = colsq / (double)n;
+    sigma = 2.5 / (mean > 0.0 ? mean : 1.0);
+  }
+
+  double kkt1 = INFINITY, kkt3 = INFINITY, eta = INFINITY, F = NAN, D = NAN;
+  int status = SSNAL_NOT_CONVERGED, newton = 0, outer_done = 0, rows = 0;
+  int64_t r = 0;
+  bool stalled = false, pending = false, converged = false;
+  int pending_row = -1;
+
+  for (int outer = 0; outer < o.max_outer; ++outer) {
+    const ProxArgs pa = prox_args(sigma, l1, l2);
+    const double kappa = sigma / pa.den;
+    LsArgs la;
+    la.sigma = sigma;
+    la.thr = pa.thr;
+    la.den = pa.den;
+    la.kappa = kappa;
+    la.mu = o.mu;
+    la.K = o.max_backtrack + 1;
+    {
+      double s = 1.0;
+      for (int k = 0; k < la.K; ++k) {
+        la.s[k] = s;
+        s *= o.delta;
+      }
+    }
+    bool refreshed = false;
+    int inner = 0;
+    for (;;) {
+      if (int rc = prox_grad(A, dt, lda, b, m, n, x, pa, pending, w, st)) return rc;
+      pending = false;
+      if (int rc = readback(c, w, st, &syncs)) return rc;
+      {
+        int cinfo = 0;
+        std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
+        if (cinfo != 0) return fail(SSNAL_ENUMERIC, "Cholesky: non-positive pivot at row %d", cinfo - 1);
+      }
+      if (pending_row >= 0) {
+        if (o.trace && pending_row < o.trace_cap) o.trace[pending_row * 6 + 4] = hs[SC_S];
+        pending_row = -1;
+        if (hs[SC_LSK] < 0.0) {
+          stalled = true;
+        } else {
+          ++newton;
+        }
+      }
+      r = (int64_t)hs[SC_R];
+      kkt1 = std::sqrt(hs[SC_GG]) / (1.0 + normb);
+      if (!std::isfinite(kkt1)) return fail(SSNAL_ENONFINITE, "non-finite gradient");
+      if (stalled) break;
+      if (kkt1 <= tol) {
+        if (mixed && !o.no_refine && !refreshed) {
+          // refresh A^T y with FP64 accumulation over the stored A, then re-test
+          if (int rc = tm.rec_start()) return rc;
+          HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.y, w.wy, true, st));
+          if (int rc = tm.rec_stop()) return rc;
+          ++gemv_calls;
+          refreshed = true;
+          continue;
+        }
+        break;
+      }
+      if (inner >= o.max_inner) break;
+      refreshed = false;
+      // Newton direction
+      int rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, o.no_smw ? 0 : -1, w, st);
+      if (rc) return rc;
+      // w_d = A^T d, the HBM pass
+      if ((rc = tm.rec_start())) return rc;
+      HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.d, w.wd, !mixed, st));
+      if ((rc = tm.rec_stop())) return rc;
+      ++gemv_calls;
+      HIPCHK(linesearch(x, w.wy, w.wd, n, la, w.g, w.d, w.y, m, w.part, w.scal, w.ctr + CT_LS, st));
+      pending = true;
+      if (o.trace && rows < o.trace_cap) {
+        double* row = o.trace + rows * 6;
+        row[0] = outer;
+        row[1] = inner;
+        row[2] = (double)r;
+        row[3] = sigma;
+        row[4] = 0.0;
+        row[5] = kkt1;
+      }
+      pending_row = rows;
+      ++rows;
+      ++inner;
+    }
+    // multiplier update x <- prox(x - sigma A^T y)
+    HIPCHK(outer_update(x, w.wy, n, pa, l1, l2, w.y, m, w.part, w.scal, w.ctr + CT_OUTER, st));
+    ++outer_done;
+    bool need_eta = false;
+    if (int rc = readback(c, w, st, &syncs)) return rc;
+    kkt3 = std::sqrt(hs[SC_XU]) / sigma / (1.0 + std::sqrt(hs[SC_YY]) + std::sqrt(hs[SC_ZZ]));
+    need_eta = (kkt1 <= tol && kkt3 <= tol);
+    if (need_eta) {
+      if (int rc = certify(A, dt, lda, m, n, x, l1, l2, w, st, tm, &gemv_calls)) return rc;
+      if (int rc = readback(c, w, st, &syncs)) return rc;
+      certificate_values(hs, l1, l2, &eta, &F, &D);
+      if (eta <= tol) {
+        converged = true;
+        status = SSNAL_OK;
+        break;
+      }
+    }
+    if (stalled) break;
+    sigma *= o.sigma_factor;
+    if (sigma > o.sigma_max) sigma = o.sigma_max;
+  }
+  if (!converged) {
+    // certificates of the returned point; rho = A x - b from the last gradient
+    if (int rc = certify(A, dt, lda, m, n, x, l1, l2, w, st, tm, &gemv_calls)) return rc;
+    if (int rc = readback(c, w, st, &syncs)) return rc;
+    certificate_values(hs, l1, l2, &eta, &F, &D);
+    status = stalled ? SSNAL_LINESEARCH_STALL : SSNAL_NOT_CONVERGED;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->outer_iters = outer_done;
+    info->newton_iters = newton;
+    info->r_final = (int32_t)r;
+    info->nnz = r;
+    info->kkt_rel = eta;
+    info->kkt1 = kkt1;
+    info->kkt3 = kkt3;
+    info->primal_obj = F;
+    info->dual_obj = D;
+    info->rel_gap = (F - D) / (1.0 + std::fabs(F));
+    info->sigma_final = sigma;
+    info->gemv_calls = gemv_calls;
+    info->syncs = syncs;
+    double gms = 0.0;
+    if (int rc = tm.total_ms(&gms)) return rc;
+    info->gemv_ms = gms;
+    info->solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (status != SSNAL_OK) {
+    snprintf(g_err, sizeof(g_err), "%s after %d outer iterations (eta=%.3e, tol=%.3e)",
+             status == SSNAL_NOT_CONVERGED ? "not converged" : "line search stalled", outer_done,
+             eta, tol);
+  }
+  return status;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void ssnal_en_opts_init(ssnal_en_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sigma0 = 0.0;
+  o->sigma_factor = 5.0;
+  o->sigma_max = 1e8;
+  o->mu = 0.2;
+  o->delta = 0.5;
+  o->max_outer = 100;
+  o->max_inner = 50;
+  o->max_backtrack = 30;
+}
+
+const char* ssnal_last_error(void) { return g_err; }
+
+int ssnal_ctx_create(int device, ssnal_ctx** out) {
+  g_err[0] = 0;
+  if (!out) return fail(SSNAL_EINVAL, "out must be non-null");
+  *out = nullptr;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(SSNAL_EINVAL, "device %d not in [0, %d)", device, count);
+  HIPCHK(hipSetDevice(device));
+  ssnal_ctx* c = new (std::nothrow) ssnal_ctx();
+  if (!c) return fail(SSNAL_ENOMEM, "host allocation failed");
+  c->device = device;
+  int rc;
+  if ((rc = ensure(c->scal, SC_SIZE * sizeof(double))) || (rc = ensure(c->ctr, CT_SIZE * 4))) {
+    ssnal_ctx_destroy(c);
+    return rc;
+  }
+  if (hipMemset(c->scal.p, 0, c->scal.bytes) != hipSuccess || hipMemset(c->ctr.p, 0, c->ctr.bytes) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_scal, SC_SIZE * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      chol_init() != hipSuccess) {
+    ssnal_ctx_destroy(c);
+    return fail(SSNAL_EHIP, "context initialisation failed");
+  }
+  *out = c;
+  return 0;
+}
+
+void ssnal_ctx_destroy(ssnal_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart,
+                    &c->V, &c->syrk, &c->mvec, &c->scal, &c->ctr};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                   int64_t m, int64_t n, double lambda1, double lambda2, const double* x0,
+                   double tol, hipStream_t stream, double* x_out, const ssnal_en_opts* opts,
+                   ssnal_en_info* info) {
+  g_err[0] = 0;
+  if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
+  return solve_impl(ctx, A, (int)a_dtype, lda, b, m, n, lambda1, lambda2, x0, tol, stream, x_out,
+                    opts, info);
+}
+
+int ssnal_gemv_t(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,
+                 int64_t n, const double* v, double* w, int acc64, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
+  if (int rc = check_args(A, (int)a_dtype, lda, v, m, n)) return rc;
+  if (!w) return fail(SSNAL_EINVAL, "w is null");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(gemv_t(A, (int)a_dtype, lda, (int)m, n, nullptr, v, w, acc64 != 0 || a_dtype == SSNAL_F64,
+                stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+int ssnal_active_prox(ssnal_ctx* ctx, const double* x, const double* w, int64_t n, double sigma,
+                      double lambda1, double lambda2, int32_t* J, double* uJ, int64_t* r_out,
+                      hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !x || !w || !J || !uJ || !r_out) return fail(SSNAL_EINVAL, "null argument");
+  if (n < 1) return fail(SSNAL_EINVAL, "n must be >= 1");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, 1, n, ws)) return rc;
+  const ProxArgs pa = prox_args(sigma, lambda1, lambda2);
+  HIPCHK(prox_count(x, const_cast<double*>(w), nullptr, nullptr, n, pa, ws.counts, stream));
+  HIPCHK(prox_write(x, w, n, pa, ws.counts, J, uJ, ws.scal + SC_R, stream));
+  if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
+  *r_out = (int64_t)ctx->h_scal[SC_R];
+  return 0;
+}
+
+int ssnal_newton_matrix(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,
+                        const int32_t* J, int64_t r, double kappa, int form, double* out,
+                        hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !out || (r > 0 && !J)) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, out, m, 1)) return rc;
+  if (form != 0 && form != 1) return fail(SSNAL_EINVAL, "form must be 0 or 1");
+  if (form == 1 && (r < 1 || r > 4096)) return fail(SSNAL_EINVAL, "form 1 needs 1 <= r <= 4096");
+  if (!(kappa > 0)) return fail(SSNAL_EINVAL, "kappa must be > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  const int64_t Nmax = form == 0 ? m : (r > m ? r : m);
+  if (int rc = prepare(ctx, Nmax, 1, ws)) return rc;
+  if (form == 0)
+    HIPCHK(syrk(A, (int)a_dtype, lda, (int)m, J, r, 0, 1.0, kappa, out, ws.syrk, stream));
+  else
+    HIPCHK(syrk(A, (int)a_dtype, lda, (int)m, J, r, 1, 1.0 / kappa, 1.0, out, ws.syrk, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !V) return fail(SSNAL_EINVAL, "null argument");
+  if (N < 1 || N > 4096) return fail(SSNAL_EINVAL, "N must lie in [1, 4096]");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, N, 1, ws)) return rc;
+  HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int), stream));
+  HIPCHK(cholesky(V, (int)N, ws.info, stream));
+  if (N > kSmallN) HIPCHK(zero_upper(V, (int)N, stream));
+  int hinfo = 0;
+  HIPCHK(hipMemcpyAsync(&hinfo, ws.info, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
+  return 0;
+}
+
+int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                           int64_t m, const int32_t* J, int64_t r, double kappa, const double* g,
+                           double* d, int form, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !g || !d || (r > 0 && !J)) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, g, m, 1)) return rc;
+  if (!(kappa > 0)) return fail(SSNAL_EINVAL, "kappa must be > 0");
+  if (form == 1 && r >= m) return fail(SSNAL_EINVAL, "form 1 needs r < m");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, m, r > 0 ? r : 1, ws)) return rc;
+  HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int), stream));
+  if (int rc = newton_direction(A, (int)a_dtype, lda, (int)m, J, r, kappa, g, d, form, ws, stream))
+    return rc;
+  int hinfo = 0;
+  HIPCHK(hipMemcpyAsync(&hinfo, ws.info, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
+  return 0;
+}
+
+int ssnal_ls_delta(ssnal_ctx* ctx, const double* x, const double* w, const double* wd, int64_t n,
+                   double sigma, double lambda1, double lambda2, double gd, double dd, int K,
+                   const double* s, double* delta_out, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !x || !w || !wd || !s || !delta_out) return fail(SSNAL_EINVAL, "null argument");
+  if (n < 1 || K < 1 || K > kMaxTrials) return fail(SSNAL_EINVAL, "need n >= 1 and 1 <= K <= 32");
+  for (int k = 1; k < K; ++k)
+    if (!(s[k] <= s[k - 1])) return fail(SSNAL_EINVAL, "trial steps must be non-increasing");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, 1, n, ws)) return rc;
+  const ProxArgs pa = prox_args(sigma, lambda1, lambda2);
+  LsArgs la;
+  la.sigma = sigma;
+  la.thr = pa.thr;
+  la.den = pa.den;
+  la.kappa = sigma / pa.den;
+  la.mu = 0.2;
+  la.K = K;
+  for (int k = 0; k < kMaxTrials; ++k) la.s[k] = k < K ? s[k] : 0.0;
+  HIPCHK(ls_delta(x, w, wd, n, la, gd, dd, ws.part, ws.scal, ws.ctr + CT_LS, stream));
+  if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
+  for (int k = 0; k < K; ++k) delta_out[k] = ctx->h_scal[SC_DELTA + k];
+  return 0;
+}
+
+int ssnal_kkt(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+              int64_t m, int64_t n, const double* x, double lambda1, double lambda2, double* out4,
+              hipStream_t stream) {
+  g_err[0] = 0;
+  if (!ctx || !x || !out4) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
+  if (!(lambda2 > 0)) return fail(SSNAL_EINVAL, "lambda2 must be > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, m, n, ws)) return rc;
+  const int dt = (int)a_dtype;
+  HIPCHK(support_count(x, n, ws.counts, stream));
+  HIPCHK(support_write(x, n, ws.counts, ws.J, ws.uJ, ws.scal + SC_R, stream));
+  HIPCHK(gather_gemv_partial(A, dt, lda, (int)m, ws.J, ws.uJ, ws.scal + SC_R, n, ws.gpart, stream));
+  // mode 0 with y = 0 gives rho = A x - b and its norms
+  HIPCHK(vec_fill(ws.y, 0.0, m, stream));
+  HIPCHK(gather_finish(ws.gpart, ws.scal + SC_R, 0, (int)m, 0, ws.y, b, ws.g, ws.rho, ws.scal,
+                       ws.ctr + CT_GATHER, stream));
+  Timer tm{ctx, stream, false};
+  int calls = 0;
+  if (int rc = certify(A, dt, lda, (int)m, n, x, lambda1, lambda2, ws, stream, tm, &calls)) return rc;
+  if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
+  double eta, F, D;
+  certificate_values(ctx->h_scal, lambda1, lambda2, &eta, &F, &D);
+  out4[0] = eta;
+  out4[1] = F;
+  out4[2] = D;
+  out4[3] = (F - D) / (1.0 + std::fabs(F));
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+"""The C-ABI library loads on the CPU and exports every symbol the header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssnal_en.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(ssnal_[a-z0-9_]+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("ssnal_ctx_create", "ssnal_ctx_destroy", "ssnal_en_solve", "ssnal_last_error",
+                 "ssnal_gemv_t", "ssnal_cholesky"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2006_03970_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libssnal_en.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_structs_match_header():
+    """ctypes mirrors of ssnal_en_opts / ssnal_en_info have the header's field order."""
+    from paper_2006_03970_amd import binding
+    src = open(HEADER).read()
+    for struct, cls in (("ssnal_en_opts", binding.Opts), ("ssnal_en_info", binding.Info)):
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + ";", src).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = decl.replace("*", " ").split()
+            names = " ".join(parts[1:]).split(",")
+            fields += [n.strip() for n in names]
+        assert fields == [f for f, _ in cls._fields_], (struct, fields)
+
+
+def test_error_message_without_gpu():
+    """Entry points fail cleanly (no abort) when no device is usable."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2006_03970_amd import binding
+    with pytest.raises(binding.SsnalError):
+        binding.Context(0)

@@ -1,0 +1,181 @@
+"""Whole-solve parity of the HIP path against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+from tests import pinlib
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    return gpu.Context(0)
+
+
+def _upload(p, lda=None):
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    return design_to_device(p.AT, p.store, lda=lda), vec_to_device(p.b)
+
+
+def _support_ok(x, xr, thr=1e-8):
+    """supp(x) and supp(xr) agree apart from coefficients within thr of zero."""
+    diff = (x != 0) ^ (xr != 0)
+    return np.all(np.abs(x[diff]) <= thr) and np.all(np.abs(xr[diff]) <= thr)
+
+
+def _rel_obj(F, Fr):
+    return abs(F - Fr) / abs(Fr)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_small_workload_fp64_vs_oracle(gpu, ctx, orc, seed):
+    """m=100, n=2000 Gaussian design, tol 1e-10: rel. objective 1e-10, same support."""
+    import datagen
+    p = datagen.make_problem("c1", seed=seed)
+    _say("c1 fp64 seed", seed)
+    A, b = _upload(p)
+    x, info, trace = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, trace_cap=512)
+    x = x.cpu().numpy()
+    xr, ir, tr = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=p.tol)
+    assert info["status"] == 0, info
+    assert info["kkt_rel"] <= p.tol
+    assert orc.eta(p.AT, p.b, x, p.lam1, p.lam2) <= p.tol
+    F = orc.primal_obj(p.AT, p.b, x, p.lam1, p.lam2)
+    assert _rel_obj(F, ir["primal_obj"]) <= 1e-10
+    assert _support_ok(x, xr)
+    # r trajectory of the first Newton steps follows the oracle's
+    assert trace[0, 2] == tr[0, 2]
+
+
+def test_block_toeplitz_fp64_vs_oracle(gpu, ctx, orc):
+    """m=500, n=100000 block-Toeplitz design (rho=0.6), FP64, tol 1e-6 (full size)."""
+    import datagen
+    p = datagen.make_problem("c2", seed=1)
+    _say("c2 fp64 full size")
+    A, b = _upload(p)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x = x.cpu().numpy()
+    xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-10)
+    assert info["status"] == 0, info
+    assert orc.eta(p.AT, p.b, x, p.lam1, p.lam2) <= p.tol
+    F = orc.primal_obj(p.AT, p.b, x, p.lam1, p.lam2)
+    # tol 1e-6 bounds eta; the objective gap to the tight oracle point is far smaller
+    assert _rel_obj(F, ir["primal_obj"]) <= 1e-9
+    assert _support_ok(x, xr, thr=1e-5)
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_block_toeplitz_mixed(gpu, ctx, orc, store):
+    """Reduced-precision storage: KKT residual <= 1e-6 on the stored design
+    (FP64 oracle on the dequantised design) and the error to the FP64 oracle
+    on the original design reported."""
+    import datagen
+    p = datagen.make_problem("c2", seed=1, store=store)
+    _say("c2 mixed", store)
+    A, b = _upload(p)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    assert info["kkt_rel"] <= p.tol
+    eta_stored = orc.eta(p.AT64, p.b, x, p.lam1, p.lam2)
+    assert eta_stored <= 1.5 * p.tol
+    xr, ir, _ = orc.en_solve(p.AT64, p.b, p.lam1, p.lam2, tol=1e-10)
+    F = orc.primal_obj(p.AT64, p.b, x, p.lam1, p.lam2)
+    assert _rel_obj(F, ir["primal_obj"]) <= 1e-8
+    print(f"[report] {store}: eta_stored={eta_stored:.3e} relobj_stored={_rel_obj(F, ir['primal_obj']):.3e}")
+
+
+def test_zero_solution(gpu, ctx, orc):
+    """lambda1 >= ||A^T b||_inf: x = 0 with r = 0 throughout."""
+    import datagen
+    p = datagen.make_problem("c1", seed=4)
+    lmax = np.max(np.abs(p.AT @ p.b))
+    A, b = _upload(p)
+    _say("zero solution")
+    x, info = gpu.ssnal_en_solve(ctx, A, b, lmax * 1.01, 0.3, tol=1e-10)
+    assert info["status"] == 0 and info["nnz"] == 0
+    assert np.count_nonzero(x.cpu().numpy()) == 0
+
+
+def test_ridge_limit(gpu, ctx, orc):
+    """lambda1 = 0: J is every column (r = n > m), the m x m system every step."""
+    A_, b_, _, _ = pinlib.gaussian_problem(60, 900, 9)
+    l2 = 0.7
+    import torch
+    A = torch.from_numpy(np.ascontiguousarray(A_.T)).cuda()
+    b = torch.from_numpy(b_).cuda()
+    _say("ridge")
+    x, info = gpu.ssnal_en_solve(ctx, A, b, 0.0, l2, tol=1e-11)
+    ref = A_.T @ np.linalg.solve(A_ @ A_.T + l2 * np.eye(60), b_)
+    assert info["status"] == 0
+    assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-9
+
+
+@pytest.mark.parametrize("m,n", [(1, 50), (7, 1), (300, 40)])
+def test_edge_shapes(gpu, ctx, orc, m, n):
+    """m = 1, n = 1, and m > n (orthogonal-ish designs)."""
+    import torch
+    g = np.random.default_rng(m * 100 + n)
+    A_ = g.standard_normal((m, n))
+    b_ = g.standard_normal(m)
+    l1 = 0.3 * np.max(np.abs(A_.T @ b_))
+    l2 = 0.2
+    A = torch.from_numpy(np.ascontiguousarray(A_.T)).cuda()
+    b = torch.from_numpy(b_).cuda()
+    _say("edge", m, n)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, l1, l2, tol=1e-11)
+    xr, ir, _ = orc.en_solve(np.ascontiguousarray(A_.T), b_, l1, l2, tol=1e-12)
+    assert info["status"] == 0, info
+    assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-8
+
+
+def test_padded_lda_and_warm_start(gpu, ctx, orc):
+    """lda > m with NaN padding rows; a warm start reaches the same minimiser."""
+    import datagen
+    p = datagen.make_problem("c1", seed=5)
+    A, b = _upload(p, lda=p.m + 4)
+    _say("padded lda + warm start")
+    x_cold, ic = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, m=p.m)
+    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1 * 1.2, p.lam2 * 1.2, tol=1e-10, m=p.m)
+    x_warm, iw = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x1, tol=1e-10, m=p.m)
+    assert ic["status"] == 0 and iw["status"] == 0
+    xc, xw = x_cold.cpu().numpy(), x_warm.cpu().numpy()
+    xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-11)
+    assert np.max(np.abs(xc - xr)) <= 1e-8 and np.max(np.abs(xw - xr)) <= 1e-8
+
+
+def test_errors(gpu, ctx):
+    import datagen
+    import torch
+    p = datagen.make_problem("c1", seed=6)
+    A, b = _upload(p)
+    _say("errors")
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, 0.0)
+    assert e.value.code == -1
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, b, -1.0, 0.5)
+    assert e.value.code == -1
+    bn = b.clone()
+    bn[3] = float("nan")
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, bn, p.lam1, p.lam2)
+    assert e.value.code == -2
+    o = gpu.make_opts(max_outer=1)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-14, opts=o)
+    assert info["status"] == 1
+
+
+def test_repeat_bitwise(gpu, ctx):
+    """Deterministic reductions: two solves of the same input agree bit for bit."""
+    import datagen
+    p = datagen.make_problem("c1", seed=7)
+    A, b = _upload(p)
+    _say("repeat")
+    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    x2, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())

@@ -141,6 +141,20 @@ def test_active_set_rule_and_tie(orc):
         assert u == orc.prox_sp(x[j], sigma, l1, l2)
 
 
+def test_smw_matrix_woodbury_identity(orc):
+    """eq. smw_formula: (I + kappa A_J A_J^T)^{-1} = I - A_J W^{-1} A_J^T with W the r x r matrix."""
+    A, b, l1, l2 = pinlib.gaussian_problem(25, 60, 21)
+    J = np.array([2, 5, 11, 17, 30, 41, 59], dtype=np.int32)
+    kappa = 0.37
+    W = orc.smw_matrix(A.T, J, kappa)
+    V = orc.newton_matrix(A.T, J, kappa)
+    AJ = A[:, J]
+    lhs = np.linalg.inv(V)
+    rhs = np.eye(25) - AJ @ np.linalg.inv(W) @ AJ.T
+    assert np.allclose(lhs, rhs, atol=1e-12)
+    assert np.allclose(W, W.T)
+
+
 def test_cholesky_against_library(orc):
     g = np.random.default_rng(11)
     M = g.standard_normal((30, 50))
