@@ -12,21 +12,69 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- reductions
-// Butterfly sums: every lane ends with the same value (a + b == b + a), and
-// the order is fixed, so results are bitwise reproducible run to run.
+// Wave sums on DPP lane permutations (no LDS traffic): xor-1 and xor-2
+// inside quads, then the half-row and row mirrors, which leaves every lane of
+// a 16-lane row holding the row sum; the four row sums are read out and
+// added in a fixed order.  At each step a lane adds the same two values as
+// its partner (a + b == b + a), so every lane ends with the same bits and
+// the result is reproducible run to run.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_d<kQuadXor1>(v);
+  v += dpp_d<kQuadXor2>(v);
+  v += dpp_d<kRowHalfMirror>(v);
+  v += dpp_d<kRowMirror>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f<kQuadXor1>(v);
+  v += dpp_f<kQuadXor2>(v);
+  v += dpp_f<kRowHalfMirror>(v);
+  v += dpp_f<kRowMirror>(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  v += dpp_i<kQuadXor1>(v);
+  v += dpp_i<kQuadXor2>(v);
+  v += dpp_i<kRowHalfMirror>(v);
+  v += dpp_i<kRowMirror>(v);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+// Sum over aligned groups of 8 lanes (every lane of a group gets the sum);
+// only the lanes of each group need to be active.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_d<kQuadXor1>(v);
+  v += dpp_d<kQuadXor2>(v);
+  v += dpp_d<kRowHalfMirror>(v);
   return v;
 }
 
@@ -45,22 +93,27 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
   return t;
 }
 
-// "Last block finishes" protocol: each block publishes its partials, then
-// counts itself in; the block that arrives last sees every partial (agent-
-// scope release/acquire fences make the writes of other XCDs visible) and
-// resets the counter for the next launch.  Returns true in the last block.
-__device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nblocks) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(counter, 1u);
-    last = (prev == nblocks - 1);
-    if (last) atomicExch(counter, 0u);
+// Sums of K components over nb partial rows part[b*K + k], by one block of
+// NT threads: thread t adds rows t, t+NT, ... (each row's K loads issued
+// together), then one tree per component.  out[k] is written by thread 0.
+// Fixed partition and order: reproducible.
+template <int NT, int K>
+__device__ __forceinline__ void final_sums(const double* part, int nb, double* out, double* lds) {
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) {
+    double row[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) row[k] = part[(int64_t)b * K + k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += row[k];
   }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double t = block_sum<NT>(v[k], lds);
+    if (threadIdx.x == 0) out[k] = t;
+  }
 }
 
 // ---------------------------------------------------------------- storage types

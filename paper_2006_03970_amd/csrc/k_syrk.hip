@@ -18,7 +18,7 @@
 namespace ssnal {
 
 constexpr int kTile = 64;
-constexpr int kKS = 16;          // K elements staged per step
+constexpr int kKS = 32;          // K elements staged per step
 constexpr int kPitch = kTile + 1;  // LDS row pitch (odd, to spread banks)
 
 template <typename T> struct MfmaOf { using C = float; };
@@ -49,34 +49,50 @@ __device__ __forceinline__ void tile_of(int t, int& ti, int& tj) {
 
 // Z element loaders.  form 0: Z[a][k] = A[a, J[k]] (a < m, k < r).
 //                     form 1: Z[a][k] = A[k, J[a]] (a < r, k < m).
+// A stage is 64 rows x kKS k-values = 2048 elements, 8 per thread, fetched
+// into registers (the next stage's loads are in flight while the matrix
+// cores work on the current one) and then stored to LDS.
 template <typename T, typename C, int FORM>
-__device__ __forceinline__ void stage(const T* __restrict__ A, int64_t lda, int N, int64_t K,
+__device__ __forceinline__ void fetch(const T* __restrict__ A, int64_t lda, int N, int64_t K,
                                       const int32_t* __restrict__ J, int row0, int64_t k0,
-                                      C (*dst)[kPitch]) {
-  // 64 rows x kKS k-values = 1024 elements, 4 per thread
+                                      C (&v)[8]) {
   const int t = threadIdx.x;
   if (FORM == 0) {
-    const int kk = t / 16;          // 16 columns
-    const int a0 = (t % 16) * 4;    // 4 consecutive rows
+    const int kk = t / 8;           // 32 columns
+    const int a0 = (t % 8) * 8;     // 8 consecutive rows
     const int64_t k = k0 + kk;
     const bool kok = k < K;
     const T* col = A + (kok ? (int64_t)J[k] : 0) * lda;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int a = row0 + a0 + q;
-      dst[kk][a0 + q] = (kok && a < N) ? load1<C>(col + a) : (C)0;
+      v[q] = (kok && a < N) ? load1<C>(col + a) : (C)0;
     }
   } else {
     const int aa = t / 4;           // 64 gathered columns
-    const int kq = (t % 4) * 4;     // 4 consecutive rows of that column
+    const int kq = (t % 4) * 8;     // 8 consecutive rows of that column
     const int a = row0 + aa;
     const bool aok = a < N;
     const T* col = A + (aok ? (int64_t)J[a] : 0) * lda;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int64_t k = k0 + kq + q;
-      dst[kq + q][aa] = (aok && k < K) ? load1<C>(col + k) : (C)0;
+      v[q] = (aok && k < K) ? load1<C>(col + k) : (C)0;
     }
+  }
+}
+
+template <typename C, int FORM>
+__device__ __forceinline__ void store_stage(const C (&v)[8], C (*dst)[kPitch]) {
+  const int t = threadIdx.x;
+  if (FORM == 0) {
+    const int kk = t / 8, a0 = (t % 8) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[kk][a0 + q] = v[q];
+  } else {
+    const int aa = t / 4, kq = (t % 4) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[kq + q][aa] = v[q];
   }
 }
 
@@ -106,11 +122,18 @@ __global__ __launch_bounds__(256) void k_syrk_partial(const T* __restrict__ A, i
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = V4{0, 0, 0, 0};
 
+  C ri[8], rj[8];
+  fetch<T, C, FORM>(A, lda, N, ke, J, ti * kTile, kb, ri);
+  if (!diag) fetch<T, C, FORM>(A, lda, N, ke, J, tj * kTile, kb, rj);
   for (int64_t k0 = kb; k0 < ke; k0 += kKS) {
     __syncthreads();
-    stage<T, C, FORM>(A, lda, N, ke, J, ti * kTile, k0, zi);
-    if (!diag) stage<T, C, FORM>(A, lda, N, ke, J, tj * kTile, k0, zj);
+    store_stage<C, FORM>(ri, zi);
+    if (!diag) store_stage<C, FORM>(rj, zj);
     __syncthreads();
+    if (k0 + kKS < ke) {
+      fetch<T, C, FORM>(A, lda, N, ke, J, ti * kTile, k0 + kKS, ri);
+      if (!diag) fetch<T, C, FORM>(A, lda, N, ke, J, tj * kTile, k0 + kKS, rj);
+    }
     C (*zb)[kPitch] = diag ? zi : zj;
 #pragma unroll
     for (int ks = 0; ks < kKS; ks += 4) {
@@ -142,24 +165,35 @@ __global__ __launch_bounds__(256) void k_syrk_partial(const T* __restrict__ A, i
       }
 }
 
+// One thread per tile element (16 workgroups per tile); the split partials
+// are summed in split order, eight loads in flight.
 __global__ __launch_bounds__(256) void k_syrk_finish(const double* __restrict__ part, int N,
                                                      int ntiles, int nsplit, double shift,
                                                      double scale, double* __restrict__ out) {
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x / 16;
+  const int e = (blockIdx.x % 16) * 256 + threadIdx.x;
   int ti, tj;
   tile_of(tile, ti, tj);
-  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-    const int li = e / kTile, lj = e % kTile;
-    const int i = ti * kTile + li, j = tj * kTile + lj;
-    if (i >= N || j >= N) continue;
-    if (ti == tj && li > lj) continue;  // diagonal tile: upper half, mirrored below
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * ntiles + tile) * (kTile * kTile) + e];
-    double v = scale * s;
-    if (i == j) v += shift;
-    out[(int64_t)i * N + j] = v;
-    out[(int64_t)j * N + i] = v;
+  const int li = e / kTile, lj = e % kTile;
+  const int i = ti * kTile + li, j = tj * kTile + lj;
+  if (i >= N || j >= N) return;
+  if (ti == tj && li > lj) return;  // diagonal tile: upper half, mirrored below
+  const double* src = part + (int64_t)tile * (kTile * kTile) + e;
+  const int64_t stride = (int64_t)ntiles * (kTile * kTile);
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(sp + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
+  for (; sp < nsplit; ++sp) s += src[sp * stride];
+  double v = scale * s;
+  if (i == j) v += shift;
+  out[(int64_t)i * N + j] = v;
+  out[(int64_t)j * N + i] = v;
 }
 
 namespace {
@@ -173,8 +207,8 @@ SyrkPlan plan(int form, int m, int64_t r) {
   p.K = form == 0 ? r : m;
   p.T = (p.N + kTile - 1) / kTile;
   p.ntiles = p.T * (p.T + 1) / 2;
-  int64_t want = (2048 + p.ntiles - 1) / p.ntiles;
-  int64_t maxs = (p.K + 255) / 256;
+  int64_t want = (1024 + p.ntiles - 1) / p.ntiles;
+  int64_t maxs = (p.K + 63) / 64;
   if (maxs < 1) maxs = 1;
   int64_t s = want < maxs ? want : maxs;
   if (s < 1) s = 1;
@@ -207,8 +241,8 @@ static hipError_t launch_syrk(const T* A, int64_t lda, int m, const int32_t* J, 
                        p.ntiles, p.kchunk, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_syrk_finish, dim3(p.ntiles), dim3(256), 0, st, work, p.N, p.ntiles, p.nsplit,
-                     shift, scale, out);
+  hipLaunchKernelGGL(k_syrk_finish, dim3(p.ntiles * 16), dim3(256), 0, st, work, p.N, p.ntiles,
+                     p.nsplit, shift, scale, out);
   return hipGetLastError();
 }
 

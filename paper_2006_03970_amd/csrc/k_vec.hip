@@ -17,6 +17,25 @@ int prox_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
 __device__ __forceinline__ bool active(double t, double thr) { return t > thr || t < -thr; }
 
+// ------------------------------------------------------------------ finishers
+// Reductions that span blocks finish in a second, single-block kernel: the
+// kernel boundary makes every block's partials visible, with no device-wide
+// cache write-back inside the producing kernel.
+template <int K>
+__global__ __launch_bounds__(kNT) void k_final(const double* __restrict__ part, int nb,
+                                               double* __restrict__ out,
+                                               const double* __restrict__ y, int m,
+                                               double* __restrict__ yy_out) {
+  __shared__ double red[kNT / kWave];
+  final_sums<kNT, K>(part, nb, out, red);
+  if (y) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < m; i += kNT) t += y[i] * y[i];
+    t = block_sum<kNT>(t, red);
+    if (threadIdx.x == 0) *yy_out = t;
+  }
+}
+
 // ------------------------------------------------------------------ compaction
 // Active set J = {i : |t_i| > sigma*lambda1} (eq. Q_def), t = x - sigma*w.
 template <bool UPDATE, bool SUPPORT>
@@ -144,19 +163,21 @@ __host__ __device__ __forceinline__ void chunk_plan(int64_t r, int& nc, int64_t&
     return;
   }
   int64_t c = (r + 1023) / 1024;
-  if (c < 64) c = 64;
+  c = (c + 15) / 16 * 16;  // whole groups of 16 columns
   nc = (int)((r + c - 1) / c);
-  ck = (r + nc - 1) / nc;
+  ck = c;
 }
 
-// Upper bound of the chunk count for any r <= r_bound: nc(r) <= ceil(r/64)
-// while r <= 65536 and nc(r) <= 1024 beyond (nc itself is not monotone in r).
+// Upper bound of the chunk count for any r <= r_bound: nc(r) = ceil(r/16)
+// while r <= 16384 and nc(r) <= 1024 beyond (nc itself is not monotone in r).
 int gather_chunks(int64_t r_bound) {
   if (r_bound <= 0) return 0;
-  const int64_t c = (r_bound + 63) / 64;
+  const int64_t c = (r_bound + 15) / 16;
   return (int)(c < 1024 ? c : 1024);
 }
 
+// Block b sums columns [b*ck, (b+1)*ck) of A_J weighted by c, for every row;
+// a thread keeps the loads of 16 columns in flight.
 template <typename T, int NQ>
 __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A, int64_t lda, int m,
                                                          const int32_t* __restrict__ J,
@@ -173,27 +194,26 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  int64_t k = k0;
-  for (; k + 1 < k1; k += 2) {
-    const T* a0 = A + (int64_t)J[k] * lda;
-    const T* a1 = A + (int64_t)J[k + 1] * lda;
-    const double c0 = c[k], c1 = c[k + 1];
+  for (int64_t kb = k0; kb < k1; kb += 16) {
+    int64_t col[16];
+    double cv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t k = kb + u;
+      const bool ok = k < k1;
+      col[u] = ok ? (int64_t)J[k] * lda : -1;
+      cv[u] = ok ? c[k] : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int row = threadIdx.x + q * kNT;
       if (row < m) {
-        acc[q] += load1<double>(a0 + row) * c0;
-        acc[q] += load1<double>(a1 + row) * c1;
-      }
-    }
-  }
-  if (k < k1) {
-    const T* a0 = A + (int64_t)J[k] * lda;
-    const double c0 = c[k];
+        double v[16];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int row = threadIdx.x + q * kNT;
-      if (row < m) acc[q] += load1<double>(a0 + row) * c0;
+        for (int u = 0; u < 16; ++u) v[u] = col[u] >= 0 ? load1<double>(A + col[u] + row) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[q] += v[u] * cv[u];
+      }
     }
   }
 #pragma unroll
@@ -243,16 +263,24 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
                                                         const double* __restrict__ b,
                                                         double* __restrict__ g,
                                                         double* __restrict__ out2,
-                                                        double* __restrict__ scal,
-                                                        unsigned int* counter) {
+                                                        double* __restrict__ scal) {
   const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
   int nchunks;
   int64_t ck;
   chunk_plan(r, nchunks, ck);
   const int row = blockIdx.x * kNT + threadIdx.x;
   double S = 0.0;
-  if (row < m)
-    for (int c = 0; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+  if (row < m) {
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S += v[u];
+    }
+    for (; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+  }
   double v1 = 0.0, v2 = 0.0, v3 = 0.0;
   if (row < m) {
     if (mode == 0) {  // gradient of psi (eq. grad_phy) and the primal residual A u - b
@@ -279,20 +307,18 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
     scal[SC_BLK + 3 * blockIdx.x + 1] = s2;
     scal[SC_BLK + 3 * blockIdx.x + 2] = s3;
   }
-  if (!arrive_last(counter, gridDim.x)) return;
-  if (threadIdx.x < 3) {
-    double t = 0.0;
-    for (unsigned int q = 0; q < gridDim.x; ++q) t += scal[SC_BLK + 3 * q + threadIdx.x];
-    scal[SC_GG + threadIdx.x] = t;
-  }
 }
 
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         unsigned int* counter, hipStream_t st) {
+                         hipStream_t st) {
   const int nb = (m + kNT - 1) / kNT;
   hipLaunchKernelGGL(k_gather_finish, dim3(nb), dim3(kNT), 0, st, part, r_dev, r_host, m, mode, y, b,
-                     g, out2, scal, counter);
+                     g, out2, scal);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode != 0) return e;
+  hipLaunchKernelGGL((k_final<3>), dim3(1), dim3(kNT), 0, st, scal + SC_BLK, nb, scal + SC_GG,
+                     (const double*)nullptr, 0, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -308,13 +334,8 @@ constexpr int kLsSlots = kMaxTrials + 1;  // 32 trial sums + the common second-o
 __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x,
                                                      const double* __restrict__ w,
                                                      const double* __restrict__ wd, int64_t n,
-                                                     LsArgs la, const double* __restrict__ g,
-                                                     const double* __restrict__ d,
-                                                     double* __restrict__ y, int m,
-                                                     double* __restrict__ part,
-                                                     double* __restrict__ scal,
-                                                     unsigned int* counter, int select, double gd_in,
-                                                     double dd_in) {
+                                                     LsArgs la,
+                                                     double* __restrict__ part) {
   const double sigma = la.sigma, thr = la.thr, den = la.den, kappa = la.kappa;
   const int K = la.K;
   double e[kMaxTrials];
@@ -323,11 +344,21 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
   double e2 = 0.0;
   const double smax = la.s[0];
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double xv[kEPT], wv[kEPT], dv[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {  // issue every load first
+    const int64_t i = base + q * kNT + threadIdx.x;
+    const bool ok = i < n;
+    xv[q] = ok ? x[i] : 0.0;
+    wv[q] = ok ? w[i] : 0.0;
+    dv[q] = ok ? wd[i] : 0.0;
+  }
+#pragma unroll
   for (int q = 0; q < kEPT; ++q) {
     const int64_t i = base + q * kNT + threadIdx.x;
-    if (i >= n) break;
-    const double t0 = fma(-sigma, w[i], x[i]);
-    const double wi = wd[i];
+    if (i >= n) continue;
+    const double t0 = fma(-sigma, wv[q], xv[q]);
+    const double wi = dv[q];
     const double a0 = fabs(t0);
     const double reach = smax * sigma * fabs(wi) * (1.0 + 1e-12);
     if (a0 + reach < thr) continue;  // inactive for every trial step
@@ -336,20 +367,16 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
       continue;
     }
     const double u0 = prox_en(t0, thr, den);
+    const double rden = 1.0 / den, h = den / (2.0 * sigma), hk = 0.5 * kappa * wi * wi;
 #pragma unroll
     for (int k = 0; k < kMaxTrials; ++k) {
-      if (k < K) {
-        const double s = la.s[k];
-        const double t1 = fma(-(s * sigma), wi, t0);
-        double ek;
-        if ((t0 > thr && t1 > thr) || (t0 < -thr && t1 < -thr)) {
-          ek = 0.5 * s * s * kappa * wi * wi;
-        } else {
-          const double u1 = prox_en(t1, thr, den);
-          ek = den / (2.0 * sigma) * (u1 * u1 - u0 * u0) + s * wi * u0;
-        }
-        e[k] += ek;
-      }
+      const double s = la.s[k];
+      const double t1 = fma(-(s * sigma), wi, t0);
+      const bool same = (t0 > thr && t1 > thr) || (t0 < -thr && t1 < -thr);
+      const double num = t1 > thr ? t1 - thr : (t1 < -thr ? t1 + thr : 0.0);
+      const double u1 = num * rden;
+      const double other = h * (u1 * u1 - u0 * u0) + s * wi * u0;
+      e[k] += (k < K) ? (same ? s * s * hk : other) : 0.0;
     }
   }
   // block reduction of the 33 sums
@@ -371,19 +398,23 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
     for (int q = 0; q < kNT / kWave; ++q) t += wsum[q][threadIdx.x];
     part[(int64_t)blockIdx.x * kLsSlots + threadIdx.x] = t;
   }
-  if (!arrive_last(counter, gridDim.x)) return;
+}
 
+// Trial selection (one block): Delta_k from the partial sums, the first k
+// with Delta_k <= mu s_k g^T d, y += s d.  With select == 0 only the
+// increments are produced (for the caller's g^T d and |d|^2).
+__global__ __launch_bounds__(kNT) void k_ls_select(const double* __restrict__ part, int nb, LsArgs la,
+                                                   const double* __restrict__ g,
+                                                   const double* __restrict__ d,
+                                                   double* __restrict__ y, int m,
+                                                   double* __restrict__ scal, int select,
+                                                   double gd_in, double dd_in) {
   __shared__ double tot[kLsSlots];
   __shared__ double sh_s;
-  if (threadIdx.x < kLsSlots) {
-    double t = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[(int64_t)b * kLsSlots + threadIdx.x];
-    tot[threadIdx.x] = t;
-  }
-  // g^T d and |d|^2 (m-vectors), or the caller's values
+  __shared__ double red[kNT / kWave];
+  final_sums<kNT, kLsSlots>(part, nb, tot, red);
   double gd = gd_in, dd = dd_in;
   if (select) {
-    __shared__ double red[kNT / kWave];
     double pgd = 0.0, pdd = 0.0;
     for (int i = threadIdx.x; i < m; i += kNT) {
       pgd += g[i] * d[i];
@@ -396,7 +427,7 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
   if (threadIdx.x == 0) {
     double acc_s = 0.0;
     int acc_k = -1;
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < la.K; ++k) {
       const double s = la.s[k];
       const double delta = s * gd + 0.5 * s * s * dd + s * s * tot[kMaxTrials] + tot[k];
       scal[SC_DELTA + k] = delta;
@@ -423,20 +454,24 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
 
 hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
                       const double* g, const double* d, double* y, int m, double* part,
-                      double* scal, unsigned int* counter, hipStream_t st) {
+                      double* scal, hipStream_t st) {
   const int nb = prox_blocks(n);
-  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, g, d, y, m, part,
-                     scal, counter, 1, 0.0, 0.0);
+  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kNT), 0, st, part, nb, la, g, d, y, m, scal, 1, 0.0,
+                     0.0);
   return hipGetLastError();
 }
 
 hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
-                    double gd, double dd, double* part, double* scal, unsigned int* counter,
-                    hipStream_t st) {
+                    double gd, double dd, double* part, double* scal, hipStream_t st) {
   const int nb = prox_blocks(n);
-  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la,
-                     (const double*)nullptr, (const double*)nullptr, (double*)nullptr, 0, part, scal,
-                     counter, 0, gd, dd);
+  hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kNT), 0, st, part, nb, la, (const double*)nullptr,
+                     (const double*)nullptr, (double*)nullptr, 0, scal, 0, gd, dd);
   return hipGetLastError();
 }
 
@@ -446,9 +481,8 @@ hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t 
 // enters the kkt3 denominator.
 __global__ __launch_bounds__(kNT) void k_outer(double* __restrict__ x, const double* __restrict__ w,
                                                 int64_t n, double sigma, double thr, double den,
-                                                double l1, double l2, const double* __restrict__ y,
-                                                int m, double* __restrict__ part,
-                                                double* __restrict__ scal, unsigned int* counter) {
+                                                double l1, double l2,
+                                                double* __restrict__ part) {
   double xu = 0.0, zz = 0.0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
 #pragma unroll
@@ -475,24 +509,17 @@ __global__ __launch_bounds__(kNT) void k_outer(double* __restrict__ x, const dou
     part[2 * blockIdx.x] = s1;
     part[2 * blockIdx.x + 1] = s2;
   }
-  if (!arrive_last(counter, gridDim.x)) return;
-  double yy = 0.0;
-  for (int i = threadIdx.x; i < m; i += kNT) yy += y[i] * y[i];
-  yy = block_sum<kNT>(yy, red);
-  if (threadIdx.x < 2) {
-    double t = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[2 * b + threadIdx.x];
-    scal[SC_XU + threadIdx.x] = t;
-  }
-  if (threadIdx.x == 0) scal[SC_YY] = yy;
 }
 
 hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
-                        const double* y, int m, double* part, double* scal, unsigned int* counter,
-                        hipStream_t st) {
+                        const double* y, int m, double* part, double* scal, hipStream_t st) {
   const int nb = prox_blocks(n);
-  hipLaunchKernelGGL(k_outer, dim3(nb), dim3(kNT), 0, st, x, w, n, pa.sigma, pa.thr, pa.den, l1, l2, y,
-                     m, part, scal, counter);
+  hipLaunchKernelGGL(k_outer, dim3(nb), dim3(kNT), 0, st, x, w, n, pa.sigma, pa.thr, pa.den, l1, l2,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_final<2>), dim3(1), dim3(kNT), 0, st, part, nb, scal + SC_XU, y, m,
+                     scal + SC_YY);
   return hipGetLastError();
 }
 
@@ -502,8 +529,7 @@ hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, doub
 // and for the objectives F(x) and D(rho) (p^* of Prop. 1 at -q).
 __global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
                                               const double* __restrict__ q, int64_t n, double l1,
-                                              double den1, double* __restrict__ part,
-                                              double* __restrict__ scal, unsigned int* counter) {
+                                              double den1, double* __restrict__ part) {
   double se = 0.0, sxx = 0.0, sx1 = 0.0, sps = 0.0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
 #pragma unroll
@@ -531,19 +557,17 @@ __global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
     part[4 * blockIdx.x + 2] = r2;
     part[4 * blockIdx.x + 3] = r3;
   }
-  if (!arrive_last(counter, gridDim.x)) return;
-  if (threadIdx.x < 4) {
-    double t = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) t += part[4 * b + threadIdx.x];
-    scal[SC_ETA_E + threadIdx.x] = t;
-  }
 }
 
 hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2, double* part,
-                    double* scal, unsigned int* counter, hipStream_t st) {
+                    double* scal, hipStream_t st) {
   const int nb = prox_blocks(n);
   const double den1 = 1.0 + l2;
-  hipLaunchKernelGGL(k_eta, dim3(nb), dim3(kNT), 0, st, x, q, n, l1, den1, part, scal, counter);
+  hipLaunchKernelGGL(k_eta, dim3(nb), dim3(kNT), 0, st, x, q, n, l1, den1, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_final<4>), dim3(1), dim3(kNT), 0, st, part, nb, scal + SC_ETA_E,
+                     (const double*)nullptr, 0, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -577,8 +601,7 @@ hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st) {
 }
 
 __global__ __launch_bounds__(kNT) void k_nonfinite(const double* __restrict__ v, int64_t n,
-                                                    double* __restrict__ part,
-                                                    double* __restrict__ slot, unsigned int* counter) {
+                                                    double* __restrict__ part) {
   int c = 0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
 #pragma unroll
@@ -589,18 +612,16 @@ __global__ __launch_bounds__(kNT) void k_nonfinite(const double* __restrict__ v,
   __shared__ int red[kNT / kWave];
   const int t = block_sum<kNT>(c, red);
   if (threadIdx.x == 0) part[blockIdx.x] = (double)t;
-  if (!arrive_last(counter, gridDim.x)) return;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) s += part[b];
-    *slot = s;
-  }
 }
 
-hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, unsigned int* counter,
-                           double* part, hipStream_t st) {
+hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, double* part,
+                           hipStream_t st) {
   const int nb = prox_blocks(n);
-  hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(kNT), 0, st, v, n, part, scal_slot, counter);
+  hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(kNT), 0, st, v, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, scal_slot,
+                     (const double*)nullptr, 0, (double*)nullptr);
   return hipGetLastError();
 }
 

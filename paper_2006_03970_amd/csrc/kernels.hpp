@@ -52,11 +52,11 @@ hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, con
 //  mode 2 (residual): out2 = y = S - b
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         unsigned int* counter, hipStream_t st);
+                         hipStream_t st);
 
 // Line search: for the K trial steps s_k, Delta_k = psi(y + s_k d) - psi(y);
-// the last block picks the first k with Delta_k <= mu s_k g^T d, updates
-// y += s d and writes s (0 if none) to scal.
+// a one-block follow-up kernel picks the first k with Delta_k <= mu s_k g^T d,
+// updates y += s d and writes s (0 if none) to scal.
 constexpr int kMaxTrials = 32;
 struct LsArgs {
   double sigma, thr, den, kappa, mu;
@@ -65,27 +65,25 @@ struct LsArgs {
 };
 hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
                       const double* g, const double* d, double* y, int m, double* part,
-                      double* scal, unsigned int* counter, hipStream_t st);
+                      double* scal, hipStream_t st);
 // Line-search increments only (no selection): scal[SC_DELTA + k] = Delta_k, k < K.
 hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
-                    double gd, double dd, double* part, double* scal, unsigned int* counter,
-                    hipStream_t st);
+                    double gd, double dd, double* part, double* scal, hipStream_t st);
 
 // Multiplier update x <- prox(t), with |x - u|^2, |z|^2 (z the conjugate
 // prox of Prop. 2 (2)) and |y|^2 reduced into scal.
 hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
-                        const double* y, int m, double* part, double* scal, unsigned int* counter,
-                        hipStream_t st);
+                        const double* y, int m, double* part, double* scal, hipStream_t st);
 // eta pass over q = A^T rho: sums of (x - prox_p(x - q))^2, x^2, |x|, and
 // (|q| - l1)_+^2 into scal.
 hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2,
-                    double* part, double* scal, unsigned int* counter, hipStream_t st);
+                    double* part, double* scal, hipStream_t st);
 
 // Small helpers
 hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st);
 hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st);
-hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, unsigned int* counter,
-                           double* part, hipStream_t st);
+hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, double* part,
+                           hipStream_t st);
 
 // ---- Newton matrix (k_syrk.hip) ------------------------------------------
 // form 0: out = shift*I_m + scale * A_J A_J^T   (m x m, K = r)
@@ -96,19 +94,16 @@ hipError_t syrk(const void* A, int dtype, int64_t lda, int m, const int32_t* J, 
                 double shift, double scale, double* out, void* work, hipStream_t st);
 
 // ---- Cholesky and triangular solves (k_chol.hip) --------------------------
-// In-place factor of an SPD N x N row-major matrix: lower triangle = L.
-// info_dev (int) receives 0 or k+1 for a non-positive pivot k.
-hipError_t cholesky(double* V, int N, int* info_dev, hipStream_t st);
-// Solve L L^T x = rhs for x (may alias rhs); alpha scales rhs first.
-hipError_t chol_solve(const double* L, int N, const double* rhs, double alpha, double* x,
-                      hipStream_t st);
-// Raise the dynamic LDS limits of the single-workgroup kernels (once per device).
+// Raise the dynamic LDS limits of the Cholesky kernels (once per device).
 hipError_t chol_init();
+// Factor the SPD N x N row-major V in place (lower triangle = L; the strict
+// upper triangle keeps stale values) and, when rhs is non-null, solve
+// L L^T x = alpha*rhs (z: N doubles of scratch for L^{-1} alpha rhs; x may
+// alias rhs).  info_dev (int) receives row+1 of a non-positive pivot.
+hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, double* z,
+                             double* x, int* info_dev, hipStream_t st);
+hipError_t cholesky(double* V, int N, int* info_dev, hipStream_t st);
 // Zero the strict upper triangle (for callers that want L alone).
 hipError_t zero_upper(double* V, int N, hipStream_t st);
-// Fused small path (N <= kSmallN): factor + solve in one workgroup.
-constexpr int kSmallN = 128;
-hipError_t chol_factor_solve_small(double* V, int N, const double* rhs, double alpha, double* x,
-                                   int* info_dev, hipStream_t st);
 
 }  // namespace ssnal

@@ -27,7 +27,4 @@ enum Scal : int {
   SC_SIZE = 160
 };
 
-// Counters of the "last block finishes" reductions, one per kernel kind.
-enum Ctr : int { CT_GATHER = 0, CT_LS = 1, CT_OUTER = 2, CT_ETA = 3, CT_NONFIN = 4, CT_SIZE = 8 };
-
 }  // namespace ssnal

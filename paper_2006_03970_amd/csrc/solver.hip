@@ -51,7 +51,7 @@ struct DevBuf {
 
 struct ssnal_ctx {
   int device = 0;
-  DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal, ctr;
+  DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal;
   double* h_scal = nullptr;  // pinned, SC_SIZE doubles
   std::vector<hipEvent_t> ev;
   bool chol_ready = false;
@@ -79,15 +79,14 @@ int ensure(DevBuf& b, size_t bytes) {
 }
 
 // m-vector slots inside ctx->mvec
-enum MV : int { MV_Y = 0, MV_G, MV_D, MV_RHO, MV_T1, MV_T2, MV_COUNT };
+enum MV : int { MV_Y = 0, MV_G, MV_D, MV_RHO, MV_T1, MV_T2, MV_T3, MV_COUNT };
 
 struct Workspace {
   double *wy, *wd, *uJ, *part, *gpart, *V, *scal;
-  double *y, *g, *d, *rho, *t1, *t2;
+  double *y, *g, *d, *rho, *t1, *t2, *t3;
   int32_t* J;
   int* counts;
   void* syrk;
-  unsigned int* ctr;
   int* info;
 };
 
@@ -119,8 +118,8 @@ int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
   w.rho = mv + MV_RHO * m;
   w.t1 = mv + MV_T1 * m;
   w.t2 = mv + MV_T2 * m;
+  w.t3 = mv + MV_T3 * m;
   w.scal = (double*)c->scal.p;
-  w.ctr = (unsigned int*)c->ctr.p;
   w.info = (int*)(w.scal + SC_CHOL);  // Cholesky status, read back with the scalars
   return 0;
 }
@@ -191,12 +190,7 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   if (form < 0) form = (r < m) ? 1 : 0;
   if (form == 0) {
     HIPCHK(syrk(A, dt, lda, m, J, r, 0, 1.0, kappa, w.V, w.syrk, st));
-    if (m <= kSmallN) {
-      HIPCHK(chol_factor_solve_small(w.V, m, g, -1.0, d, w.info, st));
-    } else {
-      HIPCHK(cholesky(w.V, m, w.info, st));
-      HIPCHK(chol_solve(w.V, m, g, -1.0, d, st));
-    }
+    HIPCHK(chol_factor_solve(w.V, m, g, -1.0, w.t3, d, w.info, st));
     return 0;
   }
   // (I + kappa A_J A_J^T)^{-1} = I - A_J (I/kappa + A_J^T A_J)^{-1} A_J^T
@@ -206,14 +200,9 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   double* q = w.t2;
   HIPCHK(gemv_t(A, dt, lda, m, r, J, g, v, true, st));
   HIPCHK(syrk(A, dt, lda, m, J, r, 1, 1.0 / kappa, 1.0, w.V, w.syrk, st));
-  if (N <= kSmallN) {
-    HIPCHK(chol_factor_solve_small(w.V, N, v, 1.0, q, w.info, st));
-  } else {
-    HIPCHK(cholesky(w.V, N, w.info, st));
-    HIPCHK(chol_solve(w.V, N, v, 1.0, q, st));
-  }
+  HIPCHK(chol_factor_solve(w.V, N, v, 1.0, w.t3, q, w.info, st));
   HIPCHK(gather_gemv_partial(A, dt, lda, m, J, q, nullptr, r, w.gpart, st));
-  HIPCHK(gather_finish(w.gpart, nullptr, r, m, 1, nullptr, nullptr, const_cast<double*>(g), d, w.scal, w.ctr + CT_GATHER,
+  HIPCHK(gather_finish(w.gpart, nullptr, r, m, 1, nullptr, nullptr, const_cast<double*>(g), d, w.scal,
                        st));
   return 0;
 }
@@ -236,8 +225,7 @@ int prox_grad(const void* A, int dt, int64_t lda, const double* b, int m, int64_
   HIPCHK(prox_count(x, w.wy, w.wd, pending ? w.scal + SC_S : nullptr, n, pa, w.counts, st));
   HIPCHK(prox_write(x, w.wy, n, pa, w.counts, w.J, w.uJ, w.scal + SC_R, st));
   HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
-  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal,
-                       w.ctr + CT_GATHER, st));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal, st));
   return 0;
 }
 
@@ -248,7 +236,7 @@ int certify(const void* A, int dt, int64_t lda, int m, int64_t n, const double* 
   HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.rho, w.wd, true, st));
   if (int rc = tm.rec_stop()) return rc;
   ++*gemv_calls;
-  HIPCHK(eta_pass(x, w.wd, n, l1, l2, w.part, w.scal, w.ctr + CT_ETA, st));
+  HIPCHK(eta_pass(x, w.wd, n, l1, l2, w.part, w.scal, st));
   return 0;
 }
 
@@ -301,14 +289,13 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   // ---- start: x = x0 (or 0), y = A x0 - b, w_y = A^T y
   if (x0) {
     if (x0 != x) HIPCHK(hipMemcpyAsync(x, x0, n * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(nonfinite_count(x, n, w.scal + SC_NONFIN, w.ctr + CT_NONFIN, w.part, st));
+    HIPCHK(nonfinite_count(x, n, w.scal + SC_NONFIN, w.part, st));
     if (int rc = readback(c, w, st, &syncs)) return rc;
     if (hs[SC_NONFIN] != 0.0) return fail(SSNAL_ENONFINITE, "x0 holds %g non-finite entries", hs[SC_NONFIN]);
     HIPCHK(support_count(x, n, w.counts, st));
     HIPCHK(support_write(x, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
     HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
-    HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 2, nullptr, b, nullptr, w.y, w.scal,
-                         w.ctr + CT_GATHER, st));
+    HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 2, nullptr, b, nullptr, w.y, w.scal, st));
   } else {
     HIPCHK(hipMemsetAsync(x, 0, n * 8, st));
     HIPCHK(vec_scale_copy(b, -1.0, w.y, m, st));
@@ -318,7 +305,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   HIPCHK(gemv_t_colsq(A, dt, lda, m, n, w.y, w.wy, w.part, &nparts, st));
   if (int rc = tm.rec_stop()) return rc;
   ++gemv_calls;
-  HIPCHK(nonfinite_count(w.wy, n, w.scal + SC_NONFIN, w.ctr + CT_NONFIN, w.part + 2048, st));
+  HIPCHK(nonfinite_count(w.wy, n, w.scal + SC_NONFIN, w.part + 2048, st));
   std::vector<double> hb(m), hpart(nparts);
   HIPCHK(hipMemcpyAsync(hb.data(), b, m * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(hpart.data(), w.part, nparts * 8, hipMemcpyDeviceToHost, st));
@@ -406,7 +393,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.d, w.wd, !mixed, st));
       if ((rc = tm.rec_stop())) return rc;
       ++gemv_calls;
-      HIPCHK(linesearch(x, w.wy, w.wd, n, la, w.g, w.d, w.y, m, w.part, w.scal, w.ctr + CT_LS, st));
+      HIPCHK(linesearch(x, w.wy, w.wd, n, la, w.g, w.d, w.y, m, w.part, w.scal, st));
       pending = true;
       if (o.trace && rows < o.trace_cap) {
         double* row = o.trace + rows * 6;
@@ -422,7 +409,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       ++inner;
     }
     // multiplier update x <- prox(x - sigma A^T y)
-    HIPCHK(outer_update(x, w.wy, n, pa, l1, l2, w.y, m, w.part, w.scal, w.ctr + CT_OUTER, st));
+    HIPCHK(outer_update(x, w.wy, n, pa, l1, l2, w.y, m, w.part, w.scal, st));
     ++outer_done;
     bool need_eta = false;
     if (int rc = readback(c, w, st, &syncs)) return rc;
@@ -511,11 +498,11 @@ int ssnal_ctx_create(int device, ssnal_ctx** out) {
   if (!c) return fail(SSNAL_ENOMEM, "host allocation failed");
   c->device = device;
   int rc;
-  if ((rc = ensure(c->scal, SC_SIZE * sizeof(double))) || (rc = ensure(c->ctr, CT_SIZE * 4))) {
+  if ((rc = ensure(c->scal, SC_SIZE * sizeof(double)))) {
     ssnal_ctx_destroy(c);
     return rc;
   }
-  if (hipMemset(c->scal.p, 0, c->scal.bytes) != hipSuccess || hipMemset(c->ctr.p, 0, c->ctr.bytes) != hipSuccess ||
+  if (hipMemset(c->scal.p, 0, c->scal.bytes) != hipSuccess ||
       hipHostMalloc((void**)&c->h_scal, SC_SIZE * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       chol_init() != hipSuccess) {
     ssnal_ctx_destroy(c);
@@ -530,7 +517,7 @@ void ssnal_ctx_destroy(ssnal_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart,
-                    &c->V, &c->syrk, &c->mvec, &c->scal, &c->ctr};
+                    &c->V, &c->syrk, &c->mvec, &c->scal};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -608,7 +595,7 @@ int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream) {
   if (int rc = prepare(ctx, N, 1, ws)) return rc;
   HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int), stream));
   HIPCHK(cholesky(V, (int)N, ws.info, stream));
-  if (N > kSmallN) HIPCHK(zero_upper(V, (int)N, stream));
+  HIPCHK(zero_upper(V, (int)N, stream));
   int hinfo = 0;
   HIPCHK(hipMemcpyAsync(&hinfo, ws.info, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
@@ -657,7 +644,7 @@ int ssnal_ls_delta(ssnal_ctx* ctx, const double* x, const double* w, const doubl
   la.mu = 0.2;
   la.K = K;
   for (int k = 0; k < kMaxTrials; ++k) la.s[k] = k < K ? s[k] : 0.0;
-  HIPCHK(ls_delta(x, w, wd, n, la, gd, dd, ws.part, ws.scal, ws.ctr + CT_LS, stream));
+  HIPCHK(ls_delta(x, w, wd, n, la, gd, dd, ws.part, ws.scal, stream));
   if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
   for (int k = 0; k < K; ++k) delta_out[k] = ctx->h_scal[SC_DELTA + k];
   return 0;
@@ -679,8 +666,7 @@ int ssnal_kkt(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, c
   HIPCHK(gather_gemv_partial(A, dt, lda, (int)m, ws.J, ws.uJ, ws.scal + SC_R, n, ws.gpart, stream));
   // mode 0 with y = 0 gives rho = A x - b and its norms
   HIPCHK(vec_fill(ws.y, 0.0, m, stream));
-  HIPCHK(gather_finish(ws.gpart, ws.scal + SC_R, 0, (int)m, 0, ws.y, b, ws.g, ws.rho, ws.scal,
-                       ws.ctr + CT_GATHER, stream));
+  HIPCHK(gather_finish(ws.gpart, ws.scal + SC_R, 0, (int)m, 0, ws.y, b, ws.g, ws.rho, ws.scal, stream));
   Timer tm{ctx, stream, false};
   int calls = 0;
   if (int rc = certify(A, dt, lda, (int)m, n, x, lambda1, lambda2, ws, stream, tm, &calls)) return rc;
