@@ -5,19 +5,25 @@
 //
 // Right-looking, 64 x 64 blocks, ONE launch per block column s:
 //   * panel workgroups p = 0 .. T-s-1 own row block s+p of column s.  Each
-//     first applies the rank-64 update of the previous step to its own tile
-//     and to the diagonal tile (matrix cores, FP64 MFMA), then runs the
-//     elimination of the stacked [diagonal tile; own tile] on registers
-//     (256 threads x 8 x 4 entries, one barrier per column), in unscaled
-//     form: a_il -= a_ij a_lj / a_jj, then L_il = a_il / sqrt(a_ll).
-//     Every panel workgroup factors the diagonal tile itself, so no
+//     applies the previous step's rank-64 update to its own tile and to the
+//     diagonal tile (FP64 matrix cores), then eliminates the stacked
+//     [diagonal tile; own tile] held in the MFMA accumulators, four columns at
+//     a time.  Every panel workgroup factors the diagonal tile itself, so no
 //     workgroup waits for another inside a launch.
-//   * the same launch's remaining workgroups apply the previous step's
-//     update to the trailing tiles of columns s+1 .. T-1.
+//   * the launch's remaining workgroups apply the previous step's update to
+//     the trailing tiles of columns s+1 .. T-1.
 //   * the forward substitution L z = alpha*rhs rides along: workgroup p
-//     subtracts L_{s+p,s-1} z_{s-1} from its block of the right-hand side,
-//     and the diagonal workgroup solves its block for z_s.
+//     subtracts L_{s+p,s-1} z_{s-1} from its block of the right-hand side, and
+//     an otherwise idle wave of the diagonal workgroup solves block s while
+//     the columns are eliminated.
 // A single workgroup then runs the backward substitution L^T x = z.
+//
+// Every chain here is latency-bound (N <= 4096, one 64-column block per
+// launch), so the kernels issue all global loads of a phase before the first
+// use (unconditional loads at clamped addresses, masked with non-short-
+// circuit conditions: a guarded load becomes a branch that waits for it), and
+// pivots use the hardware reciprocal-square-root estimate refined by Newton
+// steps instead of a correctly rounded sqrt and divide.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -25,6 +31,35 @@ namespace ssnal {
 
 constexpr int kNB = 64;
 constexpr int kBP = kNB + 1;  // LDS pitch of a 64 x 64 tile
+constexpr double kMinPivot = 2.2250738585072014e-308;  // smallest positive normal double
+
+// 1/sqrt(t) for a positive normal t: hardware estimate, then two Newton steps
+// y <- y + y (1 - t y^2) / 2 (quadratic convergence: a 2^-22 estimate reaches
+// rounding level after the second step).
+__device__ __forceinline__ double rsqrt_pos(double t) {
+  double y = __builtin_amdgcn_rsq(t);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-(t * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// 1/d for a normal d: hardware estimate, then two Newton steps r <- r + r(1 - d r).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+  }
+  return r;
+}
+
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
 
 __device__ __forceinline__ void tri_of(int t, int& i, int& j) {
   // t enumerates lower-triangle pairs (i >= j) row by row: t = i(i+1)/2 + j
@@ -35,18 +70,22 @@ __device__ __forceinline__ void tri_of(int t, int& i, int& j) {
   j = t - r * (r + 1) / 2;
 }
 
-// Stage a 64 x 64 block of V (rows i0.., cols k0..) transposed into LDS:
-// dst[k][i] = V[i0+i][k0+k], zero outside the matrix.
-// All 16 loads of a thread are issued before the first store to LDS.
-__device__ __forceinline__ void stage_t(const double* __restrict__ V, int N, int i0, int k0,
-                                        double (*dst)[kBP]) {
-  double v[16];
+// Load the 64 x 64 block of V at rows i0.., cols k0.. (256 threads, 16 each;
+// thread t holds entry e = t + 256q as (e / 64, e % 64)); zero outside the
+// matrix.  Addresses are clamped into the matrix, so every load is issued
+// unconditionally and all 16 are in flight together.
+__device__ __forceinline__ void load_tile(const double* __restrict__ V, int N, int i0, int k0,
+                                          double (&v)[16]) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + q * 256;
-    const int i = e / kNB, k = e % kNB;
-    v[q] = (i0 + i < N && k0 + k < N) ? V[(int64_t)(i0 + i) * N + k0 + k] : 0.0;
+    const int i = i0 + e / kNB, k = k0 + e % kNB;
+    const double x = V[(int64_t)min(i, N - 1) * N + min(k, N - 1)];
+    v[q] = ((i < N) & (k < N)) ? x : 0.0;
   }
+}
+// Store a block loaded by load_tile transposed: dst[k][i].
+__device__ __forceinline__ void store_t(const double (&v)[16], double (*dst)[kBP]) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + q * 256;
@@ -55,11 +94,11 @@ __device__ __forceinline__ void stage_t(const double* __restrict__ V, int N, int
 }
 
 // C[i][j] = sum_k P[k][i] Q[k][j] for the 64 x 64 tile, with P, Q staged by
-// stage_t.  Wave w owns rows 32*(w>>1).., columns 32*(w&1)..; FP64 MFMA
+// store_t.  Wave w owns rows 32*(w>>1).., columns 32*(w&1)..; FP64 MFMA
 // 16x16x4, whose accumulator v holds row lane/16 + 4*v, column lane%16.
 __device__ __forceinline__ void mfma_64(double (*P)[kBP], double (*Q)[kBP], dbl4 acc[2][2]) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
+  const int wid = wave_id();
   const int wi = wid >> 1, wj = wid & 1;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -81,33 +120,59 @@ __device__ __forceinline__ void mfma_64(double (*P)[kBP], double (*Q)[kBP], dbl4
   }
 }
 
-// tile[r][c] -= C  (r, c local to the 64 x 64 tile)
-__device__ __forceinline__ void sub_acc(double (*tile)[kBP], dbl4 acc[2][2]) {
+struct StepLds {
+  union {
+    struct {
+      double P[kNB][kBP];  // L_{s,s-1}, transposed (previous step's update)
+      double Q[kNB][kBP];  // L_{s+p,s-1}, transposed
+    } st;
+    double LF[2 * kNB][kBP];  // factor of the stacked [diagonal tile; own tile]
+  } u;
+  double PN[2 * kNB][5];      // current 4-column panel
+  double zprev[kNB];          // z_{s-1}
+  double zrow[kNB];           // right-hand side of block s after the previous updates
+};
+
+// 16 x 16 FP64 MFMA accumulator blocks: acc[rb][cb][v] holds row lane/16 + 4v,
+// column lane%16 of block (rb, cb).
+typedef dbl4 Acc[2][4];
+
+// Trailing update of step s-1 on tile (i, l): V_il -= L_{i,s-1} L_{l,s-1}^T.
+__device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int s, int i, int l,
+                                              StepLds& L) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
+  const int wid = wave_id();
   const int wi = wid >> 1, wj = wid & 1;
+  const int k0 = (s - 1) * kNB;
+  double pv[16], qv[16], ov[2][2][4];
+  load_tile(V, N, i * kNB, k0, pv);
+  load_tile(V, N, l * kNB, k0, qv);
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = wi * 32 + p * 16 + (lane / 16) + 4 * v;
-        const int c = wj * 32 + q * 16 + (lane & 15);
-        tile[r][c] -= acc[p][q][v];
+        const int r = i * kNB + wi * 32 + p * 16 + (lane / 16) + 4 * v;
+        const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
+        ov[p][q][v] = V[(int64_t)min(r, N - 1) * N + min(c, N - 1)];
+      }
+  store_t(pv, L.u.st.P);
+  store_t(qv, L.u.st.Q);
+  __syncthreads();
+  dbl4 acc[2][2];
+  mfma_64(L.u.st.P, L.u.st.Q, acc);
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = i * kNB + wi * 32 + p * 16 + (lane / 16) + 4 * v;
+        const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
+        if (r < N && c < N && (i != l || c <= r)) V[(int64_t)r * N + c] = ov[p][q][v] - acc[p][q][v];
       }
 }
-
-struct StepLds {
-  double P[kNB][kBP];  // L_{s,s-1}, transposed
-  double Q[kNB][kBP];  // L_{s+p,s-1}, transposed
-  double D[kNB][kBP];  // diagonal tile
-  double B[kNB][kBP];  // own tile
-  double col[2][2 * kNB];
-  double piv[kNB];
-  double rs[kNB];
-  double zprev[kNB];
-};
 
 __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N, int T, int s,
                                                    const double* __restrict__ rhs, double alpha,
@@ -115,237 +180,365 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
   extern __shared__ double smem[];
   StepLds& L = *reinterpret_cast<StepLds*>(smem);
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = wave_id();
   const int npanel = T - s;
   const int s0 = s * kNB;
 
   if ((int)blockIdx.x >= npanel) {
-    // ---- trailing update of step s-1 on tiles (i, l), s+1 <= l <= i < T
     int ii, ll;
     tri_of((int)blockIdx.x - npanel, ii, ll);
-    const int i = s + 1 + ii, l = s + 1 + ll;
-    const int k0 = (s - 1) * kNB;
-    stage_t(V, N, i * kNB, k0, L.P);
-    stage_t(V, N, l * kNB, k0, L.Q);
-    __syncthreads();
-    dbl4 acc[2][2];
-    mfma_64(L.P, L.Q, acc);
-    const int lane = tid & (kWave - 1), wid = tid / kWave;
-    const int wi = wid >> 1, wj = wid & 1;
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = i * kNB + wi * 32 + p * 16 + (lane / 16) + 4 * v;
-          const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
-          if (r < N && c < N && (i != l || c <= r)) V[(int64_t)r * N + c] -= acc[p][q][v];
-        }
+    trailing_tile(V, N, s, s + 1 + ii, s + 1 + ll, L);
     return;
   }
 
-  // ---- panel workgroup p: row block s+p of column s
-  for (int e = tid; e < 4 * kNB; e += blockDim.x) (&L.col[0][0])[e] = 0.0;
+  // ---- panel workgroup p: row block s+p of column s.  The stacked matrix
+  // S = [diagonal tile; own tile] (128 x 64) lives in MFMA accumulators:
+  // wave w owns row blocks 2w, 2w+1 (rows 32w..32w+31 of S) x 4 column blocks.
+  // Waves 0, 1 hold the diagonal tile ("D"), waves 2, 3 the own tile ("B");
+  // of D only the blocks on or below the diagonal are kept up to date.
   const int p = blockIdx.x;
   const int b0 = (s + p) * kNB;
   const int nk = N - s0 < kNB ? N - s0 : kNB;  // width of column s
   const int nbr = p == 0 ? 0 : (N - b0 < kNB ? N - b0 : kNB);
+  const bool in_b = wid >= 2;
+  const bool live = !in_b || p > 0;
+  const bool fwd = rhs != nullptr && p == 0;  // wave 2 solves block s of L z = rhs
 
-  {
-    double vd[16], vb[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + q * 256;
-      const int r = e / kNB, c = e % kNB;
-      vd[q] = (r < nk && c <= r) ? V[(int64_t)(s0 + r) * N + s0 + c] : (r == c ? 1.0 : 0.0);
-      vb[q] = (p > 0 && r < nbr && c < nk) ? V[(int64_t)(b0 + r) * N + s0 + c] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + q * 256;
-      L.D[e / kNB][e % kNB] = vd[q];
-      L.B[e / kNB][e % kNB] = vb[q];
-    }
+  // ---- every global load first: previous-step factors, right-hand side, S
+  double pv[16], qv[16];
+  if (s > 0) {
+    load_tile(V, N, s0, s0 - kNB, pv);
+    if (p > 0) load_tile(V, N, b0, s0 - kNB, qv);
   }
+  double zp = 0.0, zc = 0.0;
   if (rhs && tid < kNB) {
     const int g = b0 + tid;
-    if (s == 0) {
-      if (g < N) z[g] = alpha * rhs[g];
-    } else {
-      L.zprev[tid] = z[s0 - kNB + tid];  // block s-1 is always full
-    }
+    if (s > 0) zp = z[s0 - kNB + tid];  // block s-1 is always full
+    const double r0 = s == 0 ? alpha * rhs[min(g, N - 1)] : z[min(g, N - 1)];
+    zc = g < N ? r0 : 0.0;
   }
-  if (s > 0) {
-    // previous step's rank-64 update of the diagonal tile and of the own tile
-    stage_t(V, N, s0, s0 - kNB, L.P);
-    if (p > 0) stage_t(V, N, b0, s0 - kNB, L.Q);
-    __syncthreads();
-    dbl4 acc[2][2];
-    mfma_64(L.P, L.P, acc);
-    sub_acc(L.D, acc);
-    if (p > 0) {
-      mfma_64(L.Q, L.P, acc);
-      sub_acc(L.B, acc);
-    }
-    if (rhs && tid < kNB && b0 + tid < N) {
-      // rhs block s+p loses L_{s+p,s-1} z_{s-1}
-      double(*Lp)[kBP] = p > 0 ? L.Q : L.P;
-      double t = 0.0;
-      for (int k = 0; k < kNB; ++k) t += Lp[k][tid] * L.zprev[k];
-      z[b0 + tid] -= t;
-    }
-  }
-  __syncthreads();
+  Acc acc;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int R = 32 * wid + 16 * rb + lane / 16 + 4 * v;
+        const int C = 16 * cb + (lane & 15);
+        double val = 0.0;
+        if (!in_b) {
+          if (cb <= 2 * wid + rb) {
+            // the diagonal tile: zero above the diagonal, identity padding
+            const double x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
+            val = ((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0);
+          }
+        } else if (p > 0) {
+          const int rr = R - kNB;
+          const double x = V[(int64_t)(b0 + min(rr, nbr - 1)) * N + s0 + min(C, nk - 1)];
+          val = ((rr < nbr) & (C < nk)) ? x : 0.0;
+        }
+        acc[rb][cb][v] = val;
+      }
 
-  // ---- elimination on registers: thread (tr, tc) owns rows 8tr..8tr+7 of
-  // the stacked [D; B] (128 rows) and columns 4tc..4tc+3
-  const int tr = tid / 16, tc = tid % 16;
-  const bool in_b = tr >= 8;
-  const bool live = !in_b || p > 0;
-  double a[8][4];
+  if (s > 0) {
+    // previous step's rank-64 update: S -= [L_{s,s-1}; L_{s+p,s-1}] L_{s,s-1}^T
+    store_t(pv, L.u.st.P);
+    if (p > 0) store_t(qv, L.u.st.Q);
+    if (rhs && tid < kNB) L.zprev[tid] = zp;
+    __syncthreads();
+    if (live) {
+      double(*Ls)[kBP] = in_b ? L.u.st.Q : L.u.st.P;
+      const int rbase = in_b ? 32 * wid - kNB : 32 * wid;
+#pragma unroll 4
+      for (int ks = 0; ks < kNB; ks += 4) {
+        const int kr = ks + lane / 16;
+        double a[2], b[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
+        for (int rb = 0; rb < 2; ++rb) a[rb] = -Ls[kr][rbase + 16 * rb + (lane & 15)];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int r = 8 * tr + q, col = 4 * tc + c;
-      a[q][c] = live ? (in_b ? L.B[r - kNB][col] : L.D[r][col]) : 0.0;
+        for (int cb = 0; cb < 4; ++cb) b[cb] = L.u.st.P[kr][16 * cb + (lane & 15)];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            if (in_b || cb <= 2 * wid + rb)
+              acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+      }
     }
-  // Four columns per iteration, so the column a thread publishes is a
-  // compile-time register index (a runtime pick serialises the LDS writes).
-  for (int j0 = 0; j0 < kNB; j0 += 4) {
-    const bool owner = (tc == (j0 >> 2)) && live;
+    if (rhs && tid < kNB) {
+      // rhs block s+p loses L_{s+p,s-1} z_{s-1} (wave 0, the lightest in the update)
+      double(*Lp)[kBP] = p > 0 ? L.u.st.Q : L.u.st.P;
+      double t = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < kNB; ++k) t = fma(Lp[k][tid], L.zprev[k], t);
+      zc -= t;
+    }
+    __syncthreads();  // P and Q are reused as LF below
+  }
+  if (rhs && tid < kNB) {
+    if (p > 0) {
+      if (b0 + tid < N) z[b0 + tid] = zc;
+    } else {
+      L.zrow[tid] = zc;
+    }
+  }
+  double zv = 0.0;  // wave 2 of the diagonal workgroup: residual rhs of row `lane` of block s
+  if (fwd) {
+    __syncthreads();
+    if (wid == 2) zv = L.zrow[lane];
+  }
+
+  // ---- elimination, four columns at a time.  Per panel: the owners write the
+  // four columns to PN; every thread factors the 4 x 4 pivot block itself and
+  // the first 128 threads solve their row of S against it into LF; then the
+  // rank-4 update of the accumulators right of the panel.  Rows of the
+  // diagonal tile above the pivot block get zeros in LF, so the strict upper
+  // triangle never feeds a later column.
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) {
-      const int j = j0 + c4;
-      double* cb = L.col[j & 1];
-      if (owner) {
+  for (int cbp = 0; cbp < 4; ++cbp) {
+    for (int sub = 0; sub < 16; sub += 4) {
+      const int j0 = 16 * cbp + sub;
+      const int cc = (lane & 15) - sub;
+      if (cc >= 0 && cc < 4) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cb[8 * tr + q] = a[q][c4];
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) L.PN[32 * wid + 16 * rb + lane / 16 + 4 * v][cc] = acc[rb][cbp][v];
       }
       __syncthreads();
-      const double pv = cb[j];
-      if (!(pv > 0.0)) {  // every thread reads the same pivot: a uniform exit
-        if (tid == 0 && p == 0) *info = s0 + j + 1;
-        return;
-      }
-      if (tid == 0) L.piv[j] = pv;
-      // Branch-free update of every column > j.  In the diagonal tile this
-      // also touches entries above the diagonal: they start at zero, stay
-      // finite, and are never read back (only columns j' >= j of rows > j
-      // feed later steps, and the write-back keeps the lower triangle).
-      const double inv = 1.0 / pv;
-      double ci[8], cl[4];
+      // 4 x 4 pivot block, factored redundantly by every thread (same bits everywhere)
+      double l[4][4], rl[4];
+      int bad = -1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) ci[q] = cb[8 * tr + q] * inv;
+      for (int k = 0; k < 4; ++k) {
+        double t = L.PN[j0 + k][k];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) cl[c] = (4 * tc + c > j) ? cb[4 * tc + c] : 0.0;
+        for (int q = 0; q < k; ++q) t = fma(-l[k][q], l[k][q], t);
+        if (!(t >= kMinPivot) && bad < 0) bad = k;
+        const double y = rsqrt_pos(t);
+        rl[k] = y;
+        l[k][k] = t * y;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+        for (int i = k + 1; i < 4; ++i) {
+          double u = L.PN[j0 + i][k];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a[q][c] = fma(-ci[q], cl[c], a[q][c]);
-    }
-  }
-  __syncthreads();
-  if (tid < kNB) L.rs[tid] = 1.0 / sqrt(L.piv[tid]);
-  __syncthreads();
-  // scale and write back: L_rc = a_rc / sqrt(d_c), L_cc = sqrt(d_c)
-  if (live) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int r = 8 * tr + q, col = 4 * tc + c;
-        if (in_b) {
-          const int rr = r - kNB;
-          if (rr < nbr && col < nk) V[(int64_t)(b0 + rr) * N + s0 + col] = a[q][c] * L.rs[col];
-        } else if (col <= r) {
-          const double v = col == r ? L.piv[col] * L.rs[col] : a[q][c] * L.rs[col];
-          L.D[r][col] = v;
-          if (p == 0 && r < nk) V[(int64_t)(s0 + r) * N + s0 + col] = v;
+          for (int q = 0; q < k; ++q) u = fma(-l[i][q], l[k][q], u);
+          l[i][k] = u * y;
         }
       }
-  }
-  if (p != 0 || !rhs) return;
-  __syncthreads();
-  // forward substitution of this block: L_ss z_s = (updated) rhs_s
-  if (tid < kWave) {
-    const int lane = tid;
-    double v = lane < nk ? z[s0 + lane] : 0.0;
-    for (int j = 0; j < nk; ++j) {
-      const double zj = readlane_d(v, j) * L.rs[j];
-      const double upd = fma(-L.D[lane][j], zj, v);
-      v = lane == j ? zj : (lane > j ? upd : v);
+      if (bad >= 0) {  // every thread saw the same pivots: a uniform exit
+        if (tid == 0 && p == 0) *info = s0 + j0 + bad + 1;
+        return;
+      }
+      if (tid < 2 * kNB) {
+        const int R = tid;
+        double x[4];
+        if (R >= kNB || R >= j0 + 4) {
+          // row below the pivot block: x L^T = a
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            double u = L.PN[R][k];
+#pragma unroll
+            for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
+            x[k] = u * rl[k];
+          }
+        } else {
+          // row of the pivot block (its L row) or above it (zeros)
+          const int r = R - j0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            double e = 0.0;
+#pragma unroll
+            for (int i = k; i < 4; ++i) e = r == i ? l[i][k] : e;
+            x[k] = e;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L.u.LF[R][j0 + k] = x[k];
+      }
+      double zz[4];
+      if (fwd && wid == 2) {
+        // z entries of the pivot rows: L_pivot zz = (residual rhs of rows j0..j0+3)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double u = readlane_d(zv, j0 + k);
+#pragma unroll
+          for (int q = 0; q < k; ++q) u = fma(-l[k][q], zz[q], u);
+          zz[k] = u * rl[k];
+        }
+      }
+      __syncthreads();
+      // rank-4 update of column blocks cbp..3: S -= L_panel L_panel(cols)^T
+      if (live) {
+        const int kr = j0 + lane / 16;
+        double a[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) a[rb] = -L.u.LF[32 * wid + 16 * rb + (lane & 15)][kr];
+#pragma unroll
+        for (int cb = cbp; cb < 4; ++cb) {
+          const double bv = L.u.LF[16 * cb + (lane & 15)][kr];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+            if (in_b || cb <= 2 * wid + rb)
+              acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, acc[rb][cb], 0, 0, 0);
+        }
+      }
+      if (fwd && wid == 2) {
+        // rows below the pivot rows lose L[row][j0..j0+3] zz; pivot rows take zz
+        const int rel = lane - j0;
+        if (rel >= 4) {
+          double u = zv;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) u = fma(-L.u.LF[lane][j0 + k], zz[k], u);
+          zv = u;
+        } else if (rel >= 0) {
+          double e = zz[0];
+#pragma unroll
+          for (int k = 1; k < 4; ++k) e = rel == k ? zz[k] : e;
+          zv = e;
+        }
+      }
     }
-    if (lane < nk) z[s0 + lane] = v;
   }
+  // ---- write back (LF is complete after the last panel's second barrier):
+  // the diagonal workgroup writes L_ss, the others their L_{s+p,s}
+  {
+    const int C = tid & (kNB - 1);
+    const int base = p == 0 ? 0 : kNB;
+    double wv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) wv[i] = L.u.LF[base + wid + 4 * i][C];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int R = wid + 4 * i;
+      const bool ok = p == 0 ? (R < nk && C <= R) : (R < nbr && C < nk);
+      if (ok) V[(int64_t)(b0 + R) * N + s0 + C] = wv[i];
+    }
+  }
+  if (fwd && wid == 2 && lane < nk) z[s0 + lane] = zv;
 }
 
-// Backward substitution L^T x = z by one workgroup (1024 threads).
+// Backward substitution L^T x = z by one workgroup of 1024 threads.  Blocks
+// of 64 rows from the last: the diagonal block is solved by wave 0 (one
+// readlane-broadcast step per row, operands read from LDS ahead of the
+// chain), then every row above loses the block's contribution.  The next
+// diagonal block and this block's row of L are loaded before the solve, so
+// their latency hides behind it.
+constexpr int kBackNT = 1024;
+constexpr int kBackPre = 4;  // (column, part) items per thread held in registers
+
 __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ Lm, int N,
                                                     const double* __restrict__ z,
                                                     double* __restrict__ x) {
   extern __shared__ double sm[];
   double* xs = sm;                                                          // N
   double(*Ld)[kBP] = reinterpret_cast<double(*)[kBP]>(sm + ((N + 1) & ~1));  // 64 x 65
-  double* rinv = sm + ((N + 1) & ~1) + kNB * kBP;                           // 64
-  for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = z[i];
+  const int tid = threadIdx.x;
+  const int wid = wave_id();
+  const int lane = tid & (kWave - 1);
+  for (int i = tid; i < N; i += kBackNT) xs[i] = z[i];
   const int T = (N + kNB - 1) / kNB;
+
+  // diagonal block of row block s, four entries per thread (row e/64, col e%64)
+  auto load_diag = [&](int s, double (&d)[4]) {
+    const int s0 = s * kNB;
+    const int nk = N - s0 < kNB ? N - s0 : kNB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * kBackNT;
+      const int r = e / kNB, c = e % kNB;
+      const double v = Lm[(int64_t)(s0 + min(r, nk - 1)) * N + s0 + min(c, nk - 1)];
+      d[q] = ((r < nk) & (c <= r)) ? v : 0.0;
+    }
+  };
+  double dnext[4];
+  load_diag(T - 1, dnext);
   for (int s = T - 1; s >= 0; --s) {
     const int s0 = s * kNB;
     const int nk = N - s0 < kNB ? N - s0 : kNB;
-    __syncthreads();
-    {
-      double v[4];
+    // this block's row of L left of the diagonal: item (i, part) covers
+    // L[s0 + 8 part + q][i], q < 8, for column i < s0
+    const int items = s0 * 8;
+    double lv[kBackPre][8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + q * 1024;
-        const int r = e / kNB, c = e % kNB;
-        v[q] = (r < nk && c <= r) ? Lm[(int64_t)(s0 + r) * N + s0 + c] : 0.0;
-      }
+    for (int j = 0; j < kBackPre; ++j) {
+      const int idx = tid + j * kBackNT;
+      const int i = min(idx >> 3, s0 > 0 ? s0 - 1 : 0), part = idx & 7;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + q * 1024;
-        Ld[e / kNB][e % kNB] = v[q];
+      for (int q = 0; q < 8; ++q) {
+        const int b = 8 * part + q;
+        const double v = Lm[(int64_t)(s0 + min(b, nk - 1)) * N + i];
+        lv[j][q] = ((idx < items) & (b < nk)) ? v : 0.0;
       }
     }
+    double dcur[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dcur[q] = dnext[q];
+    if (s > 0) load_diag(s - 1, dnext);
+    __syncthreads();  // xs complete from the previous block; Ld free
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * kBackNT;
+      Ld[e / kNB][e % kNB] = dcur[q];
+    }
     __syncthreads();
-    if (threadIdx.x < kNB) rinv[threadIdx.x] = threadIdx.x < nk ? 1.0 / Ld[threadIdx.x][threadIdx.x] : 0.0;
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-      const int lane = threadIdx.x;
+    if (wid == 0) {
+      const double dg = Ld[lane][lane];
+      const double rinv = lane < nk ? rcp_nr(dg) : 0.0;
       double v = lane < nk ? xs[s0 + lane] : 0.0;
-      for (int b = nk - 1; b >= 0; --b) {
-        const double xb = readlane_d(v, b) * rinv[b];
-        const double upd = fma(-Ld[b][lane], xb, v);
-        v = lane == b ? xb : (lane < b ? upd : v);
+#pragma unroll
+      for (int b8 = kNB - 8; b8 >= 0; b8 -= 8) {
+        double col[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) col[q] = Ld[b8 + q][lane];
+#pragma unroll
+        for (int q = 7; q >= 0; --q) {
+          const int b = b8 + q;
+          const double xb = readlane_d(v, b) * readlane_d(rinv, b);
+          const double upd = fma(-col[q], xb, v);
+          v = lane == b ? xb : (lane < b ? upd : v);
+        }
       }
       if (lane < nk) xs[s0 + lane] = v;
     }
     __syncthreads();
-    // entries above the block: x_i -= sum_b L[s0+b][i] x_{s0+b}.  Eight
-    // threads share a column i (rows b = 8*part .. 8*part+7 < nk, loads
-    // issued together) and combine with lane shuffles; a group of eight
-    // lanes enters and leaves the loop together.
-    for (int idx = threadIdx.x; idx < s0 * 8; idx += blockDim.x) {
+    // entries above the block: x_i -= sum_b L[s0+b][i] x_{s0+b}; eight
+    // threads share a column and combine with lane permutations
+    double xb[8];
+#pragma unroll
+    for (int j = 0; j < kBackPre; ++j) {
+      const int idx = tid + j * kBackNT;
+      if (j * kBackNT >= items) break;  // uniform
+      const int part = idx & 7;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xb[q] = xs[s0 + 8 * part + q];
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t = fma(lv[j][q], xb[q], t);
+      t = group8_sum(t);
+      if (part == 0 && idx < items) xs[idx >> 3] -= t;
+    }
+    // columns beyond what the registers held (N > 512 only)
+    for (int idx = tid + kBackPre * kBackNT; idx < items; idx += kBackNT) {
       const int i = idx >> 3, part = idx & 7;
-      double lv[8];
+      double lw[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int b = 8 * part + q;
-        lv[q] = b < nk ? Lm[(int64_t)(s0 + b) * N + i] : 0.0;
+        const double v = Lm[(int64_t)(s0 + min(b, nk - 1)) * N + i];
+        lw[q] = b < nk ? v : 0.0;
       }
       double t = 0.0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int b = 8 * part + q;
-        if (b < nk) t += lv[q] * xs[s0 + b];
-      }
+      for (int q = 0; q < 8; ++q) t = fma(lw[q], xs[s0 + 8 * part + q], t);
       t = group8_sum(t);
       if (part == 0) xs[i] -= t;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = xs[i];
+  for (int i = tid; i < N; i += kBackNT) x[i] = xs[i];
 }
 
 __global__ void k_zero_upper(double* __restrict__ V, int N) {
@@ -358,7 +551,7 @@ __global__ void k_zero_upper(double* __restrict__ V, int N) {
 }
 
 // ---------------------------------------------------------------- launchers
-static size_t back_lds(int N) { return sizeof(double) * ((size_t)((N + 1) & ~1) + kNB * kBP + kNB); }
+static size_t back_lds(int N) { return sizeof(double) * ((size_t)((N + 1) & ~1) + kNB * kBP); }
 
 hipError_t chol_init() {
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_step,
@@ -381,7 +574,7 @@ hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, 
     if (e != hipSuccess) return e;
   }
   if (!rhs) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_back, dim3(1), dim3(1024), back_lds(N), st, V, N, z, x);
+  hipLaunchKernelGGL(k_chol_back, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, z, x);
   return hipGetLastError();
 }
 

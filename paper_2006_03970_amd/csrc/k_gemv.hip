@@ -33,7 +33,10 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
   for (int it = 0; it < ITERS; ++it) {
     const int r0 = (it * kWave + lane) * VN;
 #pragma unroll
-    for (int q = 0; q < VN; ++q) vr[it][q] = (r0 + q < m) ? (ACC)v[r0 + q] : (ACC)0;
+    for (int q = 0; q < VN; ++q) {
+      const ACC x = (ACC)v[r0 + q < m ? r0 + q : m - 1];
+      vr[it][q] = (r0 + q < m) ? x : (ACC)0;
+    }
   }
 
   const int64_t c0 = (int64_t)blockIdx.x * cpb;
@@ -44,18 +47,15 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
     ACC e[COLS][ITERS][VN];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
+      // loads are unconditional (clamped column and row start) and masked
+      // below: a guarded load would be compiled into a branch that waits for
+      // it, serialising the COLS x ITERS loads of the lane
       const int64_t j = cb + c;
-      const bool ok = j < c1;
-      const T* a = A + (ok ? j : 0) * lda;
+      const T* a = A + (j < c1 ? j : c0) * lda;
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         const int r0 = (it * kWave + lane) * VN;
-        if (ok && r0 < m) {
-          load16<ACC>(a + r0, e[c][it]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < VN; ++q) e[c][it][q] = (ACC)0;
-        }
+        load16<ACC>(a + (r0 < m ? r0 : 0), e[c][it]);
       }
     }
 #pragma unroll
@@ -76,10 +76,11 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
 #pragma unroll
         for (int q = 0; q < VN; ++q) acc += e[c][it][q] * vr[it][q];
       if (COLSQ) {
+        const bool ok = cb + c < c1;
 #pragma unroll
         for (int it = 0; it < ITERS; ++it)
 #pragma unroll
-          for (int q = 0; q < VN; ++q) sq += (double)e[c][it][q] * (double)e[c][it][q];
+          for (int q = 0; q < VN; ++q) sq += ok ? (double)e[c][it][q] * (double)e[c][it][q] : 0.0;
       }
       const double s = (double)wave_sum(acc);
       if (lane == 0 && cb + c < c1) w[cb + c] = s;

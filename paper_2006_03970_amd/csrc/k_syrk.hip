@@ -62,22 +62,24 @@ __device__ __forceinline__ void fetch(const T* __restrict__ A, int64_t lda, int 
     const int a0 = (t % 8) * 8;     // 8 consecutive rows
     const int64_t k = k0 + kk;
     const bool kok = k < K;
-    const T* col = A + (kok ? (int64_t)J[k] : 0) * lda;
+    const T* col = A + (int64_t)J[kok ? k : K - 1] * lda;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int a = row0 + a0 + q;
-      v[q] = (kok && a < N) ? load1<C>(col + a) : (C)0;
+      const C x = load1<C>(col + (a < N ? a : N - 1));
+      v[q] = (kok & (a < N)) ? x : (C)0;
     }
   } else {
     const int aa = t / 4;           // 64 gathered columns
     const int kq = (t % 4) * 8;     // 8 consecutive rows of that column
     const int a = row0 + aa;
     const bool aok = a < N;
-    const T* col = A + (aok ? (int64_t)J[a] : 0) * lda;
+    const T* col = A + (int64_t)J[aok ? a : N - 1] * lda;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t k = k0 + kq + q;
-      v[q] = (aok && k < K) ? load1<C>(col + k) : (C)0;
+      const C x = load1<C>(col + (k < K ? k : K - 1));
+      v[q] = (aok & (k < K)) ? x : (C)0;
     }
   }
 }

@@ -15,7 +15,13 @@ constexpr int kChunk = kNT * kEPT;
 
 int prox_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
-__device__ __forceinline__ bool active(double t, double thr) { return t > thr || t < -thr; }
+__device__ __forceinline__ bool active(double t, double thr) { return (t > thr) | (t < -thr); }
+
+// Element loads below read at a clamped, always valid index and mask the
+// value afterwards.  A load guarded by `if (i < n)`, or selected by a
+// short-circuit condition, is compiled into a branch that waits for the load
+// before the join, which serialises the loads of a thread.
+__device__ __forceinline__ int64_t clampi(int64_t i, int64_t n) { return i < n ? i : n - 1; }
 
 // ------------------------------------------------------------------ finishers
 // Reductions that span blocks finish in a second, single-block kernel: the
@@ -46,20 +52,27 @@ __global__ __launch_bounds__(kNT) void k_count(const double* __restrict__ x, dou
   const double s = UPDATE ? *s_dev : 0.0;
   int cnt = 0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double xv[kEPT], wv[kEPT], dv[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t ic = clampi(base + k * kNT + threadIdx.x, n);
+    xv[k] = x[ic];
+    if (!SUPPORT) wv[k] = w[ic];
+    if (UPDATE) dv[k] = wd[ic];
+  }
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int64_t i = base + k * kNT + threadIdx.x;
-    if (i < n) {
-      if (SUPPORT) {
-        cnt += (x[i] != 0.0);
-      } else {
-        double wi = w[i];
-        if (UPDATE) {
-          wi = fma(s, wd[i], wi);  // w_y += s * w_d
-          w[i] = wi;
-        }
-        cnt += active(fma(-sigma, wi, x[i]), thr);
+    const bool in = i < n;
+    if (SUPPORT) {
+      cnt += in & (xv[k] != 0.0);
+    } else {
+      double wi = wv[k];
+      if (UPDATE) {
+        wi = fma(s, dv[k], wi);  // w_y += s * w_d
+        if (in) w[i] = wi;
       }
+      cnt += in & active(fma(-sigma, wi, xv[k]), thr);
     }
   }
   __shared__ int red[kNT / kWave];
@@ -82,19 +95,17 @@ __global__ __launch_bounds__(kNT) void k_write(const double* __restrict__ x,
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double tv[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const int64_t ic = clampi(base + k * kNT + threadIdx.x, n);
+    tv[k] = SUPPORT ? x[ic] : fma(-sigma, w[ic], x[ic]);
+  }
+#pragma unroll
   for (int k = 0; k < kEPT; ++k) {
     const int64_t i = base + k * kNT + threadIdx.x;
-    double t = 0.0;
-    bool act = false;
-    if (i < n) {
-      if (SUPPORT) {
-        t = x[i];
-        act = (t != 0.0);
-      } else {
-        t = fma(-sigma, w[i], x[i]);
-        act = active(t, thr);
-      }
-    }
+    const double t = tv[k];
+    const bool act = (i < n) & (SUPPORT ? (t != 0.0) : active(t, thr));
     const unsigned long long mask = __ballot(act);
     const int pre = __popcll(mask & ((1ull << lane) - 1ull));
     __syncthreads();
@@ -197,12 +208,14 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
   for (int64_t kb = k0; kb < k1; kb += 16) {
     int64_t col[16];
     double cv[16];
+    bool ok[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int64_t k = kb + u;
-      const bool ok = k < k1;
-      col[u] = ok ? (int64_t)J[k] * lda : -1;
-      cv[u] = ok ? c[k] : 0.0;
+      ok[u] = k < k1;
+      const int64_t kc = ok[u] ? k : k1 - 1;  // past the chunk: a valid column, weight 0
+      col[u] = (int64_t)J[kc] * lda;
+      cv[u] = c[kc];
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -210,9 +223,9 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
       if (row < m) {
         double v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = col[u] >= 0 ? load1<double>(A + col[u] + row) : 0.0;
+        for (int u = 0; u < 16; ++u) v[u] = load1<double>(A + col[u] + row);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[q] += v[u] * cv[u];
+        for (int u = 0; u < 16; ++u) acc[q] += ok[u] ? v[u] * cv[u] : 0.0;
       }
     }
   }
@@ -485,22 +498,25 @@ __global__ __launch_bounds__(kNT) void k_outer(double* __restrict__ x, const dou
                                                 double* __restrict__ part) {
   double xu = 0.0, zz = 0.0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double xv[kEPT], wv[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {
+    const int64_t ic = clampi(base + q * kNT + threadIdx.x, n);
+    xv[q] = x[ic];
+    wv[q] = w[ic];
+  }
 #pragma unroll
   for (int q = 0; q < kEPT; ++q) {
     const int64_t i = base + q * kNT + threadIdx.x;
-    if (i < n) {
-      const double xi = x[i];
-      const double t = fma(-sigma, w[i], xi);
-      const double u = prox_en(t, thr, den);
-      double z;
-      if (t >= thr) z = (t * l2 + l1) / den;
-      else if (t <= -thr) z = (t * l2 - l1) / den;
-      else z = t / sigma;
-      const double e = xi - u;
-      xu += e * e;
-      zz += z * z;
-      x[i] = u;
-    }
+    const double xi = xv[q];
+    const double t = fma(-sigma, wv[q], xi);
+    const double u = prox_en(t, thr, den);
+    const double z = t >= thr ? (t * l2 + l1) / den : (t <= -thr ? (t * l2 - l1) / den : t / sigma);
+    const double e = xi - u;
+    const bool in = i < n;
+    xu += in ? e * e : 0.0;
+    zz += in ? z * z : 0.0;
+    if (in) x[i] = u;
   }
   __shared__ double red[kNT / kWave];
   const double s1 = block_sum<kNT>(xu, red);
@@ -532,19 +548,24 @@ __global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
                                               double den1, double* __restrict__ part) {
   double se = 0.0, sxx = 0.0, sx1 = 0.0, sps = 0.0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double xv[kEPT], qv[kEPT];
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) {
-    const int64_t i = base + k * kNT + threadIdx.x;
-    if (i < n) {
-      const double xi = x[i], qi = q[i];
-      const double p = prox_en(xi - qi, l1, den1);
-      const double e = xi - p;
-      se += e * e;
-      sxx += xi * xi;
-      sx1 += fabs(xi);
-      const double a = fabs(qi) - l1;
-      if (a > 0.0) sps += a * a;
-    }
+    const int64_t ic = clampi(base + k * kNT + threadIdx.x, n);
+    xv[k] = x[ic];
+    qv[k] = q[ic];
+  }
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const bool in = base + k * kNT + threadIdx.x < n;
+    const double xi = in ? xv[k] : 0.0, qi = in ? qv[k] : 0.0;
+    const double p = prox_en(xi - qi, l1, den1);
+    const double e = xi - p;
+    se += e * e;
+    sxx += xi * xi;
+    sx1 += fabs(xi);
+    const double a = fabs(qi) - l1;
+    sps += a > 0.0 ? a * a : 0.0;
   }
   __shared__ double red[kNT / kWave];
   const double r0 = block_sum<kNT>(se, red);
@@ -604,11 +625,11 @@ __global__ __launch_bounds__(kNT) void k_nonfinite(const double* __restrict__ v,
                                                     double* __restrict__ part) {
   int c = 0;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double vv[kEPT];
 #pragma unroll
-  for (int k = 0; k < kEPT; ++k) {
-    const int64_t i = base + k * kNT + threadIdx.x;
-    if (i < n && !isfinite(v[i])) ++c;
-  }
+  for (int k = 0; k < kEPT; ++k) vv[k] = v[clampi(base + k * kNT + threadIdx.x, n)];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) c += (base + k * kNT + threadIdx.x < n) & !isfinite(vv[k]);
   __shared__ int red[kNT / kWave];
   const int t = block_sum<kNT>(c, red);
   if (threadIdx.x == 0) part[blockIdx.x] = (double)t;
