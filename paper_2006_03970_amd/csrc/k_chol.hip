@@ -71,17 +71,25 @@ __device__ __forceinline__ void tri_of(int t, int& i, int& j) {
 }
 
 // Load the 64 x 64 block of V at rows i0.., cols k0.. (256 threads, 16 each;
-// thread t holds entry e = t + 256q as (e / 64, e % 64)); zero outside the
-// matrix.  Addresses are clamped into the matrix, so every load is issued
-// unconditionally and all 16 are in flight together.
+// thread t holds entry e = t + 256q as (e / 64, e % 64)).  Addresses are
+// clamped into the matrix, so every load is issued unconditionally; entries
+// outside the matrix are zeroed by mask_tile once every load of the phase is
+// in flight (a select right after its load would wait for it).
 __device__ __forceinline__ void load_tile(const double* __restrict__ V, int N, int i0, int k0,
                                           double (&v)[16]) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + q * 256;
     const int i = i0 + e / kNB, k = k0 + e % kNB;
-    const double x = V[(int64_t)min(i, N - 1) * N + min(k, N - 1)];
-    v[q] = ((i < N) & (k < N)) ? x : 0.0;
+    v[q] = V[(int64_t)min(i, N - 1) * N + min(k, N - 1)];
+  }
+}
+__device__ __forceinline__ void mask_tile(int N, int i0, int k0, double (&v)[16]) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + q * 256;
+    const int i = i0 + e / kNB, k = k0 + e % kNB;
+    v[q] = ((i < N) & (k < N)) ? v[q] : 0.0;
   }
 }
 // Store a block loaded by load_tile transposed: dst[k][i].
@@ -157,6 +165,9 @@ __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int
         const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
         ov[p][q][v] = V[(int64_t)min(r, N - 1) * N + min(c, N - 1)];
       }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
+  mask_tile(N, i * kNB, k0, pv);
+  mask_tile(N, l * kNB, k0, qv);
   store_t(pv, L.u.st.P);
   store_t(qv, L.u.st.Q);
   __syncthreads();
@@ -227,25 +238,38 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
       for (int v = 0; v < 4; ++v) {
         const int R = 32 * wid + 16 * rb + lane / 16 + 4 * v;
         const int C = 16 * cb + (lane & 15);
-        double val = 0.0;
+        double x = 0.0;
         if (!in_b) {
-          if (cb <= 2 * wid + rb) {
-            // the diagonal tile: zero above the diagonal, identity padding
-            const double x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
-            val = ((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0);
-          }
+          if (cb <= 2 * wid + rb) x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
         } else if (p > 0) {
-          const int rr = R - kNB;
-          const double x = V[(int64_t)(b0 + min(rr, nbr - 1)) * N + s0 + min(C, nk - 1)];
-          val = ((rr < nbr) & (C < nk)) ? x : 0.0;
+          x = V[(int64_t)(b0 + min(R - kNB, nbr - 1)) * N + s0 + min(C, nk - 1)];
         }
-        acc[rb][cb][v] = val;
+        acc[rb][cb][v] = x;
+      }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
+  // the diagonal tile keeps its lower triangle and gets identity padding; the
+  // own tile is zero outside the matrix
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int R = 32 * wid + 16 * rb + lane / 16 + 4 * v;
+        const int C = 16 * cb + (lane & 15);
+        const double x = acc[rb][cb][v];
+        acc[rb][cb][v] = !in_b ? (((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0))
+                               : (((R - kNB < nbr) & (C < nk)) ? x : 0.0);
       }
 
   if (s > 0) {
     // previous step's rank-64 update: S -= [L_{s,s-1}; L_{s+p,s-1}] L_{s,s-1}^T
+    mask_tile(N, s0, s0 - kNB, pv);
     store_t(pv, L.u.st.P);
-    if (p > 0) store_t(qv, L.u.st.Q);
+    if (p > 0) {
+      mask_tile(N, b0, s0 - kNB, qv);
+      store_t(qv, L.u.st.Q);
+    }
     if (rhs && tid < kNB) L.zprev[tid] = zp;
     __syncthreads();
     if (live) {
@@ -420,28 +444,31 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
   if (fwd && wid == 2 && lane < nk) z[s0 + lane] = zv;
 }
 
-// Backward substitution L^T x = z by one workgroup of 1024 threads.  Blocks
-// of 64 rows from the last: the diagonal block is solved by wave 0 (one
-// readlane-broadcast step per row, operands read from LDS ahead of the
-// chain), then every row above loses the block's contribution.  The next
-// diagonal block and this block's row of L are loaded before the solve, so
-// their latency hides behind it.
+// Backward substitution L^T x = z by one workgroup of 1024 threads, left-
+// looking by blocks of 64 rows from the last: block s needs
+// c_s = sum_{r below} L[r][s0 + j] x_r (lanes = the 64 columns j, the 16
+// waves take interleaved rows, so every load reads whole rows of L), then
+// wave 0 solves L_ss^T x_s = z_s - c_s four rows at a time.  Block s-1's rows
+// and diagonal block are loaded while block s is solved.
 constexpr int kBackNT = 1024;
-constexpr int kBackPre = 4;  // (column, part) items per thread held in registers
+constexpr int kBackWaves = kBackNT / kWave;
+constexpr int kBackPre = 24;  // rows per wave held in registers (all of them while N <= 448)
 
 __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ Lm, int N,
                                                     const double* __restrict__ z,
                                                     double* __restrict__ x) {
   extern __shared__ double sm[];
-  double* xs = sm;                                                          // N
-  double(*Ld)[kBP] = reinterpret_cast<double(*)[kBP]>(sm + ((N + 1) & ~1));  // 64 x 65
+  const int xsz = (N + 1) & ~1;
+  double* xs = sm;                                                   // N
+  double(*Ld)[kBP] = reinterpret_cast<double(*)[kBP]>(sm + xsz);      // 64 x 65
+  double(*cp)[kNB] = reinterpret_cast<double(*)[kNB]>(sm + xsz + kNB * kBP);  // 16 x 64
   const int tid = threadIdx.x;
   const int wid = wave_id();
   const int lane = tid & (kWave - 1);
   for (int i = tid; i < N; i += kBackNT) xs[i] = z[i];
   const int T = (N + kNB - 1) / kNB;
 
-  // diagonal block of row block s, four entries per thread (row e/64, col e%64)
+  // diagonal block of block s, four entries per thread (row e/64, col e%64)
   auto load_diag = [&](int s, double (&d)[4]) {
     const int s0 = s * kNB;
     const int nk = N - s0 < kNB ? N - s0 : kNB;
@@ -449,92 +476,83 @@ __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ L
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * kBackNT;
       const int r = e / kNB, c = e % kNB;
-      const double v = Lm[(int64_t)(s0 + min(r, nk - 1)) * N + s0 + min(c, nk - 1)];
-      d[q] = ((r < nk) & (c <= r)) ? v : 0.0;
+      d[q] = Lm[(int64_t)(s0 + min(r, nk - 1)) * N + s0 + min(c, nk - 1)];
     }
   };
-  double dnext[4];
-  load_diag(T - 1, dnext);
+    // rows s0+64+wid+16i of block column s, column s0+lane (rows past N read
+  // row N-1 and are given weight 0 where they are used)
+  auto load_below = [&](int s, double (&b)[kBackPre]) {
+    const int s0 = s * kNB;
+    const int c = min(s0 + lane, N - 1);
+#pragma unroll
+    for (int i = 0; i < kBackPre; ++i) {
+      const int r = s0 + kNB + wid + kBackWaves * i;
+      b[i] = Lm[(int64_t)min(r, N - 1) * N + c];
+    }
+  };
+  double dv[4], bv[kBackPre];
+  load_diag(T - 1, dv);
+  load_below(T - 1, bv);
   for (int s = T - 1; s >= 0; --s) {
     const int s0 = s * kNB;
     const int nk = N - s0 < kNB ? N - s0 : kNB;
-    // this block's row of L left of the diagonal: item (i, part) covers
-    // L[s0 + 8 part + q][i], q < 8, for column i < s0
-    const int items = s0 * 8;
-    double lv[kBackPre][8];
+    __syncthreads();  // x of every block below is in xs; Ld and cp are free
+    // c_s, partial over this wave's rows (x_r for rows past N is multiplied by 0)
+    {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < kBackPre; ++j) {
-      const int idx = tid + j * kBackNT;
-      const int i = min(idx >> 3, s0 > 0 ? s0 - 1 : 0), part = idx & 7;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int b = 8 * part + q;
-        const double v = Lm[(int64_t)(s0 + min(b, nk - 1)) * N + i];
-        lv[j][q] = ((idx < items) & (b < nk)) ? v : 0.0;
+      for (int i = 0; i < kBackPre; ++i) {
+        const int r = s0 + kNB + wid + kBackWaves * i;
+        const double xr = xs[min(r, N - 1)];
+        t[i & 3] = fma(bv[i], r < N ? xr : 0.0, t[i & 3]);
       }
+      for (int r = s0 + kNB + wid + kBackWaves * kBackPre; r < N; r += kBackWaves)
+        t[0] = fma(Lm[(int64_t)r * N + s0 + lane], xs[r], t[0]);
+      cp[wid][lane] = (t[0] + t[1]) + (t[2] + t[3]);
     }
     double dcur[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dcur[q] = dnext[q];
-    if (s > 0) load_diag(s - 1, dnext);
-    __syncthreads();  // xs complete from the previous block; Ld free
+    for (int q = 0; q < 4; ++q) dcur[q] = dv[q];
+    if (s > 0) {
+      load_diag(s - 1, dv);
+      load_below(s - 1, bv);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * kBackNT;
-      Ld[e / kNB][e % kNB] = dcur[q];
+      const int r = e / kNB, c = e % kNB;
+      Ld[r][c] = ((r < nk) & (c <= r)) ? dcur[q] : 0.0;
     }
     __syncthreads();
     if (wid == 0) {
-      const double dg = Ld[lane][lane];
-      const double rinv = lane < nk ? rcp_nr(dg) : 0.0;
-      double v = lane < nk ? xs[s0 + lane] : 0.0;
+      double c = 0.0;
 #pragma unroll
-      for (int b8 = kNB - 8; b8 >= 0; b8 -= 8) {
-        double col[8];
+      for (int w = 0; w < kBackWaves; ++w) c += cp[w][lane];
+      double v = lane < nk ? xs[s0 + lane] - c : 0.0;
+      const double rinv = lane < nk ? rcp_nr(Ld[lane][lane]) : 0.0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) col[q] = Ld[b8 + q][lane];
+      for (int b4 = kNB - 4; b4 >= 0; b4 -= 4) {
+        double col[4];
 #pragma unroll
-        for (int q = 7; q >= 0; --q) {
-          const int b = b8 + q;
-          const double xb = readlane_d(v, b) * readlane_d(rinv, b);
-          const double upd = fma(-col[q], xb, v);
-          v = lane == b ? xb : (lane < b ? upd : v);
+        for (int k = 0; k < 4; ++k) col[k] = Ld[b4 + k][lane];
+        double xx[4];
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+          double u = readlane_d(v, b4 + k);
+#pragma unroll
+          for (int q = k + 1; q < 4; ++q) u = fma(-Ld[b4 + q][b4 + k], xx[q], u);
+          xx[k] = u * readlane_d(rinv, b4 + k);
         }
+        const int rel = lane - b4;
+        double upd = v;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) upd = fma(-col[k], xx[k], upd);
+        double own = xx[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) own = rel == k ? xx[k] : own;
+        v = rel < 0 ? upd : (rel < 4 ? own : v);
       }
       if (lane < nk) xs[s0 + lane] = v;
-    }
-    __syncthreads();
-    // entries above the block: x_i -= sum_b L[s0+b][i] x_{s0+b}; eight
-    // threads share a column and combine with lane permutations
-    double xb[8];
-#pragma unroll
-    for (int j = 0; j < kBackPre; ++j) {
-      const int idx = tid + j * kBackNT;
-      if (j * kBackNT >= items) break;  // uniform
-      const int part = idx & 7;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) xb[q] = xs[s0 + 8 * part + q];
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t = fma(lv[j][q], xb[q], t);
-      t = group8_sum(t);
-      if (part == 0 && idx < items) xs[idx >> 3] -= t;
-    }
-    // columns beyond what the registers held (N > 512 only)
-    for (int idx = tid + kBackPre * kBackNT; idx < items; idx += kBackNT) {
-      const int i = idx >> 3, part = idx & 7;
-      double lw[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int b = 8 * part + q;
-        const double v = Lm[(int64_t)(s0 + min(b, nk - 1)) * N + i];
-        lw[q] = b < nk ? v : 0.0;
-      }
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t = fma(lw[q], xs[s0 + 8 * part + q], t);
-      t = group8_sum(t);
-      if (part == 0) xs[i] -= t;
     }
   }
   __syncthreads();
@@ -551,7 +569,9 @@ __global__ void k_zero_upper(double* __restrict__ V, int N) {
 }
 
 // ---------------------------------------------------------------- launchers
-static size_t back_lds(int N) { return sizeof(double) * ((size_t)((N + 1) & ~1) + kNB * kBP); }
+static size_t back_lds(int N) {
+  return sizeof(double) * ((size_t)((N + 1) & ~1) + kNB * kBP + kBackWaves * kNB);
+}
 
 hipError_t chol_init() {
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_step,

@@ -343,6 +343,15 @@ hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host
 // inactive for every trial step contributes nothing and is skipped; one that
 // stays active on its side for every step contributes s^2 times a common sum.
 constexpr int kLsSlots = kMaxTrials + 1;  // 32 trial sums + the common second-order sum
+// One feature per thread (grid-stride past kLsMaxBlocks blocks): only features
+// near the threshold run the trial loop, so spreading them over many waves
+// keeps that loop off a few SIMDs.
+constexpr int kLsMaxBlocks = 1024;
+int ls_blocks(int64_t n) {
+  const int64_t nb = (n + kNT - 1) / kNT;
+  return (int)(nb < kLsMaxBlocks ? nb : kLsMaxBlocks);
+}
+size_t ls_part_doubles(int64_t n) { return (size_t)ls_blocks(n) * kLsSlots; }
 
 __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x,
                                                      const double* __restrict__ w,
@@ -356,36 +365,24 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
   for (int k = 0; k < kMaxTrials; ++k) e[k] = 0.0;
   double e2 = 0.0;
   const double smax = la.s[0];
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  double xv[kEPT], wv[kEPT], dv[kEPT];
-#pragma unroll
-  for (int q = 0; q < kEPT; ++q) {  // issue every load first
-    const int64_t i = base + q * kNT + threadIdx.x;
-    const bool ok = i < n;
-    xv[q] = ok ? x[i] : 0.0;
-    wv[q] = ok ? w[i] : 0.0;
-    dv[q] = ok ? wd[i] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < kEPT; ++q) {
-    const int64_t i = base + q * kNT + threadIdx.x;
-    if (i >= n) continue;
-    const double t0 = fma(-sigma, wv[q], xv[q]);
-    const double wi = dv[q];
+  const double rden = 1.0 / den, h = den / (2.0 * sigma);
+  for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+    const double t0 = fma(-sigma, w[i], x[i]);
+    const double wi = wd[i];
     const double a0 = fabs(t0);
     const double reach = smax * sigma * fabs(wi) * (1.0 + 1e-12);
     if (a0 + reach < thr) continue;  // inactive for every trial step
-    if ((t0 > thr && t0 - reach > thr) || (t0 < -thr && t0 + reach < -thr)) {
+    if (((t0 > thr) & (t0 - reach > thr)) | ((t0 < -thr) & (t0 + reach < -thr))) {
       e2 += 0.5 * kappa * wi * wi;  // same active side for every trial step
       continue;
     }
     const double u0 = prox_en(t0, thr, den);
-    const double rden = 1.0 / den, h = den / (2.0 * sigma), hk = 0.5 * kappa * wi * wi;
+    const double hk = 0.5 * kappa * wi * wi;
 #pragma unroll
     for (int k = 0; k < kMaxTrials; ++k) {
       const double s = la.s[k];
       const double t1 = fma(-(s * sigma), wi, t0);
-      const bool same = (t0 > thr && t1 > thr) || (t0 < -thr && t1 < -thr);
+      const bool same = ((t0 > thr) & (t1 > thr)) | ((t0 < -thr) & (t1 < -thr));
       const double num = t1 > thr ? t1 - thr : (t1 < -thr ? t1 + thr : 0.0);
       const double u1 = num * rden;
       const double other = h * (u1 * u1 - u0 * u0) + s * wi * u0;
@@ -413,77 +410,123 @@ __global__ __launch_bounds__(kNT) void k_linesearch(const double* __restrict__ x
   }
 }
 
-// Trial selection (one block): Delta_k from the partial sums, the first k
-// with Delta_k <= mu s_k g^T d, y += s d.  With select == 0 only the
-// increments are produced (for the caller's g^T d and |d|^2).
-__global__ __launch_bounds__(kNT) void k_ls_select(const double* __restrict__ part, int nb, LsArgs la,
-                                                   const double* __restrict__ g,
-                                                   const double* __restrict__ d,
-                                                   double* __restrict__ y, int m,
-                                                   double* __restrict__ scal, int select,
-                                                   double gd_in, double dd_in) {
+// Trial selection (one block of 576 threads): the 33 sums over the partial
+// rows (16 lanes per sum, rows b = j mod 16, loads issued 16 at a time, then
+// a 16-lane DPP sum, all in a fixed order), Delta_k, the first k with
+// Delta_k <= mu s_k g^T d, y += s d.  With select == 0 only the increments
+// are produced (for the caller's g^T d and |d|^2).
+constexpr int kSelNT = kLsSlots * 16 + (kWave - (kLsSlots * 16) % kWave) % kWave;  // 576
+
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<kQuadXor1>(v);
+  v += dpp_d<kQuadXor2>(v);
+  v += dpp_d<kRowHalfMirror>(v);
+  v += dpp_d<kRowMirror>(v);
+  return v;
+}
+
+__global__ __launch_bounds__(kSelNT) void k_ls_select(const double* __restrict__ part, int nb,
+                                                      LsArgs la, const double* __restrict__ g,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ y, int m,
+                                                      double* __restrict__ scal, int select,
+                                                      double gd_in, double dd_in) {
   __shared__ double tot[kLsSlots];
+  __shared__ double red[2][kSelNT / kWave];
   __shared__ double sh_s;
-  __shared__ double red[kNT / kWave];
-  final_sums<kNT, kLsSlots>(part, nb, tot, red);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wid = tid / kWave;
+  {
+    // sum k = tid/16 over rows b = j, j+16, ... (j = tid%16); threads past
+    // the 33 sums run the same code on component 0 and discard it
+    const int k = tid / 16 < kLsSlots ? tid / 16 : 0;
+    const int j = tid & 15;
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int b = b0 + j + 16 * u;
+        v[u] = part[(int64_t)(b < nb ? b : 0) * kLsSlots + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (b0 + j + 16 * u < nb) ? v[u] : 0.0;
+    }
+    acc = row16_sum(acc);
+    if (j == 0 && tid / 16 < kLsSlots) tot[tid / 16] = acc;
+  }
   double gd = gd_in, dd = dd_in;
   if (select) {
     double pgd = 0.0, pdd = 0.0;
-    for (int i = threadIdx.x; i < m; i += kNT) {
-      pgd += g[i] * d[i];
-      pdd += d[i] * d[i];
+    for (int i = tid; i < m; i += kSelNT) {
+      const double gi = g[i], di = d[i];
+      pgd = fma(gi, di, pgd);
+      pdd = fma(di, di, pdd);
     }
-    gd = block_sum<kNT>(pgd, red);
-    dd = block_sum<kNT>(pdd, red);
+    pgd = wave_sum(pgd);
+    pdd = wave_sum(pdd);
+    if (lane == 0) {
+      red[0][wid] = pgd;
+      red[1][wid] = pdd;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double acc_s = 0.0;
-    int acc_k = -1;
-    for (int k = 0; k < la.K; ++k) {
-      const double s = la.s[k];
-      const double delta = s * gd + 0.5 * s * s * dd + s * s * tot[kMaxTrials] + tot[k];
-      scal[SC_DELTA + k] = delta;
-      if (acc_k < 0 && delta <= la.mu * s * gd) {
-        acc_k = k;
-        acc_s = s;
+  if (select) {
+    gd = 0.0;
+    dd = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSelNT / kWave; ++q) {
+      gd += red[0][q];
+      dd += red[1][q];
+    }
+  }
+  if (wid == 0) {
+    // lane k evaluates trial k; the first passing trial wins
+    const double s = lane < la.K ? la.s[lane < kMaxTrials ? lane : 0] : 0.0;
+    const double second = tot[kMaxTrials];
+    const double delta = s * gd + 0.5 * s * s * dd + s * s * second + tot[lane < kMaxTrials ? lane : 0];
+    if (lane < la.K) scal[SC_DELTA + lane] = delta;
+    const bool pass = (lane < la.K) & (delta <= la.mu * s * gd);
+    const unsigned long long mask = __ballot(pass);
+    const int acc_k = mask ? __ffsll((long long)mask) - 1 : -1;
+    if (lane == 0) {
+      const double acc_s = acc_k >= 0 ? la.s[acc_k] : 0.0;
+      scal[SC_GD] = gd;
+      scal[SC_DD] = dd;
+      if (select) {
+        scal[SC_S] = acc_s;
+        scal[SC_LSK] = (double)acc_k;
       }
+      sh_s = acc_s;
     }
-    scal[SC_GD] = gd;
-    scal[SC_DD] = dd;
-    if (select) {
-      scal[SC_S] = acc_s;
-      scal[SC_LSK] = (double)acc_k;
-    }
-    sh_s = acc_s;
   }
   __syncthreads();
   if (select) {
     const double s = sh_s;
     if (s > 0.0)
-      for (int i = threadIdx.x; i < m; i += kNT) y[i] = fma(s, d[i], y[i]);
+      for (int i = tid; i < m; i += kSelNT) y[i] = fma(s, d[i], y[i]);
   }
 }
 
 hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
                       const double* g, const double* d, double* y, int m, double* part,
                       double* scal, hipStream_t st) {
-  const int nb = prox_blocks(n);
+  const int nb = ls_blocks(n);
   hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kNT), 0, st, part, nb, la, g, d, y, m, scal, 1, 0.0,
-                     0.0);
+  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kSelNT), 0, st, part, nb, la, g, d, y, m, scal, 1,
+                     0.0, 0.0);
   return hipGetLastError();
 }
 
 hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
                     double gd, double dd, double* part, double* scal, hipStream_t st) {
-  const int nb = prox_blocks(n);
+  const int nb = ls_blocks(n);
   hipLaunchKernelGGL(k_linesearch, dim3(nb), dim3(kNT), 0, st, x, w, wd, n, la, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kNT), 0, st, part, nb, la, (const double*)nullptr,
+  hipLaunchKernelGGL(k_ls_select, dim3(1), dim3(kSelNT), 0, st, part, nb, la, (const double*)nullptr,
                      (const double*)nullptr, (double*)nullptr, 0, scal, 0, gd, dd);
   return hipGetLastError();
 }
@@ -629,7 +672,7 @@ __global__ __launch_bounds__(kNT) void k_nonfinite(const double* __restrict__ v,
 #pragma unroll
   for (int k = 0; k < kEPT; ++k) vv[k] = v[clampi(base + k * kNT + threadIdx.x, n)];
 #pragma unroll
-  for (int k = 0; k < kEPT; ++k) c += (base + k * kNT + threadIdx.x < n) & !isfinite(vv[k]);
+  for (int k = 0; k < kEPT; ++k) c += (base + k * kNT + threadIdx.x < n) ? (int)!isfinite(vv[k]) : 0;
   __shared__ int red[kNT / kWave];
   const int t = block_sum<kNT>(c, red);
   if (threadIdx.x == 0) part[blockIdx.x] = (double)t;

@@ -63,6 +63,8 @@ struct LsArgs {
   int K;
   double s[kMaxTrials];
 };
+// Doubles of partial sums the line-search pass writes for n features.
+size_t ls_part_doubles(int64_t n);
 hipError_t linesearch(const double* x, const double* w, const double* wd, int64_t n, LsArgs la,
                       const double* g, const double* d, double* y, int m, double* part,
                       double* scal, hipStream_t st);

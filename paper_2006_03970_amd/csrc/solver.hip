@@ -7,6 +7,7 @@
 // A^T d pass, and the line search, which also updates y on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdarg>
 #include <cmath>
@@ -97,7 +98,7 @@ int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
   const size_t syrk_bytes = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);
   if ((rc = ensure(c->wy, n * 8)) || (rc = ensure(c->wd, n * 8)) || (rc = ensure(c->uJ, n * 8)) ||
       (rc = ensure(c->J, n * 4)) || (rc = ensure(c->counts, (size_t)nb * 4)) ||
-      (rc = ensure(c->part, (size_t)((nb * 33 > 2048 + nb ? nb * 33 : 2048 + nb) + 64) * 8)) ||
+      (rc = ensure(c->part, (std::max(ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb) + 64) * 8)) ||
       (rc = ensure(c->gpart, (size_t)(gather_chunks(n) + 1) * m * 8)) ||
       (rc = ensure(c->V, (size_t)m * m * 8)) || (rc = ensure(c->syrk, syrk_bytes)) ||
       (rc = ensure(c->mvec, (size_t)MV_COUNT * m * 8)))
