@@ -45,6 +45,7 @@ typedef enum { SSNAL_F64 = 0, SSNAL_F32 = 1, SSNAL_BF16 = 2 } ssnal_dtype;
 #define SSNAL_OK 0
 #define SSNAL_NOT_CONVERGED 1     /* max_outer reached; x_out holds the last iterate */
 #define SSNAL_LINESEARCH_STALL 2  /* no trial step passed eq. line_search and eta > tol */
+#define SSNAL_PATH_TRUNCATED 3    /* ssnal_en_path stopped early at max_active nonzeros */
 #define SSNAL_EINVAL (-1)         /* invalid argument (message says which) */
 #define SSNAL_ENONFINITE (-2)     /* NaN or Inf in b, x0 or A^T b */
 #define SSNAL_ENOMEM (-3)         /* device workspace allocation failed */
@@ -134,6 +135,76 @@ int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t l
                    const double* b, int64_t m, int64_t n, double lambda1, double lambda2,
                    const double* x0, double tol, hipStream_t stream, double* x_out,
                    const ssnal_en_opts* opts, ssnal_en_info* info);
+
+/*
+ * Regularisation path with warm starts (Sec. 3.3: each solve starts from the
+ * solution at the previous, larger lambda).
+ *   alpha in (0, 1)       : mixing weight; point k solves lambda1 = alpha*lam_k,
+ *                           lambda2 = (1 - alpha)*lam_k with lam_k = c_lambda[k]*lam_max,
+ *                           lam_max = ||A^T b||_inf / alpha (the smallest lam with
+ *                           solution 0), computed with FP64 accumulation over the
+ *                           stored A.
+ *   c_lambda              : HOST, nlam factors > 0, normally decreasing.
+ *   max_active            : 0 = off; else the path stops after the first point with
+ *                           more than max_active nonzeros (later columns of X_out are
+ *                           zero and their infos carry SSNAL_PATH_TRUNCATED).
+ *   X_out                 : n x nlam, column-major (column k = point k); the state
+ *                           never leaves the device between points.
+ *   opts                  : as for ssnal_en_solve; when opts->sigma0 is not set,
+ *                           point k > 0 starts from the final sigma of point k-1,
+ *                           capped at sigma0 * sigma_factor^4 of the cold default.
+ *   infos                 : HOST, nullable, nlam entries.
+ * Returns the most severe status over the points (an error stops the path).
+ */
+int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                  int64_t m, int64_t n, double alpha, const double* c_lambda, int nlam,
+                  int64_t max_active, double tol, hipStream_t stream, double* X_out,
+                  const ssnal_en_opts* opts, ssnal_en_info* infos);
+
+/* One problem of a batch or of the serving loop (fields as in ssnal_en_solve). */
+typedef struct {
+  const void* A;
+  ssnal_dtype a_dtype;
+  int64_t lda, m, n;
+  const double* b;
+  double lambda1, lambda2;
+  const double* x0;  /* nullable */
+  double tol;
+  double* x_out;
+} ssnal_en_problem;
+
+/* Independent solves, one after the other on `stream` with the context's
+ * workspace (k-fold or grid-search style).  infos: HOST, nullable, count
+ * entries.  Returns the most severe status; an error stops the batch. */
+int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int count,
+                         const ssnal_en_opts* opts, hipStream_t stream, ssnal_en_info* infos);
+
+/*
+ * Serving loop: a slot table of up to max_slots concurrent solves on one
+ * device.  Each slot owns a context and a HIP stream (default priority) and
+ * is driven by its own host thread, so the latency-bound phases of different
+ * requests overlap on the GPU.  A request is admitted when its workspace
+ * footprint (the context allocation for its (m, n); A, b and x stay with the
+ * caller) fits in hbm_budget bytes next to the slots in use; otherwise it
+ * waits, first come first served.  A request's reductions have a fixed tiling
+ * that depends only on its (m, n), so its result is bitwise the same alone
+ * or in the mix.  Pointers in a submitted problem must stay valid until its
+ * ticket completes.
+ */
+typedef struct ssnal_srv ssnal_srv;
+int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_en_opts* opts,
+                     ssnal_srv** out);
+/* Non-blocking; *ticket identifies the request. */
+int ssnal_srv_submit(ssnal_srv* srv, const ssnal_en_problem* problem, uint64_t* ticket);
+/* 1 = pending; otherwise the request's status (its result is in problem->x_out)
+ * and *info (HOST, nullable) is filled; a ticket can be collected once. */
+int ssnal_srv_poll(ssnal_srv* srv, uint64_t ticket, ssnal_en_info* info);
+/* Blocks until the ticket completes; returns its status. */
+int ssnal_srv_wait(ssnal_srv* srv, uint64_t ticket, ssnal_en_info* info);
+/* Finishes every admitted and queued request, then frees the slots. */
+void ssnal_srv_destroy(ssnal_srv* srv);
+/* Workspace bytes a context holds for an (m, n) problem (the admission footprint). */
+size_t ssnal_workspace_bytes(int64_t m, int64_t n);
 
 /* ---------------------------------------------------------------------
  * Building blocks of the solve, exported for verification and benchmarking.

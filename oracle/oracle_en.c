@@ -372,6 +372,10 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
   double normb = nrm2(b, m);
   double sigma = opt.sigma0;
   double kkt1 = INFINITY, kkt3 = INFINITY, eta = INFINITY;
+  /* Inner tolerance: tol, divided by 10 (down to tol/1000) after an outer
+   * iteration that met kkt1 and kkt3 but not eta; the decreasing inner
+   * tolerances of the criteria the paper refers to for the inner stop. */
+  double eps_in = tol;
   int status = 1, stalled = 0, newton = 0, outer = 0, outer_done = 0, rows = 0;
   int64_t r = 0;
 
@@ -387,7 +391,7 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
       orc_gemv_n(A, lda, m, n, u, Au);
       for (int64_t i = 0; i < m; ++i) g[i] = y[i] + b[i] - Au[i]; /* eq. grad_phy */
       kkt1 = nrm2(g, m) / (1.0 + normb);                          /* eq. kkt_res */
-      if (kkt1 <= tol || inner >= opt.max_inner) break;
+      if (kkt1 <= eps_in || inner >= opt.max_inner) break;
       if (orc_newton_direction(A, lda, m, J, r, kappa, g, d) != 0) { stalled = 1; break; }
       orc_gemv_t(A, lda, m, n, d, wd);
       double gd = dot(g, d, m), dd = dot(d, d, m);
@@ -423,6 +427,7 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
     if (kkt1 <= tol && kkt3 <= tol) {
       eta = orc_eta(A, lda, b, m, n, x, l1, l2);
       if (eta <= tol) { status = 0; break; }
+      eps_in = eps_in * 0.1 > tol * 1e-3 ? eps_in * 0.1 : tol * 1e-3;
     }
     if (stalled) break;
     sigma = sigma * opt.sigma_factor;

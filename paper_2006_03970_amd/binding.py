@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libssnal_en.so")
 
 SSNAL_F64, SSNAL_F32, SSNAL_BF16 = 0, 1, 2
-STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "LINESEARCH_STALL", -1: "EINVAL", -2: "ENONFINITE",
-          -3: "ENOMEM", -4: "EHIP", -5: "ENUMERIC"}
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "LINESEARCH_STALL", 3: "PATH_TRUNCATED", -1: "EINVAL",
+          -2: "ENONFINITE", -3: "ENOMEM", -4: "EHIP", -5: "ENUMERIC"}
 
 
 class SsnalError(RuntimeError):
@@ -43,6 +43,12 @@ class Info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Problem(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("a_dtype", C.c_int), ("lda", C.c_int64), ("m", C.c_int64),
+                ("n", C.c_int64), ("b", C.c_void_p), ("lambda1", C.c_double), ("lambda2", C.c_double),
+                ("x0", C.c_void_p), ("tol", C.c_double), ("x_out", C.c_void_p)]
 
 
 _lib = None
@@ -76,6 +82,20 @@ def lib():
         L.ssnal_ls_delta.argtypes = [_vp, _vp, _vp, _vp, _i64, _d, _d, _d, _d, _d, _i,
                                      C.POINTER(_d), C.POINTER(_d), _vp]
         L.ssnal_kkt.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _d, _d, C.POINTER(_d), _vp]
+        L.ssnal_en_path.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, C.POINTER(_d), _i, _i64,
+                                    _d, _vp, _vp, C.POINTER(Opts), C.POINTER(Info)]
+        L.ssnal_en_solve_batch.argtypes = [_vp, C.POINTER(Problem), _i, C.POINTER(Opts), _vp,
+                                           C.POINTER(Info)]
+        L.ssnal_srv_create.argtypes = [_i, C.c_size_t, _i, C.POINTER(Opts), C.POINTER(_vp)]
+        L.ssnal_srv_submit.argtypes = [_vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]
+        L.ssnal_srv_poll.argtypes = [_vp, C.c_uint64, C.POINTER(Info)]
+        L.ssnal_srv_wait.argtypes = [_vp, C.c_uint64, C.POINTER(Info)]
+        L.ssnal_srv_destroy.argtypes = [_vp]
+        L.ssnal_workspace_bytes.argtypes = [_i64, _i64]
+        L.ssnal_workspace_bytes.restype = C.c_size_t
+        for name in ("ssnal_en_path", "ssnal_en_solve_batch", "ssnal_srv_create", "ssnal_srv_submit",
+                     "ssnal_srv_poll", "ssnal_srv_wait"):
+            getattr(L, name).restype = _i
         for name in ("ssnal_ctx_create", "ssnal_en_solve", "ssnal_gemv_t", "ssnal_active_prox",
                      "ssnal_newton_matrix", "ssnal_cholesky", "ssnal_newton_direction",
                      "ssnal_ls_delta", "ssnal_kkt"):
@@ -255,3 +275,93 @@ def ssnal_kkt(ctx, A, b, x, lambda1, lambda2, m=None, stream=None):
     _check(lib().ssnal_kkt(ctx.ptr, pA, dt, lda, _ptr(b), m, n, _ptr(x), float(lambda1),
                            float(lambda2), out, _stream(stream)))
     return {"eta": out[0], "primal_obj": out[1], "dual_obj": out[2], "rel_gap": out[3]}
+
+
+def workspace_bytes(m, n) -> int:
+    """Device bytes a context holds for an (m, n) problem (serving admission footprint)."""
+    return int(lib().ssnal_workspace_bytes(int(m), int(n)))
+
+
+def ssnal_en_path(ctx, A, b, alpha, c_lambda, tol=1e-6, X_out=None, m=None, max_active=0,
+                  opts=None, stream=None):
+    """Warm-started path over lam_k = c_lambda[k] * lam_max.  Returns (X (n, nlam) with
+    column-major storage viewed as X_out[k] = point k, list of info dicts, status)."""
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    nlam = len(c_lambda)
+    if X_out is None:
+        X_out = torch.empty((nlam, n), dtype=torch.float64, device=A.device)
+    assert X_out.is_contiguous() and X_out.numel() == nlam * n
+    cl = (C.c_double * nlam)(*[float(v) for v in c_lambda])
+    infos = (Info * nlam)()
+    o = opts if opts is not None else make_opts()
+    rc = lib().ssnal_en_path(ctx.ptr, pA, dt, lda, _ptr(b), m, n, float(alpha), cl, nlam,
+                             int(max_active), float(tol), _stream(stream), _ptr(X_out), C.byref(o),
+                             infos)
+    _check(rc, allow_warn=True)
+    return X_out, [infos[k].as_dict() for k in range(nlam)], rc
+
+
+def _problem(A, b, lambda1, lambda2, tol, x_out, x0=None, m=None):
+    pA, dt, lda, m, n = _design(A, m)
+    return Problem(pA, dt, lda, m, n, _ptr(b), float(lambda1), float(lambda2), _ptr(x0), float(tol),
+                   _ptr(x_out))
+
+
+def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None):
+    """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0].
+    Returns (list of info dicts, worst status)."""
+    cnt = len(problems)
+    arr = (Problem * cnt)(*[_problem(p["A"], p["b"], p["lambda1"], p["lambda2"], p["tol"], p["x_out"],
+                                     p.get("x0")) for p in problems])
+    infos = (Info * cnt)()
+    o = opts if opts is not None else make_opts()
+    rc = lib().ssnal_en_solve_batch(ctx.ptr, arr, cnt, C.byref(o), _stream(stream), infos)
+    _check(rc, allow_warn=True)
+    return [infos[i].as_dict() for i in range(cnt)], rc
+
+
+class Server:
+    """Serving loop (slot table, admission by workspace footprint)."""
+
+    def __init__(self, device=0, hbm_budget=8 << 30, max_slots=4, opts=None):
+        p = _vp()
+        o = C.byref(opts) if opts is not None else None
+        _check(lib().ssnal_srv_create(device, int(hbm_budget), int(max_slots), o, C.byref(p)))
+        self.ptr = p
+        self._keep = {}
+
+    def submit(self, A, b, lambda1, lambda2, tol, x_out, x0=None) -> int:
+        t = C.c_uint64(0)
+        prob = _problem(A, b, lambda1, lambda2, tol, x_out, x0)
+        _check(lib().ssnal_srv_submit(self.ptr, C.byref(prob), C.byref(t)))
+        self._keep[t.value] = (A, b, x_out, x0)  # tensors stay alive until collected
+        return t.value
+
+    def poll(self, ticket):
+        info = Info()
+        rc = lib().ssnal_srv_poll(self.ptr, ticket, C.byref(info))
+        if rc == 1:
+            return None
+        self._keep.pop(ticket, None)
+        _check(rc, allow_warn=True)
+        return info.as_dict()
+
+    def wait(self, ticket):
+        info = Info()
+        rc = lib().ssnal_srv_wait(self.ptr, ticket, C.byref(info))
+        self._keep.pop(ticket, None)
+        _check(rc, allow_warn=True)
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().ssnal_srv_destroy(self.ptr)
+            self.ptr = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

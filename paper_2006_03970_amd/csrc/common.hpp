@@ -69,6 +69,13 @@ __device__ __forceinline__ int wave_sum(int v) {
   return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
          (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<kQuadXor1>(v));
+  v = fmax(v, dpp_d<kQuadXor2>(v));
+  v = fmax(v, dpp_d<kRowHalfMirror>(v));
+  v = fmax(v, dpp_d<kRowMirror>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
 // Sum over aligned groups of 8 lanes (every lane of a group gets the sum);
 // only the lanes of each group need to be active.
 __device__ __forceinline__ double group8_sum(double v) {

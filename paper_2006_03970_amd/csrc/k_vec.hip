@@ -635,6 +635,53 @@ hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, doub
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ max |v_i|
+// (lambda_max of a path: ||A^T b||_inf).  Per-block maxima, then one block.
+// NaN entries are ignored by fmax; callers check finiteness separately.
+constexpr int kMaxBlocks = 1024;
+
+__global__ __launch_bounds__(kNT) void k_absmax(const double* __restrict__ v, int64_t n,
+                                                 double* __restrict__ part) {
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT)
+    mx = fmax(mx, fabs(v[i]));
+  __shared__ double red[kNT / kWave];
+  mx = wave_max(mx);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+#pragma unroll
+    for (int q = 1; q < kNT / kWave; ++q) t = fmax(t, red[q]);
+    part[blockIdx.x] = t;
+  }
+}
+__global__ __launch_bounds__(kNT) void k_absmax_final(const double* __restrict__ part, int nb,
+                                                       double* __restrict__ out) {
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kNT) mx = fmax(mx, part[b]);
+  __shared__ double red[kNT / kWave];
+  mx = wave_max(mx);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+#pragma unroll
+    for (int q = 1; q < kNT / kWave; ++q) t = fmax(t, red[q]);
+    *out = t;
+  }
+}
+
+hipError_t absmax(const double* v, int64_t n, double* part, double* out, hipStream_t st) {
+  int64_t nb = (n + kNT - 1) / kNT;
+  if (nb > kMaxBlocks) nb = kMaxBlocks;
+  hipLaunchKernelGGL(k_absmax, dim3((unsigned)nb), dim3(kNT), 0, st, v, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kNT), 0, st, part, (int)nb, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ helpers
 __global__ void k_scale_copy(const double* __restrict__ src, double alpha, double* __restrict__ dst,
                              int64_t n) {

@@ -95,6 +95,9 @@ size_t syrk_workspace_bytes(int form, int m, int64_t r);
 hipError_t syrk(const void* A, int dtype, int64_t lda, int m, const int32_t* J, int64_t r, int form,
                 double shift, double scale, double* out, void* work, hipStream_t st);
 
+// *out = max_i |v_i| (part: 1024 doubles of scratch).
+hipError_t absmax(const double* v, int64_t n, double* part, double* out, hipStream_t st);
+
 // ---- Cholesky and triangular solves (k_chol.hip) --------------------------
 // Raise the dynamic LDS limits of the Cholesky kernels (once per device).
 hipError_t chol_init();

@@ -9,6 +9,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -56,6 +61,7 @@ struct ssnal_ctx {
   double* h_scal = nullptr;  // pinned, SC_SIZE doubles
   std::vector<hipEvent_t> ev;
   bool chol_ready = false;
+  double last_sigma0 = 0.0;  // sigma0 of the last solve (after defaults)
 };
 
 namespace {
@@ -91,18 +97,54 @@ struct Workspace {
   int* info;
 };
 
-int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
-  int rc;
+// Bytes of each workspace buffer an (m, n) problem needs, in the order of
+// WsPlan::bufs (the admission footprint of the serving loop is their sum).
+struct WsPlan {
+  size_t bytes[10];
+};
+WsPlan plan_ws(int64_t m, int64_t n) {
   const int nb = prox_blocks(n);
   const int64_t T = (m + 63) / 64;
-  const size_t syrk_bytes = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);
-  if ((rc = ensure(c->wy, n * 8)) || (rc = ensure(c->wd, n * 8)) || (rc = ensure(c->uJ, n * 8)) ||
-      (rc = ensure(c->J, n * 4)) || (rc = ensure(c->counts, (size_t)nb * 4)) ||
-      (rc = ensure(c->part, (std::max(ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb) + 64) * 8)) ||
-      (rc = ensure(c->gpart, (size_t)(gather_chunks(n) + 1) * m * 8)) ||
-      (rc = ensure(c->V, (size_t)m * m * 8)) || (rc = ensure(c->syrk, syrk_bytes)) ||
-      (rc = ensure(c->mvec, (size_t)MV_COUNT * m * 8)))
-    return rc;
+  WsPlan p;
+  p.bytes[0] = (size_t)n * 8;  // wy
+  p.bytes[1] = (size_t)n * 8;  // wd
+  p.bytes[2] = (size_t)n * 8;  // uJ
+  p.bytes[3] = (size_t)n * 4;  // J
+  p.bytes[4] = (size_t)nb * 4;  // counts
+  p.bytes[5] = (std::max(ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb) + 64) * 8;  // part
+  p.bytes[6] = (size_t)(gather_chunks(n) + 1) * m * 8;  // gpart
+  p.bytes[7] = (size_t)m * m * 8;  // V
+  p.bytes[8] = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);  // syrk split-K
+  p.bytes[9] = (size_t)MV_COUNT * m * 8;  // m-vectors
+  for (size_t& b : p.bytes) b = b < 256 ? 256 : b;
+  return p;
+}
+DevBuf* ws_bufs(ssnal_ctx* c, int i) {
+  DevBuf* b[10] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart, &c->V, &c->syrk, &c->mvec};
+  return b[i];
+}
+// Bytes the context would hold after preparing for plan p (buffers only grow).
+size_t held_after(ssnal_ctx* c, const WsPlan& p) {
+  size_t t = SC_SIZE * sizeof(double);
+  for (int i = 0; i < 10; ++i) t += std::max(ws_bufs(c, i)->bytes, p.bytes[i]);
+  return t;
+}
+// Free the workspace buffers (the context stays usable; they regrow on demand).
+// The caller guarantees that no work of this context is in flight.
+void ctx_trim(ssnal_ctx* c) {
+  (void)hipSetDevice(c->device);
+  for (int i = 0; i < 10; ++i) {
+    DevBuf* b = ws_bufs(c, i);
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+}
+
+int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
+  const WsPlan plan = plan_ws(m, n);
+  for (int i = 0; i < 10; ++i)
+    if (int rc = ensure(*ws_bufs(c, i), plan.bytes[i])) return rc;
   w.wy = (double*)c->wy.p;
   w.wd = (double*)c->wd.p;
   w.uJ = (double*)c->uJ.p;
@@ -324,8 +366,13 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     const double mean = colsq / (double)n;
     sigma = 2.5 / (mean > 0.0 ? mean : 1.0);
   }
+  c->last_sigma0 = sigma;
 
   double kkt1 = INFINITY, kkt3 = INFINITY, eta = INFINITY, F = NAN, D = NAN;
+  // Inner tolerance: tol, divided by 10 (down to tol/1000) after an outer
+  // iteration that met kkt1 and kkt3 but not eta (decreasing inner
+  // tolerances, as in the inner stopping criteria the method refers to).
+  double eps_in = tol;
   int status = SSNAL_NOT_CONVERGED, newton = 0, outer_done = 0, rows = 0;
   int64_t r = 0;
   bool stalled = false, pending = false, converged = false;
@@ -372,7 +419,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       kkt1 = std::sqrt(hs[SC_GG]) / (1.0 + normb);
       if (!std::isfinite(kkt1)) return fail(SSNAL_ENONFINITE, "non-finite gradient");
       if (stalled) break;
-      if (kkt1 <= tol) {
+      if (kkt1 <= eps_in) {
         if (mixed && !o.no_refine && !refreshed) {
           // refresh A^T y with FP64 accumulation over the stored A, then re-test
           if (int rc = tm.rec_start()) return rc;
@@ -425,6 +472,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
         status = SSNAL_OK;
         break;
       }
+      eps_in = std::max(eps_in * 0.1, tol * 1e-3);
     }
     if (stalled) break;
     sigma *= o.sigma_factor;
@@ -534,6 +582,336 @@ int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t l
   if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
   return solve_impl(ctx, A, (int)a_dtype, lda, b, m, n, lambda1, lambda2, x0, tol, stream, x_out,
                     opts, info);
+}
+
+int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                  int64_t m, int64_t n, double alpha, const double* c_lambda, int nlam,
+                  int64_t max_active, double tol, hipStream_t stream, double* X_out,
+                  const ssnal_en_opts* opts, ssnal_en_info* infos) {
+  g_err[0] = 0;
+  if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
+  if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
+  if (!X_out || !c_lambda) return fail(SSNAL_EINVAL, "X_out and c_lambda must be non-null");
+  if (nlam < 1) return fail(SSNAL_EINVAL, "nlam must be >= 1");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1) (lambda2 > 0)");
+  if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
+  if (max_active < 0) return fail(SSNAL_EINVAL, "max_active must be >= 0");
+  for (int k = 0; k < nlam; ++k)
+    if (!(c_lambda[k] > 0.0) || !std::isfinite(c_lambda[k]))
+      return fail(SSNAL_EINVAL, "c_lambda[%d] must be finite and > 0", k);
+  HIPCHK(hipSetDevice(ctx->device));
+  const int dt = (int)a_dtype;
+  double amax = 0.0;
+  {
+    // lam_max = ||A^T b||_inf / alpha: the smallest lam whose solution is 0
+    Workspace ws;
+    if (int rc = prepare(ctx, m, n, ws)) return rc;
+    HIPCHK(gemv_t(A, dt, lda, (int)m, n, nullptr, b, ws.wd, true, stream));
+    HIPCHK(absmax(ws.wd, n, ws.part, ws.scal + SC_AMAX, stream));
+    HIPCHK(nonfinite_count(ws.wd, n, ws.scal + SC_NONFIN, ws.part + 2048, stream));
+    if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
+    if (ctx->h_scal[SC_NONFIN] != 0.0) return fail(SSNAL_ENONFINITE, "A^T b holds non-finite entries");
+    amax = ctx->h_scal[SC_AMAX];
+  }
+  const double lam_max = amax / alpha;
+  // Each point starts from the previous point's x and, unless the caller fixes
+  // sigma0, from its final penalty sigma: the warm start then usually ends
+  // after one multiplier update.  The carried sigma is capped at the value a
+  // cold solve reaches in its fifth outer iteration (sigma0 * factor^4):
+  // sigma only grows along a path, and far past that, t = x - sigma A^T y
+  // loses the digits of x, so x stops moving while the KKT residual stays
+  // above tol.
+  ssnal_en_opts o;
+  if (opts) o = *opts;
+  else ssnal_en_opts_init(&o);
+  o.trace = nullptr;
+  o.trace_cap = 0;
+  const bool carry_sigma = !(o.sigma0 > 0.0);
+  const double factor = o.sigma_factor > 0.0 ? o.sigma_factor : 5.0;
+  double sigma_cap = 0.0;  // set from the first cold solve
+  int worst = 0;
+  for (int k = 0; k < nlam; ++k) {
+    double* xk = X_out + (int64_t)k * n;
+    ssnal_en_info info_k;
+    std::memset(&info_k, 0, sizeof(info_k));
+    if (amax == 0.0) {
+      // A^T b = 0: x = 0 at every lambda
+      HIPCHK(hipMemsetAsync(xk, 0, (size_t)n * 8, stream));
+    } else {
+      const double lam = c_lambda[k] * lam_max;
+      const double* x0 = k > 0 ? X_out + (int64_t)(k - 1) * n : nullptr;
+      const int rc = solve_impl(ctx, A, dt, lda, b, m, n, alpha * lam, (1.0 - alpha) * lam, x0, tol,
+                                stream, xk, &o, &info_k);
+      if (rc < 0) return rc;
+      worst = std::max(worst, rc);
+      if (carry_sigma) {
+        if (sigma_cap == 0.0) sigma_cap = ctx->last_sigma0 * factor * factor * factor * factor;
+        o.sigma0 = std::min(info_k.sigma_final, sigma_cap);
+      }
+    }
+    if (infos) infos[k] = info_k;
+    if (max_active > 0 && info_k.nnz > max_active && k + 1 < nlam) {
+      HIPCHK(hipMemsetAsync(xk + n, 0, (size_t)(nlam - k - 1) * n * 8, stream));
+      if (infos)
+        for (int q = k + 1; q < nlam; ++q) {
+          std::memset(&infos[q], 0, sizeof(infos[q]));
+          infos[q].status = SSNAL_PATH_TRUNCATED;
+        }
+      worst = std::max(worst, SSNAL_PATH_TRUNCATED);
+      break;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  if (worst == SSNAL_PATH_TRUNCATED) snprintf(g_err, sizeof(g_err), "path truncated at max_active");
+  return worst;
+}
+
+int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int count,
+                         const ssnal_en_opts* opts, hipStream_t stream, ssnal_en_info* infos) {
+  g_err[0] = 0;
+  if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
+  if (count < 0 || (count > 0 && !problems)) return fail(SSNAL_EINVAL, "invalid problem list");
+  int worst = 0;
+  for (int i = 0; i < count; ++i) {
+    const ssnal_en_problem& p = problems[i];
+    ssnal_en_info info_i;
+    const int rc = solve_impl(ctx, p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1, p.lambda2,
+                              p.x0, p.tol, stream, p.x_out, opts, &info_i);
+    if (rc < 0) return rc;
+    if (infos) infos[i] = info_i;
+    worst = std::max(worst, rc);
+  }
+  return worst;
+}
+
+size_t ssnal_workspace_bytes(int64_t m, int64_t n) {
+  if (m < 1 || n < 1) return 0;
+  const WsPlan p = plan_ws(m, n);
+  size_t t = SC_SIZE * sizeof(double);
+  for (size_t b : p.bytes) t += b;
+  return t;
+}
+
+}  // extern "C"
+
+// ====================================================================== serving loop
+// Slot i is a host thread with its own context and stream.  Admission is
+// first come, first served: the request at the head of the queue goes to the
+// first idle slot whose context, grown for it, keeps the bytes held by all
+// contexts within the budget.  When nothing is running and the head still
+// does not fit, idle contexts release their workspace (no work is in flight,
+// so freeing is safe) and the head is admitted.
+struct ssnal_srv {
+  struct Req {
+    uint64_t ticket;
+    ssnal_en_problem p;
+  };
+  struct Done {
+    int status;
+    ssnal_en_info info;
+    char err[256];
+  };
+  int device = 0;
+  size_t budget = 0;
+  ssnal_en_opts opts;
+  bool has_opts = false;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req> queue;
+  std::unordered_map<uint64_t, Done> done;
+  std::unordered_map<uint64_t, int> live;  // queued or running tickets
+  std::vector<ssnal_ctx*> ctx;
+  std::vector<size_t> held;  // bytes held by each slot's context
+  std::vector<char> busy;
+  std::vector<std::thread> workers;
+  int running = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int init_rc = 0;
+  char init_err[512] = "";
+};
+
+namespace {
+
+size_t ctx_held(ssnal_ctx* c) {
+  size_t t = SC_SIZE * sizeof(double);
+  for (int i = 0; i < 10; ++i) t += ws_bufs(c, i)->bytes;
+  return t;
+}
+
+void srv_worker(ssnal_srv* s, int slot) {
+  hipStream_t st = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (hipSetDevice(s->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      s->init_rc = SSNAL_EHIP;
+      snprintf(s->init_err, sizeof(s->init_err), "slot %d: stream creation failed", slot);
+      st = nullptr;
+    }
+    s->cv_done.notify_all();
+  }
+  for (;;) {
+    ssnal_srv::Req req;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      for (;;) {
+        if (s->queue.empty()) {
+          if (s->stop) {
+            lk.unlock();
+            if (st) (void)hipStreamDestroy(st);
+            return;
+          }
+          s->cv_work.wait(lk);
+          continue;
+        }
+        const ssnal_en_problem& hp = s->queue.front().p;
+        const WsPlan plan = plan_ws(hp.m, hp.n);
+        size_t others = 0;
+        for (size_t j = 0; j < s->held.size(); ++j)
+          if ((int)j != slot) others += s->held[j];
+        const size_t mine = held_after(s->ctx[slot], plan);
+        if (others + mine <= s->budget) break;
+        if (s->running == 0) {
+          // nothing in flight: release every idle workspace, then admit the head
+          for (size_t j = 0; j < s->ctx.size(); ++j) {
+            ctx_trim(s->ctx[j]);
+            s->held[j] = ctx_held(s->ctx[j]);
+          }
+          break;
+        }
+        s->cv_work.wait(lk);
+      }
+      req = s->queue.front();
+      s->queue.pop_front();
+      s->held[slot] = held_after(s->ctx[slot], plan_ws(req.p.m, req.p.n));
+      s->busy[slot] = 1;
+      ++s->running;
+      s->cv_work.notify_all();  // the next head may fit another idle slot
+    }
+    ssnal_srv::Done d;
+    std::memset(&d.info, 0, sizeof(d.info));
+    if (st) {
+      const ssnal_en_problem& p = req.p;
+      d.status = solve_impl(s->ctx[slot], p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1,
+                            p.lambda2, p.x0, p.tol, st, p.x_out, s->has_opts ? &s->opts : nullptr,
+                            &d.info);
+    } else {
+      d.status = SSNAL_EHIP;
+    }
+    if (d.status < 0) d.info.status = d.status;
+    snprintf(d.err, sizeof(d.err), "%s", g_err);
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->held[slot] = ctx_held(s->ctx[slot]);
+      s->busy[slot] = 0;
+      --s->running;
+      s->live.erase(req.ticket);
+      s->done[req.ticket] = d;
+      s->cv_done.notify_all();
+      s->cv_work.notify_all();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_en_opts* opts,
+                     ssnal_srv** out) {
+  g_err[0] = 0;
+  if (!out) return fail(SSNAL_EINVAL, "out must be non-null");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 64) return fail(SSNAL_EINVAL, "max_slots must lie in [1, 64]");
+  if (hbm_budget == 0) return fail(SSNAL_EINVAL, "hbm_budget must be > 0");
+  ssnal_srv* s = new (std::nothrow) ssnal_srv();
+  if (!s) return fail(SSNAL_ENOMEM, "host allocation failed");
+  s->device = device;
+  s->budget = hbm_budget;
+  if (opts) {
+    s->opts = *opts;
+    s->opts.trace = nullptr;
+    s->opts.trace_cap = 0;
+    s->has_opts = true;
+  }
+  for (int i = 0; i < max_slots; ++i) {
+    ssnal_ctx* c = nullptr;
+    if (int rc = ssnal_ctx_create(device, &c)) {
+      for (ssnal_ctx* q : s->ctx) ssnal_ctx_destroy(q);
+      delete s;
+      return rc;
+    }
+    s->ctx.push_back(c);
+    s->held.push_back(ctx_held(c));
+    s->busy.push_back(0);
+  }
+  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(srv_worker, s, i);
+  *out = s;
+  return 0;
+}
+
+int ssnal_srv_submit(ssnal_srv* s, const ssnal_en_problem* p, uint64_t* ticket) {
+  g_err[0] = 0;
+  if (!s || !p || !ticket) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(p->A, (int)p->a_dtype, p->lda, p->b, p->m, p->n)) return rc;
+  if (!p->x_out) return fail(SSNAL_EINVAL, "x_out must be non-null");
+  if (!(p->lambda1 >= 0.0) || !(p->lambda2 > 0.0) || !(p->tol > 0.0))
+    return fail(SSNAL_EINVAL, "need lambda1 >= 0, lambda2 > 0, tol > 0");
+  const size_t need = ssnal_workspace_bytes(p->m, p->n);
+  if (need > s->budget)
+    return fail(SSNAL_ENOMEM, "request needs %zu workspace bytes, budget is %zu", need, s->budget);
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->init_rc) return fail(s->init_rc, "%s", s->init_err);
+  if (s->stop) return fail(SSNAL_EINVAL, "server is shutting down");
+  const uint64_t t = s->next_ticket++;
+  s->queue.push_back({t, *p});
+  s->live[t] = 1;
+  *ticket = t;
+  s->cv_work.notify_all();
+  return 0;
+}
+
+static int srv_collect(ssnal_srv* s, uint64_t ticket, ssnal_en_info* info, bool block) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    auto it = s->done.find(ticket);
+    if (it != s->done.end()) {
+      const int st = it->second.status;
+      if (info) *info = it->second.info;
+      if (st != 0) snprintf(g_err, sizeof(g_err), "%s", it->second.err);
+      s->done.erase(it);
+      return st;
+    }
+    if (!s->live.count(ticket)) return fail(SSNAL_EINVAL, "unknown or already collected ticket %llu",
+                                            (unsigned long long)ticket);
+    if (!block) return 1;
+    s->cv_done.wait(lk);
+  }
+}
+
+int ssnal_srv_poll(ssnal_srv* s, uint64_t ticket, ssnal_en_info* info) {
+  g_err[0] = 0;
+  if (!s) return fail(SSNAL_EINVAL, "null server");
+  return srv_collect(s, ticket, info, false);
+}
+
+int ssnal_srv_wait(ssnal_srv* s, uint64_t ticket, ssnal_en_info* info) {
+  g_err[0] = 0;
+  if (!s) return fail(SSNAL_EINVAL, "null server");
+  return srv_collect(s, ticket, info, true);
+}
+
+void ssnal_srv_destroy(ssnal_srv* s) {
+  if (!s) return;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  for (std::thread& t : s->workers) t.join();
+  for (ssnal_ctx* c : s->ctx) ssnal_ctx_destroy(c);
+  delete s;
 }
 
 int ssnal_gemv_t(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,

@@ -20,7 +20,9 @@ def declared_functions():
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("ssnal_ctx_create", "ssnal_ctx_destroy", "ssnal_en_solve", "ssnal_last_error",
-                 "ssnal_gemv_t", "ssnal_cholesky"):
+                 "ssnal_gemv_t", "ssnal_cholesky", "ssnal_en_path", "ssnal_en_solve_batch",
+                 "ssnal_srv_create", "ssnal_srv_submit", "ssnal_srv_poll", "ssnal_srv_wait",
+                 "ssnal_srv_destroy", "ssnal_workspace_bytes"):
         assert must in names
 
 
@@ -37,7 +39,8 @@ def test_binding_structs_match_header():
     """ctypes mirrors of ssnal_en_opts / ssnal_en_info have the header's field order."""
     from paper_2006_03970_amd import binding
     src = open(HEADER).read()
-    for struct, cls in (("ssnal_en_opts", binding.Opts), ("ssnal_en_info", binding.Info)):
+    for struct, cls in (("ssnal_en_opts", binding.Opts), ("ssnal_en_info", binding.Info),
+                        ("ssnal_en_problem", binding.Problem)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + ";", src).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
@@ -45,7 +48,7 @@ def test_binding_structs_match_header():
             decl = decl.strip()
             if not decl:
                 continue
-            parts = decl.replace("*", " ").split()
+            parts = [t for t in decl.replace("*", " ").split() if t != "const"]
             names = " ".join(parts[1:]).split(",")
             fields += [n.strip() for n in names]
         assert fields == [f for f, _ in cls._fields_], (struct, fields)
@@ -59,3 +62,14 @@ def test_error_message_without_gpu():
     from paper_2006_03970_amd import binding
     with pytest.raises(binding.SsnalError):
         binding.Context(0)
+
+
+def test_workspace_bytes_host_only():
+    """The admission footprint is a host computation (no device needed)."""
+    from paper_2006_03970_amd import binding
+    assert binding.workspace_bytes(0, 10) == 0
+    small = binding.workspace_bytes(100, 2000)
+    big = binding.workspace_bytes(500, 100000)
+    assert 0 < small < big
+    # dominated by the n-vectors, the m x m matrix and the split-K partial sums
+    assert big >= 500 * 500 * 8 + 3 * 100000 * 8
