@@ -8,11 +8,16 @@ cold start, the design already resident in HBM.  `value` is the mixed-
 precision path (design stored in FP32, FP32 accumulation in A^T v and the
 Newton matrix, FP64 Cholesky / line search / KKT residual, FP64-accumulated
 refresh of A^T y); the plain FP64 path on the same problem is reported beside
-it.  The roofline entry is the A^T v kernel, timed live with HIP events around
-each of its launches on the solve's stream.  The CPU baseline is the FP64
-oracle on the machine's host cores.
+it, and BF16 storage as a second mixed variant.  The roofline entry is the
+Newton pass w_d = A^T d (k_gemv_t over the FP32 design, FP32 accumulation),
+timed live with HIP events around each of its launches on the solve's stream.
+The CPU baseline is the FP64 oracle on the machine's host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Counter runs (HBM traffic of the A^T v kernel and of a plain copy of the same
+byte count, for the calibration factor):
+       python bench.py --profile-gemv K     K launches of the FP32 A^T v pass
+       python bench.py --profile-copy K     K device copies of m*n*4 bytes
 """
 import argparse
 import hashlib
@@ -54,6 +59,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-gemv", type=int, default=0)
+    ap.add_argument("--profile-copy", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -75,11 +82,27 @@ def main():
     p64 = datagen.make_problem("c2", seed=args.seed, store="f64")
     AT32 = p64.AT.astype(np.float32)
     print(f"[bench] generated m={p64.m} n={p64.n} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    A64 = design_to_device(p64.AT, "f64")
     A32 = design_to_device(AT32, "f32")
     b = vec_to_device(p64.b)
     ctx = binding.Context(0)
     stream = torch.cuda.current_stream()
+    if args.profile_gemv or args.profile_copy:
+        # short runs for rocprofv3 counter collection, nothing else
+        if args.profile_gemv:
+            w = torch.empty(p64.n, dtype=torch.float64, device=dev)
+            for k in range(args.profile_gemv):
+                binding.ssnal_gemv_t(ctx, A32, b, w, acc64=False, stream=stream)
+                print(f"[bench] A^T v launch {k}", file=sys.stderr, flush=True)
+        else:
+            src_t = torch.ones(p64.m * p64.n, dtype=torch.float32, device=dev)
+            dst_t = torch.empty_like(src_t)
+            for k in range(args.profile_copy):
+                dst_t.copy_(src_t)
+                torch.cuda.synchronize()
+                print(f"[bench] copy launch {k}", file=sys.stderr, flush=True)
+        return
+    A64 = design_to_device(p64.AT, "f64")
+    Abf = design_to_device(datagen.f32_to_bf16_bits(AT32), "bf16")
 
     def run(A, steps, timing):
         opts = binding.make_opts(timing=1 if timing else 0)
@@ -105,16 +128,19 @@ def main():
 
     el32, inf32, x32 = timed(A32, "mixed f32")
     el64, inf64, x64 = timed(A64, "fp64")
+    elbf, infbf, _ = timed(Abf, "mixed bf16")
 
-    def gemv_stats(infos, s_a):
-        calls = sum(i["gemv_calls"] for i in infos)
-        ms = sum(i["gemv_ms"] for i in infos)
+    def atd_stats(infos, s_a):
+        """Average duration of the Newton A^T d launches (HIP events)."""
+        calls = sum(i["atd_launches"] for i in infos)
+        ms = sum(i["atd_ms"] for i in infos)
         avg_s = ms / calls / 1e3
         bytes_per_launch = float(p64.m) * p64.n * s_a
         return avg_s, bytes_per_launch, calls / len(infos)
 
-    avg32, bpl32, calls32 = gemv_stats(inf32, 4)
-    avg64, bpl64, calls64 = gemv_stats(inf64, 8)
+    avg32, bpl32, calls32 = atd_stats(inf32, 4)
+    avg64, bpl64, calls64 = atd_stats(inf64, 8)
+    avgbf, bplbf, _ = atd_stats(infbf, 2)
     achieved = bpl32 / avg32 / 1e9
     traffic = _traffic_from_profile(os.path.join(ROOT, "paper_2006_03970_amd", "csrc", "k_gemv.hip"), "f32")
 
@@ -141,13 +167,18 @@ def main():
         "fp64_solves_per_s": args.steps / el64,
         "fp64_ms_per_step": el64 / args.steps * 1e3,
         "mixed_over_fp64": (args.steps / el32) / (args.steps / el64),
-        "eta": {"mixed_f32": inf32[-1]["kkt_rel"], "fp64": inf64[-1]["kkt_rel"]},
+        "bf16_solves_per_s": args.steps / elbf,
+        "eta": {"mixed_f32": inf32[-1]["kkt_rel"], "fp64": inf64[-1]["kkt_rel"],
+                "mixed_bf16": infbf[-1]["kkt_rel"]},
         "iterations": {"mixed_f32": [inf32[-1]["outer_iters"], inf32[-1]["newton_iters"]],
-                       "fp64": [inf64[-1]["outer_iters"], inf64[-1]["newton_iters"]]},
-        "gemv_launches_per_solve": {"mixed_f32": calls32, "fp64": calls64},
-        "gemv_gbs": {"mixed_f32": achieved, "fp64": bpl64 / avg64 / 1e9},
+                       "fp64": [inf64[-1]["outer_iters"], inf64[-1]["newton_iters"]],
+                       "mixed_bf16": [infbf[-1]["outer_iters"], infbf[-1]["newton_iters"]]},
+        "atd_launches_per_solve": {"mixed_f32": calls32, "fp64": calls64},
+        "atd_gbs": {"mixed_f32": achieved, "fp64": bpl64 / avg64 / 1e9,
+                    "mixed_bf16": bplbf / avgbf / 1e9},
         "roofline": {
-            "bound": "hbm", "kernel": "A^T v (k_gemv_t, FP32 design)",
+            "bound": "hbm",
+            "kernel": "Newton pass w_d = A^T d: k_gemv_t<float, float, 2> (FP32 design, FP32 accumulation)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,

@@ -98,6 +98,8 @@ typedef struct {
   int32_t syncs;         /* device-to-host synchronisations */
   double gemv_ms;        /* with opts.timing: summed durations of the A^T v launches */
   double solve_ms;       /* host wall time of the call */
+  int32_t atd_launches;  /* with opts.timing: launches of the Newton pass w_d = A^T d ... */
+  double atd_ms;         /* ... and their summed durations (HIP events on the solve's stream) */
 } ssnal_en_info;
 
 /* Fill *opts with the defaults listed above. */

@@ -39,7 +39,7 @@ class Info(C.Structure):
                 ("kkt1", C.c_double), ("kkt3", C.c_double), ("primal_obj", C.c_double),
                 ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double),
                 ("gemv_calls", C.c_int32), ("syncs", C.c_int32), ("gemv_ms", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("atd_launches", C.c_int32), ("atd_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -159,6 +159,32 @@ __device__ __forceinline__ void load16(const uint16_t* p, ACC* e) {
   }
 }
 
+// 8-byte vector loads (A 8-byte aligned, lda*sizeof(elem) a multiple of 8).
+template <typename ACC>
+__device__ __forceinline__ void load8(const double* p, ACC* e) {
+  e[0] = (ACC)*p;
+}
+template <typename ACC>
+__device__ __forceinline__ void load8(const float* p, ACC* e) {
+  float2 q = *reinterpret_cast<const float2*>(p);
+  e[0] = (ACC)q.x;
+  e[1] = (ACC)q.y;
+}
+template <typename ACC>
+__device__ __forceinline__ void load8(const uint16_t* p, ACC* e) {
+  uint2 q = *reinterpret_cast<const uint2*>(p);
+  e[0] = (ACC)bf16_bits_to_f32(q.x & 0xFFFFu);
+  e[1] = (ACC)bf16_bits_to_f32(q.x >> 16);
+  e[2] = (ACC)bf16_bits_to_f32(q.y & 0xFFFFu);
+  e[3] = (ACC)bf16_bits_to_f32(q.y >> 16);
+}
+// VB-byte vector load (VB = 16 or 8) of VB / sizeof(T) elements.
+template <int VB, typename T, typename ACC>
+__device__ __forceinline__ void loadv(const T* p, ACC* e) {
+  if constexpr (VB == 16) load16<ACC>(p, e);
+  else load8<ACC>(p, e);
+}
+
 template <typename ACC>
 __device__ __forceinline__ ACC load1(const double* p) { return (ACC)*p; }
 template <typename ACC>

@@ -2,12 +2,15 @@
 // iteration (w_d = A^T d), of the initial A^T y and of the KKT residual.
 //
 // Layout: each wave streams whole columns.  Lane l owns rows
-// [(it*64 + l)*VN, +VN) for it < ITERS, where VN elements make one 16-byte
-// load, so a wave reads 1 KiB per instruction and the matching slice of v
-// stays in registers for the whole kernel.  A wave keeps COLS columns in
+// [(it*64 + l)*VN, +VN) for it < ITERS, where VN elements make one VB-byte
+// load (16 bytes, or 8 when the column stride allows no more), so a wave
+// reads 1 KiB (512 B) per instruction and the matching slice of v stays in
+// registers for the whole kernel.  A wave keeps COLS columns in
 // flight (COLS*ITERS loads outstanding per lane), then reduces each column
 // across the wave.  A block owns a contiguous range of columns, so the four
 // waves of a block read neighbouring columns.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,12 +21,12 @@ struct ColsFor {
   static constexpr int value = ITERS <= 1 ? 8 : (ITERS <= 2 ? 8 : (ITERS <= 4 ? 4 : (ITERS <= 8 ? 2 : 1)));
 };
 
-template <typename T, typename ACC, int ITERS, bool COLSQ>
+template <typename T, typename ACC, int ITERS, bool COLSQ, int VB>
 __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t lda, int m,
                                                 int64_t ncols, const double* __restrict__ v,
                                                 double* __restrict__ w, int64_t cpb,
                                                 double* __restrict__ colsq_part) {
-  constexpr int VN = Vec16<T>::N;
+  constexpr int VN = VB / (int)sizeof(T);
   constexpr int COLS = ColsFor<ITERS>::value;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         const int r0 = (it * kWave + lane) * VN;
-        load16<ACC>(a + (r0 < m ? r0 : 0), e[c][it]);
+        loadv<VB>(a + (r0 < m ? r0 : 0), e[c][it]);
       }
     }
 #pragma unroll
@@ -134,10 +137,12 @@ __global__ __launch_bounds__(256) void k_colsq_gen(const T* __restrict__ A, int6
 
 namespace {
 
-template <typename T, typename ACC, bool COLSQ>
+// ev0/ev1 (nullable): events stamped by the dispatch itself around the kernel.
+template <typename T, typename ACC, bool COLSQ, int VB>
 hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
-                       double* colsq_part, int* nparts, hipStream_t st) {
-  constexpr int VN = Vec16<T>::N;
+                       double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+  constexpr int VN = VB / (int)sizeof(T);
   const int need = (m + kWave * VN - 1) / (kWave * VN);
   int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
   int cols = iters <= 2 ? 8 : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1));
@@ -152,8 +157,12 @@ hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* 
   dim3 g((unsigned)nb), b(256);
 #define SSNAL_GEMV_CASE(IT)                                                                  \
   case IT:                                                                                   \
-    hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ>), g, b, 0, st, A, lda, m, n, v, w, cpb, \
-                       colsq_part);                                                          \
+    if (ev0)                                                                                 \
+      hipExtLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, ev0, ev1, 0, A, lda, \
+                            m, n, v, w, cpb, colsq_part);                                    \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, A, lda, m, n, v, w,   \
+                         cpb, colsq_part);                                                   \
     break;
   switch (iters) {
     SSNAL_GEMV_CASE(1)
@@ -181,46 +190,67 @@ hipError_t launch_gen(const T* A, int64_t lda, int m, int64_t n, const int32_t* 
   return hipGetLastError();
 }
 
-bool fast_ok(const void* A, int dtype, int64_t lda, int m) {
+// Widest vector load (16 or 8 bytes) that every column start allows, with
+// the column held in at most 16 loads per lane; 0 = the element-wise kernel.
+int fast_vb(const void* A, int dtype, int64_t lda, int m) {
   const int es = dtype_size(dtype);
-  const int vn = 16 / es;
-  if (((uintptr_t)A) % 16 != 0) return false;
-  if (lda % vn != 0) return false;
-  return m <= 16 * kWave * vn;
+  for (int vb = 16; vb >= 8; vb /= 2) {
+    if (((uintptr_t)A) % vb != 0 || (lda * es) % vb != 0) continue;
+    if (m <= 16 * kWave * (vb / es)) return vb;
+  }
+  return 0;
+}
+
+template <typename T, typename ACC, bool COLSQ>
+hipError_t launch_vb(int vb, const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
+                     double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+  if (vb == 16)
+    return launch_fast<T, ACC, COLSQ, 16>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
+  return launch_fast<T, ACC, COLSQ, 8>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
 }
 
 template <typename T>
 hipError_t dispatch(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
-                    double* w, bool acc64, bool fast, hipStream_t st) {
+                    double* w, bool acc64, int vb, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (n <= 0) return hipSuccess;
-  if (fast && !J) {
-    if (acc64) return launch_fast<T, double, false>(A, lda, m, n, v, w, nullptr, nullptr, st);
-    return launch_fast<T, float, false>(A, lda, m, n, v, w, nullptr, nullptr, st);
+  if (vb && !J) {
+    if (acc64) return launch_vb<T, double, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
+    return launch_vb<T, float, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
   }
-  if (acc64) return launch_gen<T, double>(A, lda, m, n, J, v, w, st);
-  return launch_gen<T, float>(A, lda, m, n, J, v, w, st);
+  if (ev0) {
+    hipError_t e = hipEventRecord(ev0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = acc64 ? launch_gen<T, double>(A, lda, m, n, J, v, w, st)
+                       : launch_gen<T, float>(A, lda, m, n, J, v, w, st);
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, st);
+  return e;
 }
 
 }  // namespace
 
 hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
-                  const double* v, double* w, bool acc64, hipStream_t st) {
-  const bool fast = fast_ok(A, dtype, lda, m);
+                  const double* v, double* w, bool acc64, hipStream_t st, hipEvent_t ev0,
+                  hipEvent_t ev1) {
+  const int vb = fast_vb(A, dtype, lda, m);
   switch (dtype) {
     case kF64:
-      return dispatch<double>((const double*)A, lda, m, ncols, J, v, w, true, fast, st);
+      return dispatch<double>((const double*)A, lda, m, ncols, J, v, w, true, vb, st, ev0, ev1);
     case kF32:
-      return dispatch<float>((const float*)A, lda, m, ncols, J, v, w, acc64, fast, st);
+      return dispatch<float>((const float*)A, lda, m, ncols, J, v, w, acc64, vb, st, ev0, ev1);
     case kBF16:
-      return dispatch<uint16_t>((const uint16_t*)A, lda, m, ncols, J, v, w, acc64, fast, st);
+      return dispatch<uint16_t>((const uint16_t*)A, lda, m, ncols, J, v, w, acc64, vb, st, ev0, ev1);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n, const double* v,
-                        double* w, double* colsq_part, int* nparts, hipStream_t st) {
-  if (!fast_ok(A, dtype, lda, m)) {
-    hipError_t e = gemv_t(A, dtype, lda, m, n, nullptr, v, w, true, st);
+                        double* w, double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  const int vb = fast_vb(A, dtype, lda, m);
+  if (!vb) {
+    hipError_t e = gemv_t(A, dtype, lda, m, n, nullptr, v, w, true, st, ev0, ev1);
     if (e != hipSuccess) return e;
     const int nb = 1024;
     *nparts = nb;
@@ -240,12 +270,14 @@ hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n,
   }
   switch (dtype) {
     case kF64:
-      return launch_fast<double, double, true>((const double*)A, lda, m, n, v, w, colsq_part, nparts, st);
+      return launch_vb<double, double, true>(vb, (const double*)A, lda, m, n, v, w, colsq_part,
+                                             nparts, st, ev0, ev1);
     case kF32:
-      return launch_fast<float, double, true>((const float*)A, lda, m, n, v, w, colsq_part, nparts, st);
+      return launch_vb<float, double, true>(vb, (const float*)A, lda, m, n, v, w, colsq_part, nparts,
+                                            st, ev0, ev1);
     case kBF16:
-      return launch_fast<uint16_t, double, true>((const uint16_t*)A, lda, m, n, v, w, colsq_part,
-                                                 nparts, st);
+      return launch_vb<uint16_t, double, true>(vb, (const uint16_t*)A, lda, m, n, v, w, colsq_part,
+                                               nparts, st, ev0, ev1);
   }
   return hipErrorInvalidValue;
 }

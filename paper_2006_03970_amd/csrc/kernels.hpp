@@ -13,12 +13,15 @@ inline int dtype_size(int dt) { return dt == kF64 ? 8 : (dt == kF32 ? 4 : 2); }
 // ---- A^T v  (k_gemv.hip) -------------------------------------------------
 // w[k] = sum_i A[i, col(k)] v[i], col(k) = J ? J[k] : k, k < ncols.
 // acc64: accumulate in FP64 (always for F64 storage); else FP32.
+// ev0/ev1 (nullable): timing events, stamped by the kernel dispatch itself
+// (hipExtLaunchKernel) so that their interval is the kernel's duration.
 hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
-                  const double* v, double* w, bool acc64, hipStream_t st);
+                  const double* v, double* w, bool acc64, hipStream_t st,
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Same pass also accumulating sum_j ||a_j||^2 into colsq (FP64, one value).
 hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n,
                         const double* v, double* w, double* colsq_part, int* nparts,
-                        hipStream_t st);
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- vector passes over n  (k_vec.hip) -----------------------------------
 struct ProxArgs {

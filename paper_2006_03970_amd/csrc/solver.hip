@@ -190,7 +190,12 @@ struct Timer {
   hipStream_t st;
   bool on;
   int used = 0;
-  int rec_start() {
+  std::vector<char> tags;  // 1 = the Newton A^T d pass, 0 = any other A^T v pass
+  hipEvent_t e0 = nullptr, e1 = nullptr;  // the pair for the next timed launch
+  // Hand out the next event pair (nulls when timing is off); the launch
+  // stamps them around the kernel.
+  int next(int tag = 0) {
+    e0 = e1 = nullptr;
     if (!on) return 0;
     if ((size_t)(2 * used + 2) > c->ev.size()) {
       for (int k = 0; k < 64; ++k) {
@@ -199,23 +204,28 @@ struct Timer {
         c->ev.push_back(e);
       }
     }
-    HIPCHK(hipEventRecord(c->ev[2 * used], st));
-    return 0;
-  }
-  int rec_stop() {
-    if (!on) return 0;
-    HIPCHK(hipEventRecord(c->ev[2 * used + 1], st));
+    e0 = c->ev[2 * used];
+    e1 = c->ev[2 * used + 1];
+    tags.push_back((char)tag);
     ++used;
     return 0;
   }
-  int total_ms(double* out) {
-    double t = 0.0;
+  // Summed durations of every timed pass, and of the tag-1 passes alone.
+  int total_ms(double* out, double* out1 = nullptr, int* n1 = nullptr) {
+    double t = 0.0, t1 = 0.0;
+    int c1 = 0;
     for (int k = 0; k < used; ++k) {
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
       t += ms;
+      if (tags[k] == 1) {
+        t1 += ms;
+        ++c1;
+      }
     }
     *out = t;
+    if (out1) *out1 = t1;
+    if (n1) *n1 = c1;
     return 0;
   }
 };
@@ -275,9 +285,8 @@ int prox_grad(const void* A, int dt, int64_t lda, const double* b, int m, int64_
 // eta, F, D from rho = A x - b (already in w.rho); q = A^T rho into w.wd.
 int certify(const void* A, int dt, int64_t lda, int m, int64_t n, const double* x, double l1,
             double l2, const Workspace& w, hipStream_t st, Timer& tm, int* gemv_calls) {
-  if (int rc = tm.rec_start()) return rc;
-  HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.rho, w.wd, true, st));
-  if (int rc = tm.rec_stop()) return rc;
+  if (int rc = tm.next()) return rc;
+  HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.rho, w.wd, true, st, tm.e0, tm.e1));
   ++*gemv_calls;
   HIPCHK(eta_pass(x, w.wd, n, l1, l2, w.part, w.scal, st));
   return 0;
@@ -344,9 +353,8 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     HIPCHK(vec_scale_copy(b, -1.0, w.y, m, st));
   }
   int nparts = 0;
-  if (int rc = tm.rec_start()) return rc;
-  HIPCHK(gemv_t_colsq(A, dt, lda, m, n, w.y, w.wy, w.part, &nparts, st));
-  if (int rc = tm.rec_stop()) return rc;
+  if (int rc = tm.next()) return rc;
+  HIPCHK(gemv_t_colsq(A, dt, lda, m, n, w.y, w.wy, w.part, &nparts, st, tm.e0, tm.e1));
   ++gemv_calls;
   HIPCHK(nonfinite_count(w.wy, n, w.scal + SC_NONFIN, w.part + 2048, st));
   std::vector<double> hb(m), hpart(nparts);
@@ -422,9 +430,8 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       if (kkt1 <= eps_in) {
         if (mixed && !o.no_refine && !refreshed) {
           // refresh A^T y with FP64 accumulation over the stored A, then re-test
-          if (int rc = tm.rec_start()) return rc;
-          HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.y, w.wy, true, st));
-          if (int rc = tm.rec_stop()) return rc;
+          if (int rc = tm.next()) return rc;
+          HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.y, w.wy, true, st, tm.e0, tm.e1));
           ++gemv_calls;
           refreshed = true;
           continue;
@@ -437,9 +444,8 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       int rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, o.no_smw ? 0 : -1, w, st);
       if (rc) return rc;
       // w_d = A^T d, the HBM pass
-      if ((rc = tm.rec_start())) return rc;
-      HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.d, w.wd, !mixed, st));
-      if ((rc = tm.rec_stop())) return rc;
+      if ((rc = tm.next(1))) return rc;
+      HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.d, w.wd, !mixed, st, tm.e0, tm.e1));
       ++gemv_calls;
       HIPCHK(linesearch(x, w.wy, w.wd, n, la, w.g, w.d, w.y, m, w.part, w.scal, st));
       pending = true;
@@ -501,9 +507,12 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     info->sigma_final = sigma;
     info->gemv_calls = gemv_calls;
     info->syncs = syncs;
-    double gms = 0.0;
-    if (int rc = tm.total_ms(&gms)) return rc;
+    double gms = 0.0, dms = 0.0;
+    int dn = 0;
+    if (int rc = tm.total_ms(&gms, &dms, &dn)) return rc;
     info->gemv_ms = gms;
+    info->atd_ms = dms;
+    info->atd_launches = dn;
     info->solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }

@@ -43,6 +43,10 @@ GEMV_CASES = [
     (500, 3001, "f32", None), (1000, 1000, "f32", None), (37, 999, "f32", 40),
     (500, 3001, "bf16", None), (1000, 1000, "bf16", None), (100, 513, "bf16", 104),
     (3000, 257, "f64", None),
+    # 8-byte loads (column stride a multiple of 8 but not of 16 bytes) and the
+    # element-wise kernel (stride not a multiple of 8 bytes)
+    (502, 1001, "f32", None), (252, 700, "bf16", None), (4000, 300, "bf16", 4004),
+    (250, 1500, "bf16", None),
 ]
 
 
