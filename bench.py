@@ -14,6 +14,15 @@ timed live with HIP events around each of its launches on the solve's stream.
 The CPU baseline is the FP64 oracle on the machine's host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Serving: a stream of requests with the serving workload's distributions (m
+log-uniform in [100, 2000], n log-uniform in [1e4, n_max], Gaussian-Toeplitz
+or SNP-like designs, FP32 or BF16 storage, tol 1e-6) goes through the
+library's serving loop: first closed-loop (all submitted at once) for the
+saturated rate, then open-loop with seeded Poisson arrivals at 0.8x that rate;
+latency is scheduled arrival -> completion.  The serving designs are drawn on
+the GPU (datagen.make_problem_device: same distributions, torch's seeded
+generator).  Default: 64 requests with n_max = 5e5 (the full stream:
+--serving 512).
 Counter runs (HBM traffic of the A^T v kernel and of a plain copy of the same
 byte count, for the calibration factor):
        python bench.py --profile-gemv K     K launches of the FP32 A^T v pass
@@ -52,6 +61,84 @@ def _traffic_from_profile(kernel_src, store):
         return None
 
 
+def serving_bench(nreq, nmax, slots, seed=7):
+    """p50/p99 latency and solves/s of the serving loop over a request stream."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+
+    reqs = datagen.serving_requests(nreq, seed=seed, n_range=(10_000, int(nmax)))
+    t0 = time.time()
+    probs = []
+    dev = torch.device("cuda:0")
+    for q in reqs:
+        p = datagen.make_problem_device(q, seed=q["seed"], store=q["store"], device=dev)
+        x = torch.empty(p["n"], dtype=torch.float64, device=dev)
+        probs.append(dict(A=p["AT"], b=p["b"], l1=p["lam1"], l2=p["lam2"], x=x, m=p["m"], n=p["n"],
+                          store=p["store"]))
+    torch.cuda.synchronize()
+    print(f"[bench] serving: generated and uploaded {nreq} requests in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    srv = binding.Server(0, hbm_budget=64 << 30, max_slots=slots)
+    try:
+        # alone: one request at a time (also the warm-up)
+        alone = []
+        for q in probs[: min(8, nreq)]:
+            t = time.perf_counter()
+            info = srv.wait(srv.submit(q["A"], q["b"], q["l1"], q["l2"], 1e-6, q["x"]))
+            alone.append(time.perf_counter() - t)
+            assert info["status"] == 0, info
+        # closed loop: everything submitted at once
+        t = time.perf_counter()
+        tickets = [srv.submit(q["A"], q["b"], q["l1"], q["l2"], 1e-6, q["x"]) for q in probs]
+        infos = [srv.wait(tk) for tk in tickets]
+        sat = nreq / (time.perf_counter() - t)
+        bad = [i["status"] for i in infos if i["status"] != 0]
+        # open loop: Poisson arrivals at 0.8x the saturated rate
+        rate = 0.8 * sat
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=nreq)
+        arrive = np.cumsum(gaps) - gaps[0]
+        lat = np.zeros(nreq)
+        pending = {}
+        start = time.perf_counter()
+        nxt = 0
+        while nxt < nreq or pending:
+            now = time.perf_counter() - start
+            while nxt < nreq and arrive[nxt] <= now:
+                q = probs[nxt]
+                pending[srv.submit(q["A"], q["b"], q["l1"], q["l2"], 1e-6, q["x"])] = nxt
+                nxt += 1
+            for tk in list(pending):
+                info = srv.poll(tk)
+                if info is not None:
+                    k = pending.pop(tk)
+                    lat[k] = time.perf_counter() - start - arrive[k]
+                    if info["status"] != 0:
+                        bad.append(info["status"])
+            time.sleep(5e-5)
+        span = time.perf_counter() - start
+    finally:
+        srv.close()
+    ms = np.array([q["m"] for q in probs])
+    ns = np.array([q["n"] for q in probs])
+    return {
+        "requests": nreq, "slots": slots, "n_range": [10_000, int(nmax)], "m_range": [100, 2000],
+        "mean_m": float(ms.mean()), "mean_n": float(ns.mean()),
+        "stores": {s: sum(1 for q in probs if q["store"] == s) for s in ("f32", "bf16")},
+        "saturated_solves_per_s": sat,
+        "poisson_rate_per_s": rate,
+        "solves_per_s": nreq / span,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_latency_ms": float(lat.mean() * 1e3),
+        "alone_latency_ms_mean": float(np.mean(alone) * 1e3),
+        "nonzero_status": bad,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +146,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=64, help="requests in the serving stream (0 = off)")
+    ap.add_argument("--serving-nmax", type=float, default=5e5)
+    ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--profile-gemv", type=int, default=0)
     ap.add_argument("--profile-copy", type=int, default=0)
     args = ap.parse_args()
@@ -185,6 +275,9 @@ def main():
             "bytes_per_launch": bpl32, "avg_launch_us": avg32 * 1e6,
         },
     }
+
+    if args.serving > 0:
+        out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -263,3 +263,65 @@ def serving_requests(count: int, seed: int = 0, m_range=(100, 2000), n_range=(10
             alpha=float(g.uniform(0.2, 0.9)), c_lam=float(g.uniform(0.05, 0.8)), tol=1e-6,
             store="f32" if g.random() < 0.5 else "bf16", seed=int(seed * 100003 + i + 1)))
     return out
+
+
+def make_problem_device(cfg: dict, seed: int, store: str, device) -> dict:
+    """The recipe of make_problem drawn on the GPU with torch's seeded
+    generator (same distributions, different random stream): for workloads
+    where only throughput is measured and no oracle compares the result, such
+    as the serving stream, whose designs (up to 1e9 entries) would take
+    minutes to draw on the host.  Returns a dict with the torch tensors AT
+    (n, m; float64, float32 or bfloat16 by `store`) and b (m, float64), and
+    m, n, store, lam1, lam2."""
+    import torch
+    m, n = int(cfg["m"]), int(cfg["n"])
+    design = cfg["design"]
+    rho, block = float(cfg.get("rho", 0.6)), int(cfg.get("block", 50))
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1_000_003 + 17)
+    f32 = torch.float32
+    if design == "gauss":
+        X = torch.randn((n, m), generator=g, device=device, dtype=f32)
+    elif design == "toeplitz":
+        X = torch.randn((n, m), generator=g, device=device, dtype=f32)
+        nb = (n + block - 1) // block
+        pad = nb * block - n
+        if pad:
+            X = torch.cat([X, torch.zeros((pad, m), device=device, dtype=f32)])
+        Xb = X.view(nb, block, m)
+        s = math.sqrt(1.0 - rho * rho)
+        for j in range(1, block):  # a_j = rho a_{j-1} + sqrt(1 - rho^2) e_j inside each block
+            Xb[:, j].mul_(s).add_(Xb[:, j - 1], alpha=rho)
+        X = X[:n]
+    elif design == "snp":
+        p = 0.05 + 0.45 * torch.rand((n, 1), generator=g, device=device, dtype=f32)
+        X = (torch.rand((n, m), generator=g, device=device, dtype=f32) < p).to(f32)
+        X += (torch.rand((n, m), generator=g, device=device, dtype=f32) < p).to(f32)
+        for _ in range(100):  # redraw constant columns
+            const = (X.amax(dim=1) == X.amin(dim=1)).nonzero().flatten()
+            if const.numel() == 0:
+                break
+            pc = p[const]
+            X[const] = ((torch.rand((const.numel(), m), generator=g, device=device) < pc).to(f32)
+                        + (torch.rand((const.numel(), m), generator=g, device=device) < pc).to(f32))
+    else:
+        raise ValueError(design)
+    X -= X.mean(dim=1, keepdim=True)
+    X /= torch.linalg.vector_norm(X, dim=1, keepdim=True)
+    k = int(cfg["k"])
+    idx = torch.randperm(n, generator=g, device=device)[:k]
+    vals = (1.0 + 2.0 * torch.rand(k, generator=g, device=device, dtype=torch.float64)) * \
+        torch.where(torch.rand(k, generator=g, device=device) < 0.5, -1.0, 1.0).to(torch.float64)
+    Ax = (X[idx].to(torch.float64).T @ vals)
+    s2 = float(Ax.var(unbiased=False)) / float(cfg["snr"])
+    b = Ax + torch.randn(m, generator=g, device=device, dtype=torch.float64) * math.sqrt(s2)
+    alpha, c_lam = float(cfg["alpha"]), float(cfg["c_lam"])
+    lam_max = float((X @ b.to(f32)).abs().max()) / alpha
+    if store == "f32":
+        AT = X.contiguous()
+    elif store == "bf16":
+        AT = X.to(torch.bfloat16).contiguous()
+    else:
+        AT = X.to(torch.float64).contiguous()
+    return dict(AT=AT, b=b.contiguous(), m=m, n=n, store=store, lam1=alpha * c_lam * lam_max,
+                lam2=(1.0 - alpha) * c_lam * lam_max)

@@ -9,7 +9,11 @@
 //     diagonal tile (FP64 matrix cores), then eliminates the stacked
 //     [diagonal tile; own tile] held in the MFMA accumulators, four columns at
 //     a time.  Every panel workgroup factors the diagonal tile itself, so no
-//     workgroup waits for another inside a launch.
+//     workgroup waits for another inside a launch.  The diagonal tile of V is
+//     therefore read by every panel workgroup and written by none: the
+//     diagonal workgroup stores L_ss in a separate buffer of diagonal blocks
+//     (a workgroup may start after another has finished, for instance when
+//     other streams' kernels hold the CUs).
 //   * the launch's remaining workgroups apply the previous step's update to
 //     the trailing tiles of columns s+1 .. T-1.
 //   * the forward substitution L z = alpha*rhs rides along: workgroup p
@@ -185,9 +189,11 @@ __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int
       }
 }
 
+// Ld: T diagonal blocks of L, 64 x 64 row-major each (block s at Ld + s*4096).
 __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N, int T, int s,
                                                    const double* __restrict__ rhs, double alpha,
-                                                   double* __restrict__ z, int* __restrict__ info) {
+                                                   double* __restrict__ z, double* __restrict__ Ld,
+                                                   int* __restrict__ info) {
   extern __shared__ double smem[];
   StepLds& L = *reinterpret_cast<StepLds*>(smem);
   const int tid = threadIdx.x;
@@ -427,18 +433,27 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
     }
   }
   // ---- write back (LF is complete after the last panel's second barrier):
-  // the diagonal workgroup writes L_ss, the others their L_{s+p,s}
+  // the diagonal workgroup writes L_ss to its block of Ld (zero outside the
+  // lower triangle of the nk x nk block), the others their L_{s+p,s} to V
   {
     const int C = tid & (kNB - 1);
     const int base = p == 0 ? 0 : kNB;
     double wv[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) wv[i] = L.u.LF[base + wid + 4 * i][C];
+    if (p == 0) {
+      double* Ls = Ld + (int64_t)s * kNB * kNB;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int R = wid + 4 * i;
-      const bool ok = p == 0 ? (R < nk && C <= R) : (R < nbr && C < nk);
-      if (ok) V[(int64_t)(b0 + R) * N + s0 + C] = wv[i];
+      for (int i = 0; i < 16; ++i) {
+        const int R = wid + 4 * i;
+        Ls[R * kNB + C] = ((R < nk) & (C <= R)) ? wv[i] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int R = wid + 4 * i;
+        if (R < nbr && C < nk) V[(int64_t)(b0 + R) * N + s0 + C] = wv[i];
+      }
     }
   }
   if (fwd && wid == 2 && lane < nk) z[s0 + lane] = zv;
@@ -455,6 +470,7 @@ constexpr int kBackWaves = kBackNT / kWave;
 constexpr int kBackPre = 24;  // rows per wave held in registers (all of them while N <= 448)
 
 __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ Lm, int N,
+                                                    const double* __restrict__ Ldg,
                                                     const double* __restrict__ z,
                                                     double* __restrict__ x) {
   extern __shared__ double sm[];
@@ -468,16 +484,12 @@ __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ L
   for (int i = tid; i < N; i += kBackNT) xs[i] = z[i];
   const int T = (N + kNB - 1) / kNB;
 
-  // diagonal block of block s, four entries per thread (row e/64, col e%64)
+  // diagonal block of block s (from the block buffer), four entries per
+  // thread (row e/64, col e%64)
   auto load_diag = [&](int s, double (&d)[4]) {
-    const int s0 = s * kNB;
-    const int nk = N - s0 < kNB ? N - s0 : kNB;
+    const double* Ls = Ldg + (int64_t)s * kNB * kNB;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * kBackNT;
-      const int r = e / kNB, c = e % kNB;
-      d[q] = Lm[(int64_t)(s0 + min(r, nk - 1)) * N + s0 + min(c, nk - 1)];
-    }
+    for (int q = 0; q < 4; ++q) d[q] = Ls[tid + q * kBackNT];
   };
     // rows s0+64+wid+16i of block column s, column s0+lane (rows past N read
   // row N-1 and are given weight 0 where they are used)
@@ -559,6 +571,19 @@ __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ L
   for (int i = tid; i < N; i += kBackNT) x[i] = xs[i];
 }
 
+// Diagonal blocks of L from the block buffer into V (lower triangles).
+__global__ __launch_bounds__(256) void k_copy_diag(double* __restrict__ V, int N,
+                                                   const double* __restrict__ Ld) {
+  const int s = blockIdx.x;
+  const int s0 = s * kNB;
+  const int nk = N - s0 < kNB ? N - s0 : kNB;
+  const double* Ls = Ld + (int64_t)s * kNB * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    if (r < nk && c <= r) V[(int64_t)(s0 + r) * N + s0 + c] = Ls[e];
+  }
+}
+
 __global__ void k_zero_upper(double* __restrict__ V, int N) {
   const int64_t tot = (int64_t)N * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
@@ -582,24 +607,27 @@ hipError_t chol_init() {
 }
 
 hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, double* z,
-                             double* x, int* info_dev, hipStream_t st) {
+                             double* x, double* Ld, int* info_dev, hipStream_t st) {
   if (N < 1 || N > 4096) return hipErrorInvalidValue;
   const int T = (N + kNB - 1) / kNB;
   for (int s = 0; s < T; ++s) {
     const int npanel = T - s;
     const int U = s >= 1 ? (T - s - 1) * (T - s) / 2 : 0;
     hipLaunchKernelGGL(k_chol_step, dim3(npanel + U), dim3(256), sizeof(StepLds), st, V, N, T, s,
-                       rhs, alpha, z, info_dev);
+                       rhs, alpha, z, Ld, info_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (!rhs) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_back, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, z, x);
+  hipLaunchKernelGGL(k_chol_back, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, Ld, z, x);
   return hipGetLastError();
 }
 
-hipError_t cholesky(double* V, int N, int* info_dev, hipStream_t st) {
-  return chol_factor_solve(V, N, nullptr, 1.0, nullptr, nullptr, info_dev, st);
+hipError_t cholesky(double* V, int N, double* Ld, int* info_dev, hipStream_t st) {
+  hipError_t e = chol_factor_solve(V, N, nullptr, 1.0, nullptr, nullptr, Ld, info_dev, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_diag, dim3((N + kNB - 1) / kNB), dim3(256), 0, st, V, N, Ld);
+  return hipGetLastError();
 }
 
 hipError_t zero_upper(double* V, int N, hipStream_t st) {

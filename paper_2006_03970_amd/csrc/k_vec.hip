@@ -623,6 +623,12 @@ __global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
   }
 }
 
+hipError_t sum_parts(const double* part, int nb, double* out, const double* y, int m,
+                     double* yy_out, hipStream_t st) {
+  hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, out, y, m, yy_out);
+  return hipGetLastError();
+}
+
 hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2, double* part,
                     double* scal, hipStream_t st) {
   const int nb = prox_blocks(n);

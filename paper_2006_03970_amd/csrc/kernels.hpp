@@ -98,19 +98,26 @@ size_t syrk_workspace_bytes(int form, int m, int64_t r);
 hipError_t syrk(const void* A, int dtype, int64_t lda, int m, const int32_t* J, int64_t r, int form,
                 double shift, double scale, double* out, void* work, hipStream_t st);
 
+// *out = sum_b part[b], b < nb; with y non-null also *yy_out = |y|^2 (m entries).
+hipError_t sum_parts(const double* part, int nb, double* out, const double* y, int m,
+                     double* yy_out, hipStream_t st);
 // *out = max_i |v_i| (part: 1024 doubles of scratch).
 hipError_t absmax(const double* v, int64_t n, double* part, double* out, hipStream_t st);
 
 // ---- Cholesky and triangular solves (k_chol.hip) --------------------------
 // Raise the dynamic LDS limits of the Cholesky kernels (once per device).
 hipError_t chol_init();
-// Factor the SPD N x N row-major V in place (lower triangle = L; the strict
-// upper triangle keeps stale values) and, when rhs is non-null, solve
-// L L^T x = alpha*rhs (z: N doubles of scratch for L^{-1} alpha rhs; x may
-// alias rhs).  info_dev (int) receives row+1 of a non-positive pivot.
+// Factor the SPD N x N row-major V (the blocks below the 64 x 64 diagonal
+// blocks of V become those of L; the diagonal blocks of L go to Ld, ceil(N/64)
+// blocks of 64 x 64 doubles, while V's diagonal blocks keep stale values) and,
+// when rhs is non-null, solve L L^T x = alpha*rhs (z: N doubles of scratch for
+// L^{-1} alpha rhs; x may alias rhs).  info_dev (int) receives row+1 of a
+// non-positive pivot.
 hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, double* z,
-                             double* x, int* info_dev, hipStream_t st);
-hipError_t cholesky(double* V, int N, int* info_dev, hipStream_t st);
+                             double* x, double* Ld, int* info_dev, hipStream_t st);
+// Factor only, with the diagonal blocks of L copied back into V (lower
+// triangle = L; the strict upper triangle keeps stale values).
+hipError_t cholesky(double* V, int N, double* Ld, int* info_dev, hipStream_t st);
 // Zero the strict upper triangle (for callers that want L alone).
 hipError_t zero_upper(double* V, int N, hipStream_t st);
 

@@ -23,6 +23,8 @@ enum Scal : int {
   SC_NONFIN = 15,  // count of non-finite entries
   SC_CHOL = 16,    // Cholesky status (0 or pivot+1), stored as double
   SC_AMAX = 17,    // max_i |v_i| (path: ||A^T b||_inf)
+  SC_COLSQ = 18,   // sum_j ||a_j||^2 (default sigma0)
+  SC_BB = 19,      // ||b||^2
   SC_DELTA = 32,   // 33 slots: line-search increments Delta_k (+ second-order sum)
   SC_BLK = 80,     // per-block partials of the m-vector finishers (<= 16 blocks x 3)
   SC_SIZE = 160

@@ -243,7 +243,9 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   if (form < 0) form = (r < m) ? 1 : 0;
   if (form == 0) {
     HIPCHK(syrk(A, dt, lda, m, J, r, 0, 1.0, kappa, w.V, w.syrk, st));
-    HIPCHK(chol_factor_solve(w.V, m, g, -1.0, w.t3, d, w.info, st));
+    // the SYRK partials are dead once V is formed: their buffer holds the
+    // diagonal blocks of L
+    HIPCHK(chol_factor_solve(w.V, m, g, -1.0, w.t3, d, (double*)w.syrk, w.info, st));
     return 0;
   }
   // (I + kappa A_J A_J^T)^{-1} = I - A_J (I/kappa + A_J^T A_J)^{-1} A_J^T
@@ -253,7 +255,7 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   double* q = w.t2;
   HIPCHK(gemv_t(A, dt, lda, m, r, J, g, v, true, st));
   HIPCHK(syrk(A, dt, lda, m, J, r, 1, 1.0 / kappa, 1.0, w.V, w.syrk, st));
-  HIPCHK(chol_factor_solve(w.V, N, v, 1.0, w.t3, q, w.info, st));
+  HIPCHK(chol_factor_solve(w.V, N, v, 1.0, w.t3, q, (double*)w.syrk, w.info, st));
   HIPCHK(gather_gemv_partial(A, dt, lda, m, J, q, nullptr, r, w.gpart, st));
   HIPCHK(gather_finish(w.gpart, nullptr, r, m, 1, nullptr, nullptr, const_cast<double*>(g), d, w.scal,
                        st));
@@ -356,14 +358,12 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   if (int rc = tm.next()) return rc;
   HIPCHK(gemv_t_colsq(A, dt, lda, m, n, w.y, w.wy, w.part, &nparts, st, tm.e0, tm.e1));
   ++gemv_calls;
+  // sum_j |a_j|^2 (for the default sigma0) and |b|^2, reduced on the device
+  // and read back with the scalar slots (no pageable host copies)
+  HIPCHK(sum_parts(w.part, nparts, w.scal + SC_COLSQ, b, m, w.scal + SC_BB, st));
   HIPCHK(nonfinite_count(w.wy, n, w.scal + SC_NONFIN, w.part + 2048, st));
-  std::vector<double> hb(m), hpart(nparts);
-  HIPCHK(hipMemcpyAsync(hb.data(), b, m * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(hpart.data(), w.part, nparts * 8, hipMemcpyDeviceToHost, st));
   if (int rc = readback(c, w, st, &syncs)) return rc;
-  double normb2 = 0.0, colsq = 0.0;
-  for (int i = 0; i < m; ++i) normb2 += hb[i] * hb[i];
-  for (int k = 0; k < nparts; ++k) colsq += hpart[k];
+  const double normb2 = hs[SC_BB], colsq = hs[SC_COLSQ];
   if (!std::isfinite(normb2)) return fail(SSNAL_ENONFINITE, "b holds non-finite entries");
   if (hs[SC_NONFIN] != 0.0)
     return fail(SSNAL_ENONFINITE, "A^T (A x0 - b) holds %g non-finite entries (non-finite A?)",
@@ -374,6 +374,8 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     const double mean = colsq / (double)n;
     sigma = 2.5 / (mean > 0.0 ? mean : 1.0);
   }
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(SSNAL_EINVAL, "sigma0 = %g is not a positive number", sigma);
   c->last_sigma0 = sigma;
 
   double kkt1 = INFINITY, kkt3 = INFINITY, eta = INFINITY, F = NAN, D = NAN;
@@ -982,11 +984,11 @@ int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream) {
   Workspace ws;
   if (int rc = prepare(ctx, N, 1, ws)) return rc;
   HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int), stream));
-  HIPCHK(cholesky(V, (int)N, ws.info, stream));
+  HIPCHK(cholesky(V, (int)N, (double*)ws.syrk, ws.info, stream));
   HIPCHK(zero_upper(V, (int)N, stream));
+  if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
   int hinfo = 0;
-  HIPCHK(hipMemcpyAsync(&hinfo, ws.info, sizeof(int), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  std::memcpy(&hinfo, &ctx->h_scal[SC_CHOL], sizeof(int));
   if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
   return 0;
 }
@@ -1005,9 +1007,9 @@ int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, i
   HIPCHK(hipMemsetAsync(ws.info, 0, sizeof(int), stream));
   if (int rc = newton_direction(A, (int)a_dtype, lda, (int)m, J, r, kappa, g, d, form, ws, stream))
     return rc;
+  if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
   int hinfo = 0;
-  HIPCHK(hipMemcpyAsync(&hinfo, ws.info, sizeof(int), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  std::memcpy(&hinfo, &ctx->h_scal[SC_CHOL], sizeof(int));
   if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
   return 0;
 }

@@ -192,3 +192,72 @@ def test_server_admission_budget(gpu):
     finally:
         small.close()
     torch.cuda.synchronize()
+
+
+def test_concurrent_solves_bitwise(gpu):
+    """Sixteen requests of the serving workload's shapes solved by four host
+    threads at once (own context and stream each) and through a four-slot
+    server equal the solves run alone, bit for bit.  Regression test for a
+    race in which a Cholesky panel workgroup dispatched late (other streams
+    holding the CUs) read a diagonal tile already overwritten by the
+    factor."""
+    import threading
+    import datagen
+    import torch
+    _say("concurrent solves")
+    dev = torch.device("cuda:0")
+    reqs = datagen.serving_requests(16, seed=7, m_range=(100, 700), n_range=(20_000, 200_000))
+    probs = [datagen.make_problem_device(q, seed=q["seed"], store=q["store"], device=dev) for q in reqs]
+    torch.cuda.synchronize()
+    ctx = gpu.Context(0)
+    alone = []
+    for p in probs:
+        x, info = gpu.ssnal_en_solve(ctx, p["AT"], p["b"], p["lam1"], p["lam2"], tol=1e-6)
+        assert info["status"] == 0, info
+        alone.append(x.clone())
+    torch.cuda.synchronize()
+    outs = [None] * len(probs)
+    errs = []
+    nxt = [0]
+    lock = threading.Lock()
+
+    def worker():
+        c = gpu.Context(0)
+        st = torch.cuda.Stream(device=dev)
+        while True:
+            with lock:
+                i = nxt[0]
+                nxt[0] += 1
+            if i >= len(probs):
+                return
+            p = probs[i]
+            with torch.cuda.stream(st):
+                x = torch.empty(p["n"], dtype=torch.float64, device=dev)
+                try:
+                    gpu.ssnal_en_solve(c, p["AT"], p["b"], p["lam1"], p["lam2"], tol=1e-6, x_out=x,
+                                       stream=st)
+                    st.synchronize()
+                    outs[i] = x
+                except gpu.SsnalError as e:
+                    errs.append((i, str(e)))
+
+    threads = [threading.Thread(target=worker) for _ in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    for i, xa in enumerate(alone):
+        assert bool((outs[i] == xa).all()), i
+    xs = [torch.full((p["n"],), float("nan"), dtype=torch.float64, device=dev) for p in probs]
+    torch.cuda.synchronize()
+    srv = gpu.Server(0, hbm_budget=16 << 30, max_slots=4)
+    try:
+        tickets = [srv.submit(p["AT"], p["b"], p["lam1"], p["lam2"], 1e-6, x) for p, x in zip(probs, xs)]
+        assert all(srv.wait(t)["status"] == 0 for t in tickets)
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    for i, xa in enumerate(alone):
+        assert bool((xs[i] == xa).all()), i
