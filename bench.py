@@ -61,6 +61,55 @@ def _traffic_from_profile(kernel_src, store):
         return None
 
 
+def large_bench(reps=3):
+    """The m=1000, n=1e6 Gaussian single solve with A stored in FP32, BF16 and
+    FP64: solves/s and the A^T d bandwidth for each."""
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+
+    t0 = time.time()
+    p = datagen.make_problem("c3", seed=1, store="f32", want_f64=False)
+    print(f"[bench] c3 generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    b = vec_to_device(p.b)
+    out = {"workload": "Gaussian elastic net, m=1000, n=1000000, k=50, snr=3, alpha=0.5, "
+                       "c_lambda=0.1, tol=1e-6"}
+    for store in ("f32", "bf16", "f64"):
+        if store == "f32":
+            A = design_to_device(p.AT, "f32")
+        elif store == "bf16":
+            A = design_to_device(datagen.f32_to_bf16_bits(p.AT), "bf16")
+        else:
+            A = design_to_device(p.AT.astype("float64"), "f64")
+        opts = binding.make_opts(timing=1)
+        x = torch.empty(p.n, dtype=torch.float64, device=A.device)
+        binding.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, x_out=x, opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = []
+        for _ in range(reps):
+            _, info = binding.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, x_out=x, opts=opts,
+                                             stream=stream)
+            infos.append(info)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / reps
+        s_a = {"f32": 4, "bf16": 2, "f64": 8}[store]
+        atd_s = sum(i["atd_ms"] for i in infos) / sum(i["atd_launches"] for i in infos) / 1e3
+        out[store] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                      "eta": infos[-1]["kkt_rel"], "status": infos[-1]["status"],
+                      "iterations": [infos[-1]["outer_iters"], infos[-1]["newton_iters"]],
+                      "nnz": infos[-1]["nnz"],
+                      "atd_gbs": float(p.m) * p.n * s_a / atd_s / 1e9, "atd_us": atd_s * 1e6}
+        print(f"[bench] c3 {store}: {out[store]['ms_per_solve']:.1f} ms/solve", file=sys.stderr, flush=True)
+        del A
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(nreq, nmax, slots, seed=7):
     """p50/p99 latency and solves/s of the serving loop over a request stream."""
     import numpy as np
@@ -146,6 +195,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the m=1000, n=1e6 single-solve section")
     ap.add_argument("--serving", type=int, default=64, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-nmax", type=float, default=5e5)
     ap.add_argument("--serving-slots", type=int, default=4)
@@ -276,6 +326,8 @@ def main():
         },
     }
 
+    if not args.no_c3:
+        out["large_single_solve"] = large_bench()
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
 
