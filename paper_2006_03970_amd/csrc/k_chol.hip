@@ -7,7 +7,7 @@
 //   * panel workgroups p = 0 .. T-s-1 own row block s+p of column s.  Each
 //     applies the previous step's rank-64 update to its own tile and to the
 //     diagonal tile (FP64 matrix cores), then eliminates the stacked
-//     [diagonal tile; own tile] held in the MFMA accumulators, four columns at
+//     [diagonal tile; own tile] held in the MFMA accumulators, eight columns at
 //     a time.  Every panel workgroup factors the diagonal tile itself, so no
 //     workgroup waits for another inside a launch.  The diagonal tile of V is
 //     therefore read by every panel workgroup and written by none: the
@@ -140,8 +140,9 @@ struct StepLds {
     } st;
     double LF[2 * kNB][kBP];  // factor of the stacked [diagonal tile; own tile]
   } u;
-  double PN[2 * kNB][5];      // current 4-column panel
+  double PN[2 * kNB][9];      // current 8-column panel
   double zprev[kNB];          // z_{s-1}
+  int bad;                    // first non-positive pivot of the current panel, or -1
   double zrow[kNB];           // right-hand side of block s after the previous updates
 };
 
@@ -320,113 +321,148 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
     if (wid == 2) zv = L.zrow[lane];
   }
 
-  // ---- elimination, four columns at a time.  Per panel: the owners write the
-  // four columns to PN; every thread factors the 4 x 4 pivot block itself and
-  // the first 128 threads solve their row of S against it into LF; then the
-  // rank-4 update of the accumulators right of the panel.  Rows of the
-  // diagonal tile above the pivot block get zeros in LF, so the strict upper
-  // triangle never feeds a later column.
+  // ---- elimination, eight columns at a time.  Per panel: the owners write
+  // the eight columns to PN; the row-solving waves (0 and 1, plus wave 2 of
+  // the diagonal workgroup for the forward substitution) factor the 8 x 8
+  // pivot block themselves and the first 128 threads solve their row of S
+  // against it into LF; then the rank-8 update of the accumulators right of
+  // the panel.  Rows of the diagonal tile above the pivot block get zeros in
+  // LF, so the strict upper triangle never feeds a later column.
+  // Look-ahead: after a panel only the column block of the next panel is
+  // updated at once; the panel's updates of the blocks beyond are issued after
+  // the next panel's first barrier, where the MFMAs of the waves that hold
+  // the own tile run while waves 0 and 1 factor.
+  constexpr int kPW = 8;  // panel width
+  const bool factors = wid < 2 || (fwd && wid == 2);
+  int prev_j0 = -1, prev_cbn = 4;  // the previous panel's blocks > prev_cbn are still to update
+  auto panel_update = [&](int pj0, int cb_lo, int cb_hi) {
+    // S[rows of this wave][blocks cb_lo..cb_hi] -= L_panel(rows) L_panel(block rows)^T
+#pragma unroll
+    for (int kh = 0; kh < kPW; kh += 4) {
+      const int kr = pj0 + kh + lane / 16;
+      double a[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) a[rb] = -L.u.LF[32 * wid + 16 * rb + (lane & 15)][kr];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        if (cb < cb_lo || cb > cb_hi) continue;
+        const double bv = L.u.LF[16 * cb + (lane & 15)][kr];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          if (in_b || cb <= 2 * wid + rb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, acc[rb][cb], 0, 0, 0);
+      }
+    }
+  };
 #pragma unroll
   for (int cbp = 0; cbp < 4; ++cbp) {
-    for (int sub = 0; sub < 16; sub += 4) {
+    for (int sub = 0; sub < 16; sub += kPW) {
       const int j0 = 16 * cbp + sub;
       const int cc = (lane & 15) - sub;
-      if (cc >= 0 && cc < 4) {
+      if (cc >= 0 && cc < kPW) {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) L.PN[32 * wid + 16 * rb + lane / 16 + 4 * v][cc] = acc[rb][cbp][v];
       }
       __syncthreads();
-      // 4 x 4 pivot block, factored redundantly by every thread (same bits everywhere)
-      double l[4][4], rl[4];
-      int bad = -1;
+      // deferred updates of the previous panel (blocks this panel's extract did not need)
+      if (live && prev_j0 >= 0 && prev_cbn < 3) panel_update(prev_j0, prev_cbn + 1, 3);
+      double zz[kPW];
+      if (factors) {
+        // 8 x 8 pivot block, factored redundantly by each factoring thread
+        // (same bits everywhere).  Every LDS value the panel needs -- the
+        // pivot block and the thread's own row -- is read first, in one round
+        // trip; l[i][k] replaces the entry it came from.
+        double l[kPW][kPW], rl[kPW], a[kPW];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double t = L.PN[j0 + k][k];
+        for (int i = 0; i < kPW; ++i)
 #pragma unroll
-        for (int q = 0; q < k; ++q) t = fma(-l[k][q], l[k][q], t);
-        if (!(t >= kMinPivot) && bad < 0) bad = k;
-        const double y = rsqrt_pos(t);
-        rl[k] = y;
-        l[k][k] = t * y;
+          for (int k = 0; k <= i; ++k) l[i][k] = L.PN[j0 + i][k];
 #pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-          double u = L.PN[j0 + i][k];
+        for (int k = 0; k < kPW; ++k) a[k] = L.PN[tid < 2 * kNB ? tid : 2 * kNB - 1][k];
+        __builtin_amdgcn_sched_barrier(0);
+        int bad = -1;
 #pragma unroll
-          for (int q = 0; q < k; ++q) u = fma(-l[i][q], l[k][q], u);
-          l[i][k] = u * y;
-        }
-      }
-      if (bad >= 0) {  // every thread saw the same pivots: a uniform exit
-        if (tid == 0 && p == 0) *info = s0 + j0 + bad + 1;
-        return;
-      }
-      if (tid < 2 * kNB) {
-        const int R = tid;
-        double x[4];
-        if (R >= kNB || R >= j0 + 4) {
-          // row below the pivot block: x L^T = a
+        for (int k = 0; k < kPW; ++k) {
+          double t = l[k][k];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            double u = L.PN[R][k];
+          for (int q = 0; q < k; ++q) t = fma(-l[k][q], l[k][q], t);
+          if (!(t >= kMinPivot) && bad < 0) bad = k;
+          const double y = rsqrt_pos(t);
+          rl[k] = y;
+          l[k][k] = t * y;
 #pragma unroll
-            for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
-            x[k] = u * rl[k];
-          }
-        } else {
-          // row of the pivot block (its L row) or above it (zeros)
-          const int r = R - j0;
+          for (int i = k + 1; i < kPW; ++i) {
+            double u = l[i][k];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            double e = 0.0;
-#pragma unroll
-            for (int i = k; i < 4; ++i) e = r == i ? l[i][k] : e;
-            x[k] = e;
+            for (int q = 0; q < k; ++q) u = fma(-l[i][q], l[k][q], u);
+            l[i][k] = u * y;
           }
         }
+        if (tid == 0) L.bad = bad;
+        if (tid < 2 * kNB && bad < 0) {
+          const int R = tid;
+          double x[kPW];
+          if (R >= kNB || R >= j0 + kPW) {
+            // row below the pivot block: x L^T = a
 #pragma unroll
-        for (int k = 0; k < 4; ++k) L.u.LF[R][j0 + k] = x[k];
-      }
-      double zz[4];
-      if (fwd && wid == 2) {
-        // z entries of the pivot rows: L_pivot zz = (residual rhs of rows j0..j0+3)
+            for (int k = 0; k < kPW; ++k) {
+              double u = a[k];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          double u = readlane_d(zv, j0 + k);
+              for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
+              x[k] = u * rl[k];
+            }
+          } else {
+            // row of the pivot block (its L row) or above it (zeros)
+            const int r = R - j0;
 #pragma unroll
-          for (int q = 0; q < k; ++q) u = fma(-l[k][q], zz[q], u);
-          zz[k] = u * rl[k];
+            for (int k = 0; k < kPW; ++k) {
+              double e = 0.0;
+#pragma unroll
+              for (int i = k; i < kPW; ++i) e = r == i ? l[i][k] : e;
+              x[k] = e;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kPW; ++k) L.u.LF[R][j0 + k] = x[k];
+        }
+        if (fwd && wid == 2) {
+          // z entries of the pivot rows: L_pivot zz = (residual rhs of rows j0..j0+7)
+#pragma unroll
+          for (int k = 0; k < kPW; ++k) {
+            double u = readlane_d(zv, j0 + k);
+#pragma unroll
+            for (int q = 0; q < k; ++q) u = fma(-l[k][q], zz[q], u);
+            zz[k] = u * rl[k];
+          }
         }
       }
       __syncthreads();
-      // rank-4 update of column blocks cbp..3: S -= L_panel L_panel(cols)^T
-      if (live) {
-        const int kr = j0 + lane / 16;
-        double a[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) a[rb] = -L.u.LF[32 * wid + 16 * rb + (lane & 15)][kr];
-#pragma unroll
-        for (int cb = cbp; cb < 4; ++cb) {
-          const double bv = L.u.LF[16 * cb + (lane & 15)][kr];
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
-            if (in_b || cb <= 2 * wid + rb)
-              acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, acc[rb][cb], 0, 0, 0);
+      {
+        const int bad = L.bad;
+        if (bad >= 0) {  // a uniform exit: every thread read the same flag
+          if (tid == 0 && p == 0) *info = s0 + j0 + bad + 1;
+          return;
         }
       }
+      // the column block of the next panel at once; the blocks beyond later
+      const int cbn = sub + kPW < 16 ? cbp : cbp + 1;
+      if (live && cbn < 4) panel_update(j0, cbn, cbn);
+      prev_j0 = j0;
+      prev_cbn = cbn;
       if (fwd && wid == 2) {
-        // rows below the pivot rows lose L[row][j0..j0+3] zz; pivot rows take zz
+        // rows below the pivot rows lose L[row][j0..j0+7] zz; pivot rows take zz
         const int rel = lane - j0;
-        if (rel >= 4) {
+        if (rel >= kPW) {
           double u = zv;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) u = fma(-L.u.LF[lane][j0 + k], zz[k], u);
+          for (int k = 0; k < kPW; ++k) u = fma(-L.u.LF[lane][j0 + k], zz[k], u);
           zv = u;
         } else if (rel >= 0) {
           double e = zz[0];
 #pragma unroll
-          for (int k = 1; k < 4; ++k) e = rel == k ? zz[k] : e;
+          for (int k = 1; k < kPW; ++k) e = rel == k ? zz[k] : e;
           zv = e;
         }
       }
