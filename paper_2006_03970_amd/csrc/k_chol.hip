@@ -382,13 +382,13 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
 #pragma unroll
         for (int k = 0; k < kPW; ++k) a[k] = L.PN[tid < 2 * kNB ? tid : 2 * kNB - 1][k];
         __builtin_amdgcn_sched_barrier(0);
-        int bad = -1;
+        uint64_t badk = 0;  // bit k: pivot k not positive (wave-uniform)
 #pragma unroll
         for (int k = 0; k < kPW; ++k) {
           double t = l[k][k];
 #pragma unroll
           for (int q = 0; q < k; ++q) t = fma(-l[k][q], l[k][q], t);
-          if (!(t >= kMinPivot) && bad < 0) bad = k;
+          badk |= (uint64_t)(__builtin_amdgcn_ballot_w64(!(t >= kMinPivot)) != 0) << k;
           const double y = rsqrt_pos(t);
           rl[k] = y;
           l[k][k] = t * y;
@@ -400,32 +400,25 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
             l[i][k] = u * y;
           }
         }
+        const int bad = badk ? __builtin_ctzll(badk) : -1;
         if (tid == 0) L.bad = bad;
         if (tid < 2 * kNB && bad < 0) {
+          // x L^T = a.  For a row of the pivot block this recomputes its L row
+          // with the same operations in the same order, so the entries on or
+          // left of the diagonal equal l bit for bit; the entries right of it
+          // (and whole rows above the pivot block) are zeroed.
           const int R = tid;
+          const int r = R >= kNB ? kPW : R - j0;  // last kept column (>= kPW: all)
           double x[kPW];
-          if (R >= kNB || R >= j0 + kPW) {
-            // row below the pivot block: x L^T = a
 #pragma unroll
-            for (int k = 0; k < kPW; ++k) {
-              double u = a[k];
+          for (int k = 0; k < kPW; ++k) {
+            double u = a[k];
 #pragma unroll
-              for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
-              x[k] = u * rl[k];
-            }
-          } else {
-            // row of the pivot block (its L row) or above it (zeros)
-            const int r = R - j0;
-#pragma unroll
-            for (int k = 0; k < kPW; ++k) {
-              double e = 0.0;
-#pragma unroll
-              for (int i = k; i < kPW; ++i) e = r == i ? l[i][k] : e;
-              x[k] = e;
-            }
+            for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
+            x[k] = u * rl[k];
           }
 #pragma unroll
-          for (int k = 0; k < kPW; ++k) L.u.LF[R][j0 + k] = x[k];
+          for (int k = 0; k < kPW; ++k) L.u.LF[R][j0 + k] = k <= r ? x[k] : 0.0;
         }
         if (fwd && wid == 2) {
           // z entries of the pivot rows: L_pivot zz = (residual rhs of rows j0..j0+7)
