@@ -28,6 +28,8 @@
 // circuit conditions: a guarded load becomes a branch that waits for it), and
 // pivots use the hardware reciprocal-square-root estimate refined by Newton
 // steps instead of a correctly rounded sqrt and divide.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -190,10 +192,43 @@ __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int
       }
 }
 
+// W = L^{-1} for a full 64 x 64 lower-triangular block (row-major, zero
+// strict upper triangle), written row-major with zeros above the diagonal.
+// Wave 0 holds column j of W in lane j and eliminates right-looking: the
+// unknown of row k is final once the rows above have updated it, then it
+// updates the rows below with column k of L (broadcast from LDS).
+__device__ __forceinline__ void invert_block(const double* __restrict__ Ls, double* __restrict__ Ws,
+                                             StepLds& L) {
+  const int tid = threadIdx.x;
+  double(*A)[kBP] = L.u.LF;
+#pragma unroll
+  for (int q = 0; q < kNB * kNB / 256; ++q) {
+    const int e = tid + 256 * q;
+    A[e / kNB][e % kNB] = Ls[e];
+  }
+  __syncthreads();
+  if (wave_id() != 0) return;
+  const int j = tid;
+  double w[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) w[i] = i == j ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < kNB; ++k) {
+    w[k] *= rcp_nr(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < kNB; ++i) w[i] = fma(-A[i][k], w[k], w[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) Ws[i * kNB + j] = w[i];
+}
+
 // Ld: T diagonal blocks of L, 64 x 64 row-major each (block s at Ld + s*4096).
+// Wd (null: none): inverses of the diagonal blocks; launch s >= 1 inverts
+// block s-1 (finished by the previous launch) in one extra workgroup.
 __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N, int T, int s,
                                                    const double* __restrict__ rhs, double alpha,
                                                    double* __restrict__ z, double* __restrict__ Ld,
+                                                   double* __restrict__ Wd,
                                                    int* __restrict__ info) {
   extern __shared__ double smem[];
   StepLds& L = *reinterpret_cast<StepLds*>(smem);
@@ -204,8 +239,13 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
   const int s0 = s * kNB;
 
   if ((int)blockIdx.x >= npanel) {
+    const int q = (int)blockIdx.x - npanel;
+    if (q == (T - s - 1) * (T - s) / 2) {  // past the trailing tiles: the inverse
+      invert_block(Ld + (int64_t)(s - 1) * kNB * kNB, Wd + (int64_t)(s - 1) * kNB * kNB, L);
+      return;
+    }
     int ii, ll;
-    tri_of((int)blockIdx.x - npanel, ii, ll);
+    tri_of(q, ii, ll);
     trailing_tile(V, N, s, s + 1 + ii, s + 1 + ll, L);
     return;
   }
@@ -490,110 +530,197 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
 
 // Backward substitution L^T x = z by one workgroup of 1024 threads, left-
 // looking by blocks of 64 rows from the last: block s needs
-// c_s = sum_{r below} L[r][s0 + j] x_r (lanes = the 64 columns j, the 16
-// waves take interleaved rows, so every load reads whole rows of L), then
-// wave 0 solves L_ss^T x_s = z_s - c_s four rows at a time.  Block s-1's rows
-// and diagonal block are loaded while block s is solved.
+// c_s = sum_{r below} L[r][s0 + j] x_r, then solves L_ss^T x_s = z_s - c_s.
+// The waves split into two roles with the same barriers:
+//   * waves 1..15 ("loaders") hold the rows below block s in registers (each
+//     load instruction covers W rows of 64/W lanes, W doubles a lane: W = 2
+//     for 16-byte loads when the row pitch allows), form the partial sums of
+//     c_s, then issue the loads of block s-1 (rows and diagonal block) so they
+//     travel while block s is solved, and stage the diagonal block in the
+//     second LDS buffer;
+//   * wave 0 ("solver") sums the partials and solves the 64 x 64 triangle in
+//     eight 8 x 8 steps: the eight unknowns of a step come from a short
+//     chain on broadcast values, then one rank-8 update of the remaining
+//     right-hand sides (lanes = rows of L^T).
+// Disjoint roles keep each role's registers to itself.
 constexpr int kBackNT = 1024;
 constexpr int kBackWaves = kBackNT / kWave;
-constexpr int kBackPre = 24;  // rows per wave held in registers (all of them while N <= 448)
+constexpr int kBackLW = kBackWaves - 1;  // loader waves
+constexpr int kBackRegs = 32;             // doubles of L a loader thread holds (480 rows)
 
+template <int W>
 __global__ __launch_bounds__(1024) void k_chol_back(const double* __restrict__ Lm, int N,
                                                     const double* __restrict__ Ldg,
+                                                    const double* __restrict__ Wdg,
                                                     const double* __restrict__ z,
                                                     double* __restrict__ x) {
   extern __shared__ double sm[];
-  const int xsz = (N + 1) & ~1;
-  double* xs = sm;                                                   // N
-  double(*Ld)[kBP] = reinterpret_cast<double(*)[kBP]>(sm + xsz);      // 64 x 65
-  double(*cp)[kNB] = reinterpret_cast<double(*)[kNB]>(sm + xsz + kNB * kBP);  // 16 x 64
+  const int T = (N + kNB - 1) / kNB;
+  const int xsz = kNB * T + 2;  // x, then zeros: rows past N read x = 0
+  double* xs = sm;
+  double(*Ld)[kNB][kBP] = reinterpret_cast<double(*)[kNB][kBP]>(sm + xsz);      // 2 x 64 x 65
+  double(*cp)[kNB] = reinterpret_cast<double(*)[kNB]>(sm + xsz + 2 * kNB * kBP);  // 16 x 64
+  double* rs = sm + xsz + 2 * kNB * kBP + kBackWaves * kNB;  // 64 reciprocal pivots
   const int tid = threadIdx.x;
   const int wid = wave_id();
   const int lane = tid & (kWave - 1);
-  for (int i = tid; i < N; i += kBackNT) xs[i] = z[i];
-  const int T = (N + kNB - 1) / kNB;
+  for (int i = tid; i < xsz; i += kBackNT) {
+    const double zi = z[min(i, N - 1)];
+    xs[i] = i < N ? zi : 0.0;
+  }
 
-  // diagonal block of block s (from the block buffer), four entries per
-  // thread (row e/64, col e%64)
-  auto load_diag = [&](int s, double (&d)[4]) {
-    const double* Ls = Ldg + (int64_t)s * kNB * kNB;
+  if (wid > 0) {
+    // ------------------------------------------------------------ loaders
+    constexpr int kLPR = kNB / W;          // lanes per row
+    constexpr int kR = kBackRegs / W;      // rounds held in registers
+    constexpr int kDiag = (kNB * kNB / W + kBackLW * kWave - 1) / (kBackLW * kWave);
+    typedef typename std::conditional<W == 2, double2, double>::type VT;
+    const int lt = tid - kWave;            // 0 .. 959
+    const int wv = wid - 1;
+    const int grp = lane / kLPR, cc = lane % kLPR;
+    // row of round i of block s: rb + W * kBackLW * i, rb = first row of this
+    // thread below block s (kept opaque so the rounds' offsets stay constants)
+    auto first_row = [&](int s) {
+      int rb = s * kNB + kNB + W * wv + grp;
+      asm volatile("" : "+v"(rb));
+      return rb;
+    };
+    // row r, columns of block s (clamped into the matrix: rows past N and the
+    // columns of a partial last block are loaded but never used)
+    auto ld = [&](int r, int s) -> VT {
+      return *reinterpret_cast<const VT*>(Lm + (int64_t)min(r, N - 1) * N + min(s * kNB + W * cc, N - W));
+    };
+    VT bv[kR], dg[kDiag];
+    auto load_diag = [&](int s) {  // L_ss for the last block, W_s = L_ss^{-1} for the others
+      const VT* Ls = reinterpret_cast<const VT*>((s == T - 1 ? Ldg : Wdg) + (int64_t)s * kNB * kNB);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) d[q] = Ls[tid + q * kBackNT];
-  };
-    // rows s0+64+wid+16i of block column s, column s0+lane (rows past N read
-  // row N-1 and are given weight 0 where they are used)
-  auto load_below = [&](int s, double (&b)[kBackPre]) {
-    const int s0 = s * kNB;
-    const int c = min(s0 + lane, N - 1);
+      for (int q = 0; q < kDiag; ++q) dg[q] = Ls[min(lt + q * kBackLW * kWave, kNB * kNB / W - 1)];
+    };
+    auto store_diag = [&](int s) {
+      double(*D)[kBP] = Ld[s & 1];
 #pragma unroll
-    for (int i = 0; i < kBackPre; ++i) {
-      const int r = s0 + kNB + wid + kBackWaves * i;
-      b[i] = Lm[(int64_t)min(r, N - 1) * N + c];
-    }
-  };
-  double dv[4], bv[kBackPre];
-  load_diag(T - 1, dv);
-  load_below(T - 1, bv);
-  for (int s = T - 1; s >= 0; --s) {
-    const int s0 = s * kNB;
-    const int nk = N - s0 < kNB ? N - s0 : kNB;
-    __syncthreads();  // x of every block below is in xs; Ld and cp are free
-    // c_s, partial over this wave's rows (x_r for rows past N is multiplied by 0)
-    {
-      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < kDiag; ++q) {
+        const int e = lt + q * kBackLW * kWave;  // element group: row e / kLPR, columns W (e % kLPR)..
+        if (e < kNB * kNB / W) {
+          const double* d = reinterpret_cast<const double*>(&dg[q]);
 #pragma unroll
-      for (int i = 0; i < kBackPre; ++i) {
-        const int r = s0 + kNB + wid + kBackWaves * i;
-        const double xr = xs[min(r, N - 1)];
-        t[i & 3] = fma(bv[i], r < N ? xr : 0.0, t[i & 3]);
-      }
-      for (int r = s0 + kNB + wid + kBackWaves * kBackPre; r < N; r += kBackWaves)
-        t[0] = fma(Lm[(int64_t)r * N + s0 + lane], xs[r], t[0]);
-      cp[wid][lane] = (t[0] + t[1]) + (t[2] + t[3]);
-    }
-    double dcur[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dcur[q] = dv[q];
-    if (s > 0) {
-      load_diag(s - 1, dv);
-      load_below(s - 1, bv);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * kBackNT;
-      const int r = e / kNB, c = e % kNB;
-      Ld[r][c] = ((r < nk) & (c <= r)) ? dcur[q] : 0.0;
-    }
-    __syncthreads();
-    if (wid == 0) {
-      double c = 0.0;
-#pragma unroll
-      for (int w = 0; w < kBackWaves; ++w) c += cp[w][lane];
-      double v = lane < nk ? xs[s0 + lane] - c : 0.0;
-      const double rinv = lane < nk ? rcp_nr(Ld[lane][lane]) : 0.0;
-#pragma unroll
-      for (int b4 = kNB - 4; b4 >= 0; b4 -= 4) {
-        double col[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) col[k] = Ld[b4 + k][lane];
-        double xx[4];
-#pragma unroll
-        for (int k = 3; k >= 0; --k) {
-          double u = readlane_d(v, b4 + k);
-#pragma unroll
-          for (int q = k + 1; q < 4; ++q) u = fma(-Ld[b4 + q][b4 + k], xx[q], u);
-          xx[k] = u * readlane_d(rinv, b4 + k);
+          for (int w = 0; w < W; ++w) D[e / kLPR][W * (e % kLPR) + w] = d[w];
         }
-        const int rel = lane - b4;
-        double upd = v;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) upd = fma(-col[k], xx[k], upd);
-        double own = xx[0];
-#pragma unroll
-        for (int k = 1; k < 4; ++k) own = rel == k ? xx[k] : own;
-        v = rel < 0 ? upd : (rel < 4 ? own : v);
       }
-      if (lane < nk) xs[s0 + lane] = v;
+    };
+    // rounds of block s holding rows of the matrix for this wave (uniform)
+    auto rounds = [&](int s) {
+      const int left = N - (s * kNB + kNB + W * wv);
+      return left > 0 ? (left + W * kBackLW - 1) / (W * kBackLW) : 0;
+    };
+    load_diag(T - 1);
+    store_diag(T - 1);
+    for (int s = T - 1; s >= 0; --s) {
+      __syncthreads();  // A: x of every block below s is in xs
+      const int rb = first_row(s);
+      const int nr = rounds(s);
+      double t[2][W];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int w = 0; w < W; ++w) t[h][w] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kR; ++i) {
+        if (i < nr) {
+          const double xr = xs[min(rb + W * kBackLW * i, N)];
+          const double* b = reinterpret_cast<const double*>(&bv[i]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) t[i & 1][w] = fma(b[w], xr, t[i & 1][w]);
+        }
+      }
+      // rows past the registers (N > 544): four loads in flight at a time
+      for (int i = kR; i < nr; i += 4) {
+        VT b4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b4[u] = ld(rb + W * kBackLW * (i + u), s);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double xr = xs[min(rb + W * kBackLW * (i + u), N)];
+          const double* b = reinterpret_cast<const double*>(&b4[u]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) t[u & 1][w] = fma(b[w], xr, t[u & 1][w]);
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        double v = t[0][w] + t[1][w];
+        if (W == 2) v += __shfl_xor(v, 32);
+        if (grp == 0) cp[wid][W * cc + w] = v;
+      }
+      __syncthreads();  // B: partials in cp
+      if (s > 0) {
+        // block s-1 travels while block s is solved
+        const int rb1 = first_row(s - 1);
+        const int nr1 = min(rounds(s - 1), kR);
+#pragma unroll
+        for (int i = 0; i < kR; ++i)
+          if (i < nr1) bv[i] = ld(rb1 + W * kBackLW * i, s - 1);
+        __builtin_amdgcn_sched_barrier(0);  // the rows go out first
+        load_diag(s - 1);
+        store_diag(s - 1);
+      }
+    }
+  } else {
+    // ------------------------------------------------------------ solver
+    for (int s = T - 1; s >= 0; --s) {
+      __syncthreads();  // A: L_ss in Ld[s & 1], x of every block below s in xs
+      const int s0 = s * kNB;
+      const int nk = N - s0 < kNB ? N - s0 : kNB;
+      double(*D)[kBP] = Ld[s & 1];
+      const bool last = s == T - 1;
+      if (last) rs[lane] = lane < nk ? rcp_nr(D[lane][lane]) : 0.0;  // read back by this wave only
+      const double zs = xs[s0 + lane];
+      __syncthreads();  // B: partials in cp
+      double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int w = 1; w < kBackWaves; ++w) c[w & 3] += cp[w][lane];
+      double v = lane < nk ? zs - ((c[0] + c[1]) + (c[2] + c[3])) : 0.0;
+      if (!last) {
+        // full block below the last: x_s = W_s^T r with W_s = L_ss^{-1} in D
+        rs[lane] = v;  // r, broadcast through LDS (this wave only)
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < kNB; ++i) a[i & 3] = fma(D[i][lane], rs[i], a[i & 3]);
+        xs[s0 + lane] = (a[0] + a[1]) + (a[2] + a[3]);
+        continue;
+      }
+#pragma unroll
+      for (int j0 = kNB - 8; j0 >= 0; j0 -= 8) {
+        // every LDS value of the step first (one round trip), then the chain
+        double uu[8][8], col[8], ri[8];
+#pragma unroll
+        for (int q = 1; q < 8; ++q)
+#pragma unroll
+          for (int k = 0; k < q; ++k) uu[q][k] = D[j0 + q][j0 + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ri[k] = rs[j0 + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) col[k] = D[j0 + k][lane];
+        double u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = readlane_d(v, j0 + k);
+        __builtin_amdgcn_sched_barrier(0);
+        // right-looking: each new unknown updates the ones before it and the
+        // rows above the step (lane = row of L^T), so only one FMA and one
+        // multiply separate consecutive unknowns
+        double xx[8];
+#pragma unroll
+        for (int q = 7; q >= 0; --q) {
+          xx[q] = u[q] * ri[q];
+#pragma unroll
+          for (int k = q - 1; k >= 0; --k) u[k] = fma(-uu[q][k], xx[q], u[k]);
+          v = fma(-col[q], xx[q], v);
+        }
+        if (lane == 0) {  // past nk these are zeros, which xs keeps past N
+#pragma unroll
+          for (int k = 0; k < 8; ++k) xs[s0 + j0 + k] = xx[k];
+        }
+      }
     }
   }
   __syncthreads();
@@ -624,14 +751,18 @@ __global__ void k_zero_upper(double* __restrict__ V, int N) {
 
 // ---------------------------------------------------------------- launchers
 static size_t back_lds(int N) {
-  return sizeof(double) * ((size_t)((N + 1) & ~1) + kNB * kBP + kBackWaves * kNB);
+  return sizeof(double) *
+         ((size_t)kNB * ((N + kNB - 1) / kNB) + 2 + 2 * kNB * kBP + kBackWaves * kNB + kNB);
 }
 
 hipError_t chol_init() {
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_step,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, sizeof(StepLds));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_chol_back, hipFuncAttributeMaxDynamicSharedMemorySize,
+  e = hipFuncSetAttribute((const void*)k_chol_back<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)back_lds(4096));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_chol_back<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)back_lds(4096));
 }
 
@@ -639,16 +770,23 @@ hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, 
                              double* x, double* Ld, int* info_dev, hipStream_t st) {
   if (N < 1 || N > 4096) return hipErrorInvalidValue;
   const int T = (N + kNB - 1) / kNB;
+  double* Wd = rhs ? Ld + (int64_t)T * kNB * kNB : nullptr;
   for (int s = 0; s < T; ++s) {
     const int npanel = T - s;
     const int U = s >= 1 ? (T - s - 1) * (T - s) / 2 : 0;
-    hipLaunchKernelGGL(k_chol_step, dim3(npanel + U), dim3(256), sizeof(StepLds), st, V, N, T, s,
-                       rhs, alpha, z, Ld, info_dev);
+    const int inv = rhs && s >= 1 ? 1 : 0;  // inverse of diagonal block s-1
+    hipLaunchKernelGGL(k_chol_step, dim3(npanel + U + inv), dim3(256), sizeof(StepLds), st, V, N,
+                       T, s, rhs, alpha, z, Ld, Wd, info_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (!rhs) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_back, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, Ld, z, x);
+  // 16-byte loads need even rows and 16-byte aligned bases
+  const bool v2 = N % 2 == 0 && ((uintptr_t)V & 15) == 0 && ((uintptr_t)Ld & 15) == 0;
+  if (v2)
+    hipLaunchKernelGGL(k_chol_back<2>, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, Ld, Wd, z, x);
+  else
+    hipLaunchKernelGGL(k_chol_back<1>, dim3(1), dim3(kBackNT), back_lds(N), st, V, N, Ld, Wd, z, x);
   return hipGetLastError();
 }
 

@@ -108,11 +108,12 @@ hipError_t absmax(const double* v, int64_t n, double* part, double* out, hipStre
 // Raise the dynamic LDS limits of the Cholesky kernels (once per device).
 hipError_t chol_init();
 // Factor the SPD N x N row-major V (the blocks below the 64 x 64 diagonal
-// blocks of V become those of L; the diagonal blocks of L go to Ld, ceil(N/64)
-// blocks of 64 x 64 doubles, while V's diagonal blocks keep stale values) and,
-// when rhs is non-null, solve L L^T x = alpha*rhs (z: N doubles of scratch for
-// L^{-1} alpha rhs; x may alias rhs).  info_dev (int) receives row+1 of a
-// non-positive pivot.
+// blocks of V become those of L; the diagonal blocks of L go to Ld, T =
+// ceil(N/64) blocks of 64 x 64 doubles, while V's diagonal blocks keep stale
+// values) and, when rhs is non-null, solve L L^T x = alpha*rhs (z: N doubles
+// of scratch for L^{-1} alpha rhs; x may alias rhs; Ld then holds 2T blocks,
+// the second T for the inverses of the diagonal blocks).  info_dev (int)
+// receives row+1 of a non-positive pivot.
 hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, double* z,
                              double* x, double* Ld, int* info_dev, hipStream_t st);
 // Factor only, with the diagonal blocks of L copied back into V (lower

@@ -154,7 +154,10 @@ def test_cholesky_not_pd(gpu, ctx):
 # ----------------------------------------------------------------- Newton direction
 DIR_CASES = [(100, 2000, 76, "f64"), (100, 2000, 150, "f64"), (500, 5000, 208, "f64"),
              (500, 5000, 700, "f64"), (500, 5000, 60, "f64"), (300, 3000, 299, "f64"),
-             (500, 5000, 208, "f32"), (500, 5000, 700, "bf16"), (40, 300, 0, "f64")]
+             (500, 5000, 208, "f32"), (500, 5000, 700, "bf16"), (40, 300, 0, "f64"),
+             # systems past 544 rows (backward substitution streams rows it cannot
+             # hold), even and odd orders
+             (1000, 4000, 900, "f64"), (999, 4000, 901, "f64")]
 
 
 @pytest.mark.parametrize("m,n,r,store", DIR_CASES)
