@@ -623,6 +623,25 @@ __global__ __launch_bounds__(kNT) void k_eta(const double* __restrict__ x,
   }
 }
 
+// Copy n scalars to coherent pinned host memory, then raise the host-visible
+// sequence flag: the stores, a system-scope fence, then the flag with release
+// semantics, so a host that observes the flag reads the new scalars.
+__global__ __launch_bounds__(256) void k_publish(const double* __restrict__ s, int n,
+                                                 double* __restrict__ dst,
+                                                 unsigned long long* __restrict__ flag,
+                                                 unsigned long long seq) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = s[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t publish_scalars(const double* scal, int n, double* host_dst, unsigned long long* host_flag,
+                           unsigned long long seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, st, scal, n, host_dst, host_flag, seq);
+  return hipGetLastError();
+}
+
 hipError_t sum_parts(const double* part, int nb, double* out, const double* y, int m,
                      double* yy_out, hipStream_t st) {
   hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, out, y, m, yy_out);

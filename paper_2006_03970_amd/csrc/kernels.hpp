@@ -99,6 +99,11 @@ hipError_t syrk(const void* A, int dtype, int64_t lda, int m, const int32_t* J, 
                 double shift, double scale, double* out, void* work, hipStream_t st);
 
 // *out = sum_b part[b], b < nb; with y non-null also *yy_out = |y|^2 (m entries).
+// Copy n scalars from the device to coherent pinned host memory (host_dst,
+// host_flag: mapped host pointers) and then set *host_flag = seq; a host
+// thread that sees the new seq may read host_dst.
+hipError_t publish_scalars(const double* scal, int n, double* host_dst, unsigned long long* host_flag,
+                           unsigned long long seq, hipStream_t st);
 hipError_t sum_parts(const double* part, int nb, double* out, const double* y, int m,
                      double* yy_out, hipStream_t st);
 // *out = max_i |v_i| (part: 1024 doubles of scratch).

@@ -58,7 +58,9 @@ struct DevBuf {
 struct ssnal_ctx {
   int device = 0;
   DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal;
-  double* h_scal = nullptr;  // pinned, SC_SIZE doubles
+  double* h_scal = nullptr;  // coherent pinned: SC_SIZE doubles, then the publish flag
+  double* d_scal = nullptr;  // the same memory as the device addresses it
+  unsigned long long pub_seq = 0;
   std::vector<hipEvent_t> ev;
   bool chol_ready = false;
   double last_sigma0 = 0.0;  // sigma0 of the last solve (after defaults)
@@ -167,11 +169,39 @@ int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
   return 0;
 }
 
-// Copy the scalar slots back and wait for the stream.
+// Bring the scalar slots to the host once the stream has produced them.  A
+// one-workgroup kernel writes them into coherent pinned memory and raises a
+// sequence flag; the host spins on the flag (the stream's work before it is
+// then complete), which avoids a copy launch and the wake-up latency of a
+// stream synchronisation.  After kSpinLimit the host falls back to
+// hipStreamSynchronize; errors of the stream are picked up by hipStreamQuery
+// while spinning.
 int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
-  HIPCHK(hipMemcpyAsync(c->h_scal, w.scal, SC_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  constexpr auto kSpinLimit = std::chrono::microseconds(2000);
+  constexpr auto kQueryEvery = std::chrono::microseconds(100);
+  unsigned long long* flag = reinterpret_cast<unsigned long long*>(c->h_scal + SC_SIZE);
+  const unsigned long long seq = ++c->pub_seq;
+  HIPCHK(publish_scalars(w.scal, SC_SIZE, c->d_scal,
+                         reinterpret_cast<unsigned long long*>(c->d_scal + SC_SIZE), seq, st));
   if (syncs) ++*syncs;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto tq = t0;
+  for (;;) {
+    if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return 0;
+    const auto t = std::chrono::steady_clock::now();
+    if (t - t0 > kSpinLimit) break;
+    if (t - tq > kQueryEvery) {
+      tq = t;
+      const hipError_t e = hipStreamQuery(st);
+      if (e != hipSuccess && e != hipErrorNotReady)
+        return fail(SSNAL_EHIP, "stream error: %s", hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq)
+    return fail(SSNAL_EHIP, "scalar readback: flag %llu after the stream finished, expected %llu",
+                (unsigned long long)*flag, seq);
   return 0;
 }
 
@@ -216,6 +246,7 @@ struct Timer {
     int c1 = 0;
     for (int k = 0; k < used; ++k) {
       float ms = 0.0f;
+      HIPCHK(hipEventSynchronize(c->ev[2 * k + 1]));  // readbacks do not wait for events
       HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
       t += ms;
       if (tags[k] == 1) {
@@ -563,11 +594,14 @@ int ssnal_ctx_create(int device, ssnal_ctx** out) {
     return rc;
   }
   if (hipMemset(c->scal.p, 0, c->scal.bytes) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_scal, SC_SIZE * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_scal, (SC_SIZE + 1) * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->d_scal, c->h_scal, 0) != hipSuccess ||
       chol_init() != hipSuccess) {
     ssnal_ctx_destroy(c);
     return fail(SSNAL_EHIP, "context initialisation failed");
   }
+  std::memset(c->h_scal, 0, (SC_SIZE + 1) * sizeof(double));  // publish flag 0: nothing yet
   *out = c;
   return 0;
 }
