@@ -76,44 +76,52 @@ __device__ __forceinline__ void tri_of(int t, int& i, int& j) {
   j = t - r * (r + 1) / 2;
 }
 
-// Load the 64 x 64 block of V at rows i0.., cols k0.. (256 threads, 16 each;
-// thread t holds entry e = t + 256q as (e / 64, e % 64)).  Addresses are
-// clamped into the matrix, so every load is issued unconditionally; entries
-// outside the matrix are zeroed by mask_tile once every load of the phase is
-// in flight (a select right after its load would wait for it).
-__device__ __forceinline__ void load_tile(const double* __restrict__ V, int N, int i0, int k0,
-                                          double (&v)[16]) {
+// Cholesky step workgroups have 512 threads: four "VALU" waves (0..3) and
+// four "MFMA" waves (4..7), one of each per SIMD, so the matrix-core updates
+// of the MFMA waves run while the VALU waves factor and solve (an MFMA holds
+// up the issue of its own wave, not of the other wave on its SIMD).
+constexpr int kStepNT = 512;
+
+// Load the 64 x 64 block of V at rows i0, cols k0 with NT threads (thread t
+// holds entry e = t + NT q as (e / 64, e % 64)).  Addresses are clamped into
+// the matrix, so every load is issued unconditionally; entries outside the
+// matrix are zeroed by mask_tile once every load of the phase is in flight (a
+// select right after its load would wait for it).
+template <int NT>
+__device__ __forceinline__ void load_tile(const double* __restrict__ V, int N, int i0, int k0, int t,
+                                          double (&v)[kNB * kNB / NT]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + q * 256;
+  for (int q = 0; q < kNB * kNB / NT; ++q) {
+    const int e = t + q * NT;
     const int i = i0 + e / kNB, k = k0 + e % kNB;
     v[q] = V[(int64_t)min(i, N - 1) * N + min(k, N - 1)];
   }
 }
-__device__ __forceinline__ void mask_tile(int N, int i0, int k0, double (&v)[16]) {
+template <int NT>
+__device__ __forceinline__ void mask_tile(int N, int i0, int k0, int t, double (&v)[kNB * kNB / NT]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + q * 256;
+  for (int q = 0; q < kNB * kNB / NT; ++q) {
+    const int e = t + q * NT;
     const int i = i0 + e / kNB, k = k0 + e % kNB;
     v[q] = ((i < N) & (k < N)) ? v[q] : 0.0;
   }
 }
 // Store a block loaded by load_tile transposed: dst[k][i].
-__device__ __forceinline__ void store_t(const double (&v)[16], double (*dst)[kBP]) {
+template <int NT>
+__device__ __forceinline__ void store_t(const double (&v)[kNB * kNB / NT], int t, double (*dst)[kBP]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + q * 256;
+  for (int q = 0; q < kNB * kNB / NT; ++q) {
+    const int e = t + q * NT;
     dst[e % kNB][e / kNB] = v[q];
   }
 }
 
 // C[i][j] = sum_k P[k][i] Q[k][j] for the 64 x 64 tile, with P, Q staged by
-// store_t.  Wave w owns rows 32*(w>>1).., columns 32*(w&1)..; FP64 MFMA
+// store_t.  Wave w < 4 owns rows 32*(w>>1).., columns 32*(w&1)..; FP64 MFMA
 // 16x16x4, whose accumulator v holds row lane/16 + 4*v, column lane%16.
-__device__ __forceinline__ void mfma_64(double (*P)[kBP], double (*Q)[kBP], dbl4 acc[2][2]) {
+__device__ __forceinline__ void mfma_64(double (*P)[kBP], double (*Q)[kBP], dbl4 acc[2][2], int w) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = wave_id();
-  const int wi = wid >> 1, wj = wid & 1;
+  const int wi = w >> 1, wj = w & 1;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -152,34 +160,39 @@ struct StepLds {
 // column lane%16 of block (rb, cb).
 typedef dbl4 Acc[2][4];
 
-// Trailing update of step s-1 on tile (i, l): V_il -= L_{i,s-1} L_{l,s-1}^T.
+// Trailing update of step s-1 on tile (i, l): V_il -= L_{i,s-1} L_{l,s-1}^T
+// (all waves load, waves 0..3 multiply).
 __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int s, int i, int l,
                                               StepLds& L) {
-  const int lane = threadIdx.x & (kWave - 1);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
   const int wid = wave_id();
-  const int wi = wid >> 1, wj = wid & 1;
+  const int wi = (wid & 3) >> 1, wj = wid & 1;
   const int k0 = (s - 1) * kNB;
-  double pv[16], qv[16], ov[2][2][4];
-  load_tile(V, N, i * kNB, k0, pv);
-  load_tile(V, N, l * kNB, k0, qv);
+  double pv[kNB * kNB / kStepNT], qv[kNB * kNB / kStepNT], ov[2][2][4];
+  load_tile<kStepNT>(V, N, i * kNB, k0, tid, pv);
+  load_tile<kStepNT>(V, N, l * kNB, k0, tid, qv);
+  if (wid < 4) {
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = i * kNB + wi * 32 + p * 16 + (lane / 16) + 4 * v;
-        const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
-        ov[p][q][v] = V[(int64_t)min(r, N - 1) * N + min(c, N - 1)];
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int r = i * kNB + wi * 32 + p * 16 + (lane / 16) + 4 * v;
+          const int c = l * kNB + wj * 32 + q * 16 + (lane & 15);
+          ov[p][q][v] = V[(int64_t)min(r, N - 1) * N + min(c, N - 1)];
+        }
+  }
   __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
-  mask_tile(N, i * kNB, k0, pv);
-  mask_tile(N, l * kNB, k0, qv);
-  store_t(pv, L.u.st.P);
-  store_t(qv, L.u.st.Q);
+  mask_tile<kStepNT>(N, i * kNB, k0, tid, pv);
+  mask_tile<kStepNT>(N, l * kNB, k0, tid, qv);
+  store_t<kStepNT>(pv, tid, L.u.st.P);
+  store_t<kStepNT>(qv, tid, L.u.st.Q);
   __syncthreads();
+  if (wid >= 4) return;
   dbl4 acc[2][2];
-  mfma_64(L.u.st.P, L.u.st.Q, acc);
+  mfma_64(L.u.st.P, L.u.st.Q, acc, wid);
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -193,43 +206,87 @@ __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int
 }
 
 // W = L^{-1} for a full 64 x 64 lower-triangular block (row-major, zero
-// strict upper triangle), written row-major with zeros above the diagonal.
-// Wave 0 holds column j of W in lane j and eliminates right-looking: the
-// unknown of row k is final once the rows above have updated it, then it
-// updates the rows below with column k of L (broadcast from LDS).
+// strict upper triangle), written row-major with zeros above the diagonal,
+// by 2 x 2 blocks of 32: W11 = L11^{-1} and W22 = L22^{-1} by waves 0 and 1
+// at once (lane j holds column j and eliminates right-looking: the unknown of
+// row k is final once the rows above have updated it, then it updates the
+// rows below with column k of L, broadcast from LDS), then
+// W21 = -W22 (L21 W11) by all waves, two entries a thread per product.
 __device__ __forceinline__ void invert_block(const double* __restrict__ Ls, double* __restrict__ Ws,
                                              StepLds& L) {
+  constexpr int kH = kNB / 2;
   const int tid = threadIdx.x;
-  double(*A)[kBP] = L.u.LF;
+  const int wid = wave_id();
+  double(*A)[kBP] = L.u.LF;             // L
+  double(*WI)[kBP] = L.u.LF + kNB;      // W
+  double(*Tm)[kH + 1] = reinterpret_cast<double(*)[kH + 1]>(&L.PN[0][0]);  // L21 W11
 #pragma unroll
-  for (int q = 0; q < kNB * kNB / 256; ++q) {
-    const int e = tid + 256 * q;
+  for (int q = 0; q < kNB * kNB / kStepNT; ++q) {
+    const int e = tid + kStepNT * q;
     A[e / kNB][e % kNB] = Ls[e];
+    WI[e / kNB][e % kNB] = 0.0;
   }
   __syncthreads();
-  if (wave_id() != 0) return;
-  const int j = tid;
-  double w[kNB];
+  if (wid < 2) {
+    const int o = kH * wid;                    // diagonal block of this wave
+    const int j = threadIdx.x & (kH - 1);      // column within it (lanes 32..63 repeat 0..31)
+    double w[kH];
 #pragma unroll
-  for (int i = 0; i < kNB; ++i) w[i] = i == j ? 1.0 : 0.0;
+    for (int i = 0; i < kH; ++i) w[i] = i == j ? 1.0 : 0.0;
 #pragma unroll
-  for (int k = 0; k < kNB; ++k) {
-    w[k] *= rcp_nr(A[k][k]);
+    for (int k = 0; k < kH; ++k) {
+      w[k] *= rcp_nr(A[o + k][o + k]);
 #pragma unroll
-    for (int i = k + 1; i < kNB; ++i) w[i] = fma(-A[i][k], w[k], w[i]);
+      for (int i = k + 1; i < kH; ++i) w[i] = fma(-A[o + i][o + k], w[k], w[i]);
+    }
+    if ((threadIdx.x & (kWave - 1)) < kH) {
+#pragma unroll
+      for (int i = 0; i < kH; ++i) WI[o + i][o + j] = w[i];
+    }
   }
+  __syncthreads();
+  const int ti = tid / (kH / 2), tj = 2 * (tid % (kH / 2));  // row, first of two columns
+  {
+    // Tm = L21 W11 (W11 lower: only k >= column contributes)
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kH; ++k) {
+      const double a = A[kH + ti][k];
+      t0 = fma(a, WI[k][tj], t0);
+      t1 = fma(a, WI[k][tj + 1], t1);
+    }
+    Tm[ti][tj] = t0;
+    Tm[ti][tj + 1] = t1;
+  }
+  __syncthreads();
+  {
+    // W21 = -W22 Tm (W22 lower: only k <= row contributes)
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kH; ++k) {
+      const double a = WI[kH + ti][kH + k];
+      t0 = fma(a, Tm[k][tj], t0);
+      t1 = fma(a, Tm[k][tj + 1], t1);
+    }
+    WI[kH + ti][tj] = -t0;
+    WI[kH + ti][tj + 1] = -t1;
+  }
+  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < kNB; ++i) Ws[i * kNB + j] = w[i];
+  for (int q = 0; q < kNB * kNB / kStepNT; ++q) {
+    const int e = tid + kStepNT * q;
+    Ws[e] = WI[e / kNB][e % kNB];
+  }
 }
 
 // Ld: T diagonal blocks of L, 64 x 64 row-major each (block s at Ld + s*4096).
 // Wd (null: none): inverses of the diagonal blocks; launch s >= 1 inverts
 // block s-1 (finished by the previous launch) in one extra workgroup.
-__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N, int T, int s,
-                                                   const double* __restrict__ rhs, double alpha,
-                                                   double* __restrict__ z, double* __restrict__ Ld,
-                                                   double* __restrict__ Wd,
-                                                   int* __restrict__ info) {
+__global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, int N, int T, int s,
+                                                       const double* __restrict__ rhs, double alpha,
+                                                       double* __restrict__ z, double* __restrict__ Ld,
+                                                       double* __restrict__ Wd,
+                                                       int* __restrict__ info) {
   extern __shared__ double smem[];
   StepLds& L = *reinterpret_cast<StepLds*>(smem);
   const int tid = threadIdx.x;
@@ -251,23 +308,30 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
   }
 
   // ---- panel workgroup p: row block s+p of column s.  The stacked matrix
-  // S = [diagonal tile; own tile] (128 x 64) lives in MFMA accumulators:
-  // wave w owns row blocks 2w, 2w+1 (rows 32w..32w+31 of S) x 4 column blocks.
-  // Waves 0, 1 hold the diagonal tile ("D"), waves 2, 3 the own tile ("B");
-  // of D only the blocks on or below the diagonal are kept up to date.
+  // S = [diagonal tile; own tile] (128 x 64) lives in the accumulators of the
+  // MFMA waves: MFMA wave mw = wid - 4 owns row blocks 2mw, 2mw+1 (rows
+  // 32mw..32mw+31 of S) x 4 column blocks.  MFMA waves 0, 1 hold the
+  // diagonal tile ("D"), 2, 3 the own tile ("B"); of D only the blocks on or
+  // below the diagonal are kept up to date.  VALU wave 0 solves the rows of
+  // D, VALU wave 1 those of B, VALU wave 2 of the diagonal workgroup carries
+  // the forward substitution.
   const int p = blockIdx.x;
   const int b0 = (s + p) * kNB;
   const int nk = N - s0 < kNB ? N - s0 : kNB;  // width of column s
   const int nbr = p == 0 ? 0 : (N - b0 < kNB ? N - b0 : kNB);
-  const bool in_b = wid >= 2;
-  const bool live = !in_b || p > 0;
-  const bool fwd = rhs != nullptr && p == 0;  // wave 2 solves block s of L z = rhs
+  const bool vw = wid < 4;
+  const int mw = wid - 4;
+  const bool in_b = mw >= 2;
+  const bool live = !vw && (!in_b || p > 0);
+  const bool fwd = rhs != nullptr && p == 0;  // VALU wave 2 solves block s of L z = rhs
 
-  // ---- every global load first: previous-step factors, right-hand side, S
-  double pv[16], qv[16];
-  if (s > 0) {
-    load_tile(V, N, s0, s0 - kNB, pv);
-    if (p > 0) load_tile(V, N, b0, s0 - kNB, qv);
+  // ---- every global load first: previous-step factors (VALU waves),
+  // right-hand side (VALU wave 0), S (MFMA waves)
+  constexpr int kPT = kNB * kNB / 256;  // tile entries a VALU thread loads
+  double pv[kPT], qv[kPT];
+  if (s > 0 && vw) {
+    load_tile<256>(V, N, s0, s0 - kNB, tid, pv);
+    if (p > 0) load_tile<256>(V, N, b0, s0 - kNB, tid, qv);
   }
   double zp = 0.0, zc = 0.0;
   if (rhs && tid < kNB) {
@@ -277,51 +341,55 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
     zc = g < N ? r0 : 0.0;
   }
   Acc acc;
+  if (!vw) {
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int R = 32 * wid + 16 * rb + lane / 16 + 4 * v;
-        const int C = 16 * cb + (lane & 15);
-        double x = 0.0;
-        if (!in_b) {
-          if (cb <= 2 * wid + rb) x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
-        } else if (p > 0) {
-          x = V[(int64_t)(b0 + min(R - kNB, nbr - 1)) * N + s0 + min(C, nk - 1)];
+        for (int v = 0; v < 4; ++v) {
+          const int R = 32 * mw + 16 * rb + lane / 16 + 4 * v;
+          const int C = 16 * cb + (lane & 15);
+          double x = 0.0;
+          if (!in_b) {
+            if (cb <= 2 * mw + rb) x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
+          } else if (p > 0) {
+            x = V[(int64_t)(b0 + min(R - kNB, nbr - 1)) * N + s0 + min(C, nk - 1)];
+          }
+          acc[rb][cb][v] = x;
         }
-        acc[rb][cb][v] = x;
-      }
-  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
-  // the diagonal tile keeps its lower triangle and gets identity padding; the
-  // own tile is zero outside the matrix
+    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
+    // the diagonal tile keeps its lower triangle and gets identity padding;
+    // the own tile is zero outside the matrix
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int R = 32 * wid + 16 * rb + lane / 16 + 4 * v;
-        const int C = 16 * cb + (lane & 15);
-        const double x = acc[rb][cb][v];
-        acc[rb][cb][v] = !in_b ? (((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0))
-                               : (((R - kNB < nbr) & (C < nk)) ? x : 0.0);
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int R = 32 * mw + 16 * rb + lane / 16 + 4 * v;
+          const int C = 16 * cb + (lane & 15);
+          const double x = acc[rb][cb][v];
+          acc[rb][cb][v] = !in_b ? (((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0))
+                                 : (((R - kNB < nbr) & (C < nk)) ? x : 0.0);
+        }
+  }
 
   if (s > 0) {
     // previous step's rank-64 update: S -= [L_{s,s-1}; L_{s+p,s-1}] L_{s,s-1}^T
-    mask_tile(N, s0, s0 - kNB, pv);
-    store_t(pv, L.u.st.P);
-    if (p > 0) {
-      mask_tile(N, b0, s0 - kNB, qv);
-      store_t(qv, L.u.st.Q);
+    if (vw) {
+      mask_tile<256>(N, s0, s0 - kNB, tid, pv);
+      store_t<256>(pv, tid, L.u.st.P);
+      if (p > 0) {
+        mask_tile<256>(N, b0, s0 - kNB, tid, qv);
+        store_t<256>(qv, tid, L.u.st.Q);
+      }
     }
     if (rhs && tid < kNB) L.zprev[tid] = zp;
     __syncthreads();
     if (live) {
       double(*Ls)[kBP] = in_b ? L.u.st.Q : L.u.st.P;
-      const int rbase = in_b ? 32 * wid - kNB : 32 * wid;
+      const int rbase = in_b ? 32 * mw - kNB : 32 * mw;
 #pragma unroll 4
       for (int ks = 0; ks < kNB; ks += 4) {
         const int kr = ks + lane / 16;
@@ -334,12 +402,12 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb)
-            if (in_b || cb <= 2 * wid + rb)
+            if (in_b || cb <= 2 * mw + rb)
               acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
       }
     }
     if (rhs && tid < kNB) {
-      // rhs block s+p loses L_{s+p,s-1} z_{s-1} (wave 0, the lightest in the update)
+      // rhs block s+p loses L_{s+p,s-1} z_{s-1} (VALU wave 0, beside the MFMAs)
       double(*Lp)[kBP] = p > 0 ? L.u.st.Q : L.u.st.P;
       double t = 0.0;
 #pragma unroll 8
@@ -355,25 +423,25 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
       L.zrow[tid] = zc;
     }
   }
-  double zv = 0.0;  // wave 2 of the diagonal workgroup: residual rhs of row `lane` of block s
+  double zv = 0.0;  // VALU wave 2 of the diagonal workgroup: residual rhs of row `lane` of block s
   if (fwd) {
     __syncthreads();
     if (wid == 2) zv = L.zrow[lane];
   }
 
-  // ---- elimination, eight columns at a time.  Per panel: the owners write
-  // the eight columns to PN; the row-solving waves (0 and 1, plus wave 2 of
-  // the diagonal workgroup for the forward substitution) factor the 8 x 8
-  // pivot block themselves and the first 128 threads solve their row of S
-  // against it into LF; then the rank-8 update of the accumulators right of
-  // the panel.  Rows of the diagonal tile above the pivot block get zeros in
-  // LF, so the strict upper triangle never feeds a later column.
-  // Look-ahead: after a panel only the column block of the next panel is
-  // updated at once; the panel's updates of the blocks beyond are issued after
-  // the next panel's first barrier, where the MFMAs of the waves that hold
-  // the own tile run while waves 0 and 1 factor.
+  // ---- elimination, eight columns at a time.  Per panel: the MFMA waves
+  // write their rows of the eight columns to PN; the row-solving VALU waves
+  // (0, 1 of a workgroup with an own tile, 2 for the forward substitution)
+  // factor the 8 x 8 pivot block themselves, wave 0 solves the 64 rows of D
+  // and wave 1 the 64 of B against it into LF; then the MFMA waves apply the
+  // rank-8 update right of the panel.  Rows of the diagonal tile above the
+  // pivot block get zeros in LF, so the strict upper triangle never feeds a
+  // later column.  Look-ahead: after a panel only the column block of the
+  // next panel is updated at once; the panel's updates of the blocks beyond
+  // are issued after the next panel's first barrier, on the matrix cores
+  // while the VALU waves factor.
   constexpr int kPW = 8;  // panel width
-  const bool factors = wid < 2 || (fwd && wid == 2);
+  const bool factors = wid == 0 || (wid == 1 && p > 0) || (fwd && wid == 2);
   int prev_j0 = -1, prev_cbn = 4;  // the previous panel's blocks > prev_cbn are still to update
   auto panel_update = [&](int pj0, int cb_lo, int cb_hi) {
     // S[rows of this wave][blocks cb_lo..cb_hi] -= L_panel(rows) L_panel(block rows)^T
@@ -382,14 +450,14 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
       const int kr = pj0 + kh + lane / 16;
       double a[2];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) a[rb] = -L.u.LF[32 * wid + 16 * rb + (lane & 15)][kr];
+      for (int rb = 0; rb < 2; ++rb) a[rb] = -L.u.LF[32 * mw + 16 * rb + (lane & 15)][kr];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
         if (cb < cb_lo || cb > cb_hi) continue;
         const double bv = L.u.LF[16 * cb + (lane & 15)][kr];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
-          if (in_b || cb <= 2 * wid + rb)
+          if (in_b || cb <= 2 * mw + rb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, acc[rb][cb], 0, 0, 0);
       }
     }
@@ -399,11 +467,11 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
     for (int sub = 0; sub < 16; sub += kPW) {
       const int j0 = 16 * cbp + sub;
       const int cc = (lane & 15) - sub;
-      if (cc >= 0 && cc < kPW) {
+      if (live && cc >= 0 && cc < kPW) {
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) L.PN[32 * wid + 16 * rb + lane / 16 + 4 * v][cc] = acc[rb][cbp][v];
+          for (int v = 0; v < 4; ++v) L.PN[32 * mw + 16 * rb + lane / 16 + 4 * v][cc] = acc[rb][cbp][v];
       }
       __syncthreads();
       // deferred updates of the previous panel (blocks this panel's extract did not need)
@@ -414,13 +482,14 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
         // (same bits everywhere).  Every LDS value the panel needs -- the
         // pivot block and the thread's own row -- is read first, in one round
         // trip; l[i][k] replaces the entry it came from.
+        const int R = kNB * (wid & 1) + lane;  // row of S this lane solves (wave 2: rows of D)
         double l[kPW][kPW], rl[kPW], a[kPW];
 #pragma unroll
         for (int i = 0; i < kPW; ++i)
 #pragma unroll
           for (int k = 0; k <= i; ++k) l[i][k] = L.PN[j0 + i][k];
 #pragma unroll
-        for (int k = 0; k < kPW; ++k) a[k] = L.PN[tid < 2 * kNB ? tid : 2 * kNB - 1][k];
+        for (int k = 0; k < kPW; ++k) a[k] = L.PN[R][k];
         __builtin_amdgcn_sched_barrier(0);
         uint64_t badk = 0;  // bit k: pivot k not positive (wave-uniform)
 #pragma unroll
@@ -442,12 +511,11 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
         }
         const int bad = badk ? __builtin_ctzll(badk) : -1;
         if (tid == 0) L.bad = bad;
-        if (tid < 2 * kNB && bad < 0) {
+        if (wid < 2 && bad < 0) {
           // x L^T = a.  For a row of the pivot block this recomputes its L row
           // with the same operations in the same order, so the entries on or
           // left of the diagonal equal l bit for bit; the entries right of it
           // (and whole rows above the pivot block) are zeroed.
-          const int R = tid;
           const int r = R >= kNB ? kPW : R - j0;  // last kept column (>= kPW: all)
           double x[kPW];
 #pragma unroll
@@ -505,22 +573,23 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ V, int N
   // the diagonal workgroup writes L_ss to its block of Ld (zero outside the
   // lower triangle of the nk x nk block), the others their L_{s+p,s} to V
   {
+    constexpr int kWB = kNB * kWave / kStepNT;  // rows per thread
     const int C = tid & (kNB - 1);
     const int base = p == 0 ? 0 : kNB;
-    double wv[16];
+    double wv[kWB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) wv[i] = L.u.LF[base + wid + 4 * i][C];
+    for (int i = 0; i < kWB; ++i) wv[i] = L.u.LF[base + wid + 8 * i][C];
     if (p == 0) {
       double* Ls = Ld + (int64_t)s * kNB * kNB;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int R = wid + 4 * i;
+      for (int i = 0; i < kWB; ++i) {
+        const int R = wid + 8 * i;
         Ls[R * kNB + C] = ((R < nk) & (C <= R)) ? wv[i] : 0.0;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int R = wid + 4 * i;
+      for (int i = 0; i < kWB; ++i) {
+        const int R = wid + 8 * i;
         if (R < nbr && C < nk) V[(int64_t)(b0 + R) * N + s0 + C] = wv[i];
       }
     }
@@ -775,7 +844,7 @@ hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, 
     const int npanel = T - s;
     const int U = s >= 1 ? (T - s - 1) * (T - s) / 2 : 0;
     const int inv = rhs && s >= 1 ? 1 : 0;  // inverse of diagonal block s-1
-    hipLaunchKernelGGL(k_chol_step, dim3(npanel + U + inv), dim3(256), sizeof(StepLds), st, V, N,
+    hipLaunchKernelGGL(k_chol_step, dim3(npanel + U + inv), dim3(kStepNT), sizeof(StepLds), st, V, N,
                        T, s, rhs, alpha, z, Ld, Wd, info_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
