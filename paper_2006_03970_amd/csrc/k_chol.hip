@@ -147,6 +147,8 @@ struct StepLds {
     struct {
       double P[kNB][kBP];  // L_{s,s-1}, transposed (previous step's update)
       double Q[kNB][kBP];  // L_{s+p,s-1}, transposed
+      double D[kNB][kBP];  // diagonal tile of column s (masked, identity padding)
+      double B[kNB][kBP];  // own tile of column s (masked)
     } st;
     double LF[2 * kNB][kBP];  // factor of the stacked [diagonal tile; own tile]
   } u;
@@ -325,13 +327,30 @@ __global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, i
   const bool live = !vw && (!in_b || p > 0);
   const bool fwd = rhs != nullptr && p == 0;  // VALU wave 2 solves block s of L z = rhs
 
-  // ---- every global load first: previous-step factors (VALU waves),
-  // right-hand side (VALU wave 0), S (MFMA waves)
-  constexpr int kPT = kNB * kNB / 256;  // tile entries a VALU thread loads
-  double pv[kPT], qv[kPT];
-  if (s > 0 && vw) {
-    load_tile<256>(V, N, s0, s0 - kNB, tid, pv);
-    if (p > 0) load_tile<256>(V, N, b0, s0 - kNB, tid, qv);
+  // ---- every global load first, by all 512 threads, 16 bytes a load when
+  // the row pitch allows: previous-step factors P = L_{s,s-1} and
+  // Q = L_{s+p,s-1}, the diagonal tile D and the own tile B of column s
+  // (entry pair e = tid + 512 q of a tile: row e / 32, columns 2(e % 32)..),
+  // and the right-hand side (VALU wave 0).  Addresses are clamped into the
+  // matrix; masks are applied when the tiles are staged in LDS.
+  constexpr int kTQ = kNB * kNB / 2 / kStepNT;  // entry pairs of a tile per thread
+  const bool v2 = (N & 1) == 0 && ((uintptr_t)V & 15) == 0;
+  auto ld2 = [&](int i, int k) -> double2 {
+    const int64_t row = (int64_t)min(i, N - 1) * N;
+    if (v2) return *reinterpret_cast<const double2*>(V + row + min(k, N - 2));
+    return double2{V[row + min(k, N - 1)], V[row + min(k + 1, N - 1)]};
+  };
+  double2 pv[kTQ], qv[kTQ], dv[kTQ], bv[kTQ];
+#pragma unroll
+  for (int q = 0; q < kTQ; ++q) {
+    const int e = tid + kStepNT * q;
+    const int r = e / (kNB / 2), c = 2 * (e % (kNB / 2));
+    if (s > 0) {
+      pv[q] = ld2(s0 + r, s0 - kNB + c);
+      if (p > 0) qv[q] = ld2(b0 + r, s0 - kNB + c);
+    }
+    dv[q] = ld2(s0 + r, s0 + c);
+    if (p > 0) bv[q] = ld2(b0 + r, s0 + c);
   }
   double zp = 0.0, zc = 0.0;
   if (rhs && tid < kNB) {
@@ -340,8 +359,30 @@ __global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, i
     const double r0 = s == 0 ? alpha * rhs[min(g, N - 1)] : z[min(g, N - 1)];
     zc = g < N ? r0 : 0.0;
   }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
+#pragma unroll
+  for (int q = 0; q < kTQ; ++q) {
+    const int e = tid + kStepNT * q;
+    const int r = e / (kNB / 2), c = 2 * (e % (kNB / 2));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int C = c + h;
+      if (s > 0) {
+        // P, Q transposed, zero outside the matrix (column block s-1 is full)
+        L.u.st.P[C][r] = s0 + r < N ? (h ? pv[q].y : pv[q].x) : 0.0;
+        if (p > 0) L.u.st.Q[C][r] = b0 + r < N ? (h ? qv[q].y : qv[q].x) : 0.0;
+      }
+      // the diagonal tile keeps its lower triangle and gets identity padding;
+      // the own tile is zero outside the matrix
+      const double d = h ? dv[q].y : dv[q].x;
+      L.u.st.D[r][C] = ((r < nk) & (C <= r)) ? d : (r == C ? 1.0 : 0.0);
+      if (p > 0) L.u.st.B[r][C] = ((r < nbr) & (C < nk)) ? (h ? bv[q].y : bv[q].x) : 0.0;
+    }
+  }
+  if (rhs && tid < kNB && s > 0) L.zprev[tid] = zp;
+  __syncthreads();
   Acc acc;
-  if (!vw) {
+  if (live) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -350,43 +391,12 @@ __global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, i
         for (int v = 0; v < 4; ++v) {
           const int R = 32 * mw + 16 * rb + lane / 16 + 4 * v;
           const int C = 16 * cb + (lane & 15);
-          double x = 0.0;
-          if (!in_b) {
-            if (cb <= 2 * mw + rb) x = V[(int64_t)(s0 + min(R, nk - 1)) * N + s0 + min(C, nk - 1)];
-          } else if (p > 0) {
-            x = V[(int64_t)(b0 + min(R - kNB, nbr - 1)) * N + s0 + min(C, nk - 1)];
-          }
-          acc[rb][cb][v] = x;
-        }
-    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any use
-    // the diagonal tile keeps its lower triangle and gets identity padding;
-    // the own tile is zero outside the matrix
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int R = 32 * mw + 16 * rb + lane / 16 + 4 * v;
-          const int C = 16 * cb + (lane & 15);
-          const double x = acc[rb][cb][v];
-          acc[rb][cb][v] = !in_b ? (((R < nk) & (C <= R)) ? x : (R == C ? 1.0 : 0.0))
-                                 : (((R - kNB < nbr) & (C < nk)) ? x : 0.0);
+          acc[rb][cb][v] = in_b ? L.u.st.B[R - kNB][C] : L.u.st.D[R][C];
         }
   }
 
   if (s > 0) {
     // previous step's rank-64 update: S -= [L_{s,s-1}; L_{s+p,s-1}] L_{s,s-1}^T
-    if (vw) {
-      mask_tile<256>(N, s0, s0 - kNB, tid, pv);
-      store_t<256>(pv, tid, L.u.st.P);
-      if (p > 0) {
-        mask_tile<256>(N, b0, s0 - kNB, tid, qv);
-        store_t<256>(qv, tid, L.u.st.Q);
-      }
-    }
-    if (rhs && tid < kNB) L.zprev[tid] = zp;
-    __syncthreads();
     if (live) {
       double(*Ls)[kBP] = in_b ? L.u.st.Q : L.u.st.P;
       const int rbase = in_b ? 32 * mw - kNB : 32 * mw;
