@@ -10,7 +10,10 @@ Newton matrix, FP64 Cholesky / line search / KKT residual, FP64-accumulated
 refresh of A^T y); the plain FP64 path on the same problem is reported beside
 it, and BF16 storage as a second mixed variant.  The roofline entry is the
 Newton pass w_d = A^T d (k_gemv_t over the FP32 design, FP32 accumulation),
-timed live with HIP events around each of its launches on the solve's stream.
+timed live with HIP events around each of its launches on the solve's stream
+in every fourth timed solve (the event records leave the GPU idle for a few
+microseconds around each timed launch, so timing every solve would slow the
+solves being measured).
 The CPU baseline is the FP64 oracle on the machine's host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -244,11 +247,15 @@ def main():
     A64 = design_to_device(p64.AT, "f64")
     Abf = design_to_device(datagen.f32_to_bf16_bits(AT32), "bf16")
 
+    TIME_EVERY = 4  # solves of the timed region whose A^T d launches carry HIP events
+
     def run(A, steps, timing):
-        opts = binding.make_opts(timing=1 if timing else 0)
+        opts_t = binding.make_opts(timing=1)
+        opts_n = binding.make_opts(timing=0)
         infos = []
         x = torch.empty(p64.n, dtype=torch.float64, device=dev)
-        for _ in range(steps):
+        for k in range(steps):
+            opts = opts_t if timing and k % TIME_EVERY == 0 else opts_n
             _, info = binding.ssnal_en_solve(ctx, A, b, p64.lam1, p64.lam2, tol=p64.tol, x_out=x,
                                              opts=opts, stream=stream)
             if info["status"] != 0:
@@ -271,12 +278,14 @@ def main():
     elbf, infbf, _ = timed(Abf, "mixed bf16")
 
     def atd_stats(infos, s_a):
-        """Average duration of the Newton A^T d launches (HIP events)."""
-        calls = sum(i["atd_launches"] for i in infos)
-        ms = sum(i["atd_ms"] for i in infos)
+        """Average duration of the Newton A^T d launches (HIP events, in the
+        timed solves that carried them)."""
+        timed_infos = [i for i in infos if i["atd_launches"] > 0]
+        calls = sum(i["atd_launches"] for i in timed_infos)
+        ms = sum(i["atd_ms"] for i in timed_infos)
         avg_s = ms / calls / 1e3
         bytes_per_launch = float(p64.m) * p64.n * s_a
-        return avg_s, bytes_per_launch, calls / len(infos)
+        return avg_s, bytes_per_launch, calls / len(timed_infos)
 
     avg32, bpl32, calls32 = atd_stats(inf32, 4)
     avg64, bpl64, calls64 = atd_stats(inf64, 8)
