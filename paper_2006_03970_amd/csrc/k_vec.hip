@@ -27,11 +27,23 @@ __device__ __forceinline__ int64_t clampi(int64_t i, int64_t n) { return i < n ?
 // Reductions that span blocks finish in a second, single-block kernel: the
 // kernel boundary makes every block's partials visible, with no device-wide
 // cache write-back inside the producing kernel.
+// The end of a kernel that publishes the scalar slots to the host (one
+// workgroup): once the workgroup's slot writes are in place, copy the slots
+// to coherent pinned memory, a system-scope fence, then the flag with
+// release semantics, so a host that observes the flag reads the new slots.
+__device__ __forceinline__ void publish_block(const double* scal, const Pub& pub) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < SC_SIZE; i += blockDim.x) pub.dst[i] = scal[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(pub.flag, pub.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// out and yy_out point into the slots that a publish request copies (scal).
 template <int K>
-__global__ __launch_bounds__(kNT) void k_final(const double* __restrict__ part, int nb,
-                                               double* __restrict__ out,
-                                               const double* __restrict__ y, int m,
-                                               double* __restrict__ yy_out) {
+__global__ __launch_bounds__(kNT) void k_final(const double* __restrict__ part, int nb, double* out,
+                                               const double* __restrict__ y, int m, double* yy_out,
+                                               const double* scal, Pub pub) {
   __shared__ double red[kNT / kWave];
   final_sums<kNT, K>(part, nb, out, red);
   if (y) {
@@ -40,6 +52,7 @@ __global__ __launch_bounds__(kNT) void k_final(const double* __restrict__ part, 
     t = block_sum<kNT>(t, red);
     if (threadIdx.x == 0) *yy_out = t;
   }
+  if (pub.flag) publish_block(scal, pub);
 }
 
 // ------------------------------------------------------------------ compaction
@@ -322,16 +335,69 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
   }
 }
 
+// Mode 0 by one workgroup of 1024 threads (m <= kFin1Max): the chunk sums,
+// g, rho and the three sums of k_gather_finish + k_final<3> in one launch,
+// optionally publishing the slots to the host at the end.
+constexpr int kFin1NT = 1024;
+constexpr int kFin1Max = 2048;
+__global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __restrict__ part,
+                                                            const double* __restrict__ r_dev, int m,
+                                                            const double* __restrict__ y,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ g,
+                                                            double* __restrict__ rho,
+                                                            double* __restrict__ scal, Pub pub) {
+  int nchunks;
+  int64_t ck;
+  chunk_plan((int64_t)(*r_dev), nchunks, ck);
+  double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  for (int row = threadIdx.x; row < m; row += kFin1NT) {
+    double S = 0.0;
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S += v[u];
+    }
+    for (; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+    // gradient of psi (eq. grad_phy) and the primal residual A u - b
+    const double gi = y[row] + b[row] - S;
+    const double rh = S - b[row];
+    g[row] = gi;
+    rho[row] = rh;
+    v1 += gi * gi;
+    v2 += rh * rh;
+    v3 += b[row] * rh;
+  }
+  __shared__ double red[kFin1NT / kWave];
+  const double s1 = block_sum<kFin1NT>(v1, red);
+  const double s2 = block_sum<kFin1NT>(v2, red);
+  const double s3 = block_sum<kFin1NT>(v3, red);
+  if (threadIdx.x == 0) {
+    scal[SC_GG + 0] = s1;
+    scal[SC_GG + 1] = s2;
+    scal[SC_GG + 2] = s3;
+  }
+  if (pub.flag) publish_block(scal, pub);
+}
+
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         hipStream_t st) {
+                         hipStream_t st, Pub pub) {
+  if (mode == 0 && r_dev && m <= kFin1Max) {
+    hipLaunchKernelGGL(k_gather_finish1, dim3(1), dim3(kFin1NT), 0, st, part, r_dev, m, y, b, g, out2,
+                       scal, pub);
+    return hipGetLastError();
+  }
   const int nb = (m + kNT - 1) / kNT;
   hipLaunchKernelGGL(k_gather_finish, dim3(nb), dim3(kNT), 0, st, part, r_dev, r_host, m, mode, y, b,
                      g, out2, scal);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode != 0) return e;
   hipLaunchKernelGGL((k_final<3>), dim3(1), dim3(kNT), 0, st, scal + SC_BLK, nb, scal + SC_GG,
-                     (const double*)nullptr, 0, (double*)nullptr);
+                     (const double*)nullptr, 0, (double*)nullptr, (const double*)scal, pub);
   return hipGetLastError();
 }
 
@@ -571,14 +637,15 @@ __global__ __launch_bounds__(kNT) void k_outer(double* __restrict__ x, const dou
 }
 
 hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
-                        const double* y, int m, double* part, double* scal, hipStream_t st) {
+                        const double* y, int m, double* part, double* scal, hipStream_t st,
+                        Pub pub) {
   const int nb = prox_blocks(n);
   hipLaunchKernelGGL(k_outer, dim3(nb), dim3(kNT), 0, st, x, w, n, pa.sigma, pa.thr, pa.den, l1, l2,
                      part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_final<2>), dim3(1), dim3(kNT), 0, st, part, nb, scal + SC_XU, y, m,
-                     scal + SC_YY);
+                     scal + SC_YY, (const double*)scal, pub);
   return hipGetLastError();
 }
 
@@ -644,7 +711,8 @@ hipError_t publish_scalars(const double* scal, int n, double* host_dst, unsigned
 
 hipError_t sum_parts(const double* part, int nb, double* out, const double* y, int m,
                      double* yy_out, hipStream_t st) {
-  hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, out, y, m, yy_out);
+  hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, out, y, m, yy_out,
+                     (const double*)nullptr, Pub{});
   return hipGetLastError();
 }
 
@@ -656,7 +724,7 @@ hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, doub
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_final<4>), dim3(1), dim3(kNT), 0, st, part, nb, scal + SC_ETA_E,
-                     (const double*)nullptr, 0, (double*)nullptr);
+                     (const double*)nullptr, 0, (double*)nullptr, (const double*)nullptr, Pub{});
   return hipGetLastError();
 }
 
@@ -757,7 +825,7 @@ hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, double
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_final<1>), dim3(1), dim3(kNT), 0, st, part, nb, scal_slot,
-                     (const double*)nullptr, 0, (double*)nullptr);
+                     (const double*)nullptr, 0, (double*)nullptr, (const double*)nullptr, Pub{});
   return hipGetLastError();
 }
 

@@ -6,6 +6,15 @@
 
 namespace ssnal {
 
+// A request to publish the scalar slots to the host at the end of a kernel:
+// copy them to coherent pinned memory (dst, device address), then set *flag
+// = seq.  flag == nullptr: no request.
+struct Pub {
+  double* dst = nullptr;
+  unsigned long long* flag = nullptr;
+  unsigned long long seq = 0;
+};
+
 enum DType : int { kF64 = 0, kF32 = 1, kBF16 = 2 };
 
 inline int dtype_size(int dt) { return dt == kF64 ? 8 : (dt == kF32 ? 4 : 2); }
@@ -55,7 +64,7 @@ hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, con
 //  mode 2 (residual): out2 = y = S - b
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         hipStream_t st);
+                         hipStream_t st, Pub pub = Pub{});
 
 // Line search: for the K trial steps s_k, Delta_k = psi(y + s_k d) - psi(y);
 // a one-block follow-up kernel picks the first k with Delta_k <= mu s_k g^T d,
@@ -78,7 +87,8 @@ hipError_t ls_delta(const double* x, const double* w, const double* wd, int64_t 
 // Multiplier update x <- prox(t), with |x - u|^2, |z|^2 (z the conjugate
 // prox of Prop. 2 (2)) and |y|^2 reduced into scal.
 hipError_t outer_update(double* x, const double* w, int64_t n, ProxArgs pa, double l1, double l2,
-                        const double* y, int m, double* part, double* scal, hipStream_t st);
+                        const double* y, int m, double* part, double* scal, hipStream_t st,
+                        Pub pub = Pub{});
 // eta pass over q = A^T rho: sums of (x - prox_p(x - q))^2, x^2, |x|, and
 // (|q| - l1)_+^2 into scal.
 hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, double l2,

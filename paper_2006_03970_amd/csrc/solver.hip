@@ -176,13 +176,20 @@ int prepare(ssnal_ctx* c, int64_t m, int64_t n, Workspace& w) {
 // stream synchronisation.  After kSpinLimit the host falls back to
 // hipStreamSynchronize; errors of the stream are picked up by hipStreamQuery
 // while spinning.
-int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
+// The next publish request (the last kernel of a phase may carry it).
+Pub next_pub(ssnal_ctx* c) {
+  Pub p;
+  p.dst = c->d_scal;
+  p.flag = reinterpret_cast<unsigned long long*>(c->d_scal + SC_SIZE);
+  p.seq = ++c->pub_seq;
+  return p;
+}
+
+// Wait until the stream has published the scalar slots with sequence seq.
+int wait_pub(ssnal_ctx* c, hipStream_t st, unsigned long long seq, int* syncs) {
   constexpr auto kSpinLimit = std::chrono::microseconds(2000);
   constexpr auto kQueryEvery = std::chrono::microseconds(100);
   unsigned long long* flag = reinterpret_cast<unsigned long long*>(c->h_scal + SC_SIZE);
-  const unsigned long long seq = ++c->pub_seq;
-  HIPCHK(publish_scalars(w.scal, SC_SIZE, c->d_scal,
-                         reinterpret_cast<unsigned long long*>(c->d_scal + SC_SIZE), seq, st));
   if (syncs) ++*syncs;
   const auto t0 = std::chrono::steady_clock::now();
   auto tq = t0;
@@ -203,6 +210,12 @@ int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
     return fail(SSNAL_EHIP, "scalar readback: flag %llu after the stream finished, expected %llu",
                 (unsigned long long)*flag, seq);
   return 0;
+}
+
+int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
+  const Pub p = next_pub(c);
+  HIPCHK(publish_scalars(w.scal, SC_SIZE, p.dst, p.flag, p.seq, st));
+  return wait_pub(c, st, p.seq, syncs);
 }
 
 int check_args(const void* A, int dt, int64_t lda, const double* b, int64_t m, int64_t n) {
@@ -307,11 +320,11 @@ ProxArgs prox_args(double sigma, double l1, double l2) {
 
 // Prox + gradient: J, uJ, r (device), g, rho, |g|^2 ...  (pending step folded in)
 int prox_grad(const void* A, int dt, int64_t lda, const double* b, int m, int64_t n, const double* x,
-              const ProxArgs& pa, bool pending, const Workspace& w, hipStream_t st) {
+              const ProxArgs& pa, bool pending, const Workspace& w, hipStream_t st, Pub pub) {
   HIPCHK(prox_count(x, w.wy, w.wd, pending ? w.scal + SC_S : nullptr, n, pa, w.counts, st));
   HIPCHK(prox_write(x, w.wy, n, pa, w.counts, w.J, w.uJ, w.scal + SC_R, st));
   HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
-  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal, st));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal, st, pub));
   return 0;
 }
 
@@ -439,9 +452,10 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     bool refreshed = false;
     int inner = 0;
     for (;;) {
-      if (int rc = prox_grad(A, dt, lda, b, m, n, x, pa, pending, w, st)) return rc;
+      const Pub pub = next_pub(c);
+      if (int rc = prox_grad(A, dt, lda, b, m, n, x, pa, pending, w, st, pub)) return rc;
       pending = false;
-      if (int rc = readback(c, w, st, &syncs)) return rc;
+      if (int rc = wait_pub(c, st, pub.seq, &syncs)) return rc;
       {
         int cinfo = 0;
         std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
@@ -496,10 +510,11 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       ++inner;
     }
     // multiplier update x <- prox(x - sigma A^T y)
-    HIPCHK(outer_update(x, w.wy, n, pa, l1, l2, w.y, m, w.part, w.scal, st));
+    const Pub pub = next_pub(c);
+    HIPCHK(outer_update(x, w.wy, n, pa, l1, l2, w.y, m, w.part, w.scal, st, pub));
     ++outer_done;
     bool need_eta = false;
-    if (int rc = readback(c, w, st, &syncs)) return rc;
+    if (int rc = wait_pub(c, st, pub.seq, &syncs)) return rc;
     kkt3 = std::sqrt(hs[SC_XU]) / sigma / (1.0 + std::sqrt(hs[SC_YY]) + std::sqrt(hs[SC_ZZ]));
     need_eta = (kkt1 <= tol && kkt3 <= tol);
     if (need_eta) {
