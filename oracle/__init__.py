@@ -84,6 +84,7 @@ def lib():
         L.orc_newton_direction.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D, _D]
         L.orc_ls_delta.restype = _d
         L.orc_ls_delta.argtypes = [_D, _D, _i64, _d, _d, _d, _d, _d, _d]
+        L.orc_model_select.argtypes = [_D, _i64, _D, _i64, _i64, _d, _D, _D, _D]
         L.orc_en_solve.restype = C.c_int
         L.orc_en_solve.argtypes = [_D, _i64, _D, _i64, _i64, _d, _d, _D, _d, C.POINTER(Opts),
                                    _D, C.POINTER(Info), _D, C.c_int32, _I32]
@@ -238,3 +239,21 @@ def en_solve(AT, b, l1, l2, tol=1e-10, x0=None, trace_cap=4096, **opts):
     if rc < 0:
         raise ValueError("invalid arguments to the oracle solve")
     return x, info.as_dict(), trace[: rows.value].copy()
+
+
+def model_select(AT, b, x, l2, want_beta=False):
+    """gcv / e-bic at a solution x (Sec. "Parameter tuning", eq. gcv_bic): a
+    dict with r, nu (EN degrees of freedom), rss_en, rss (after least squares
+    on the selected features), gcv, ebic, status (0 ok, 1 r >= m, 2 A_J^T A_J
+    singular) and, on request, the de-biased coefficients."""
+    AT, m, n = _design(AT)
+    b, x = _f64(b), _f64(x)
+    out = np.empty(7)
+    beta = np.empty(n) if want_beta else None
+    lib().orc_model_select(_dp(AT), m, _dp(b), m, n, l2, _dp(x), _dp(out),
+                           _dp(beta) if want_beta else C.cast(None, _D))
+    res = dict(r=int(out[0]), nu=out[1], rss_en=out[2], rss=out[3], gcv=out[4], ebic=out[5],
+               status=int(out[6]))
+    if want_beta:
+        res["beta"] = beta
+    return res

@@ -462,3 +462,130 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
   free(y); free(g); free(d); free(Au); free(w); free(t); free(u); free(wd); free(J); free(uJ);
   return status;
 }
+
+/* Model selection at a solution x (Sec. "Parameter tuning", eq. gcv_bic).
+ * J = {i : x_i != 0}, r = |J|.
+ *   nu   = tr( A_J (A_J^T A_J + lambda2 I_r)^{-1} A_J^T )   (EN degrees of freedom)
+ *   beta = argmin ||A_J beta - b||^2                        (least squares on the
+ *          selected features: the de-biased estimate; normal equations by
+ *          Cholesky, which needs r < m and A_J of full column rank)
+ *   rss  = ||A_J beta - b||^2, rss_en = ||A x - b||^2
+ *   gcv  = (rss / m) / (1 - nu/m)^2
+ *   ebic = log(rss / m) + (nu / m) (log m + log n)
+ * out[0..6] = r, nu, rss_en, rss, gcv, ebic, status (0 ok; 1: r >= m, the
+ * least-squares fit is not determined and rss/gcv/ebic are NaN; 2: A_J^T A_J
+ * not positive definite, likewise).  beta_out (n, nullable) gets beta
+ * scattered to J (zeros elsewhere).  nu follows its definition directly:
+ * Z = (A_J^T A_J + lambda2 I)^{-1} A_J^T by Cholesky and m right-hand sides,
+ * then the trace of A_J Z. */
+void orc_model_select(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                      double lambda2, const double* x, double* out, double* beta_out) {
+  int64_t r = 0;
+  for (int64_t i = 0; i < n; ++i) r += x[i] != 0.0;
+  int32_t* J = (int32_t*)malloc(sizeof(int32_t) * (size_t)(r > 0 ? r : 1));
+  r = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (x[i] != 0.0) J[r++] = (int32_t)i;
+  const double NaN = 0.0 / 0.0;
+  /* rss of the EN estimate */
+  double* res = (double*)malloc(sizeof(double) * (size_t)m);
+  orc_gemv_n(A, lda, m, n, x, res);
+  double rss_en = 0.0;
+  for (int64_t i = 0; i < m; ++i) {
+    res[i] -= b[i];
+    rss_en += res[i] * res[i];
+  }
+  /* G = A_J^T A_J */
+  double* G = (double*)malloc(sizeof(double) * (size_t)(r * r > 0 ? r * r : 1));
+  for (int64_t p = 0; p < r; ++p)
+    for (int64_t q = 0; q < r; ++q) {
+      double s = 0.0;
+      for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * A[J[q] * lda + i];
+      G[p * r + q] = s;
+    }
+  /* nu: L L^T = G + lambda2 I, Z = L^{-T} L^{-1} A_J^T column by column */
+  double nu = 0.0;
+  if (r > 0) {
+    double* M = (double*)malloc(sizeof(double) * (size_t)(r * r));
+    for (int64_t k = 0; k < r * r; ++k) M[k] = G[k];
+    for (int64_t p = 0; p < r; ++p) M[p * r + p] += lambda2;
+    if (orc_cholesky(M, r) != 0) {
+      nu = NaN;
+    } else {
+      double* z = (double*)malloc(sizeof(double) * (size_t)r);
+      for (int64_t i = 0; i < m; ++i) {
+        /* z = M^{-1} (row i of A_J)^T; nu += (row i of A_J) . z */
+        for (int64_t p = 0; p < r; ++p) {
+          double s = A[J[p] * lda + i];
+          for (int64_t k = 0; k < p; ++k) s -= M[p * r + k] * z[k];
+          z[p] = s / M[p * r + p];
+        }
+        for (int64_t p = r - 1; p >= 0; --p) {
+          double s = z[p];
+          for (int64_t k = p + 1; k < r; ++k) s -= M[k * r + p] * z[k];
+          z[p] = s / M[p * r + p];
+        }
+        for (int64_t p = 0; p < r; ++p) nu += A[J[p] * lda + i] * z[p];
+      }
+      free(z);
+    }
+    free(M);
+  }
+  /* least squares on J */
+  double rss = NaN, gcv = NaN, ebic = NaN, status = 0.0;
+  double* beta = (double*)malloc(sizeof(double) * (size_t)(r > 0 ? r : 1));
+  if (r >= m) {
+    status = 1.0;
+  } else {
+    int ok = 1;
+    if (r > 0) {
+      double* M = (double*)malloc(sizeof(double) * (size_t)(r * r));
+      for (int64_t k = 0; k < r * r; ++k) M[k] = G[k];
+      if (orc_cholesky(M, r) != 0) {
+        ok = 0;
+      } else {
+        for (int64_t p = 0; p < r; ++p) {
+          double s = 0.0;
+          for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * b[i];
+          for (int64_t k = 0; k < p; ++k) s -= M[p * r + k] * beta[k];
+          beta[p] = s / M[p * r + p];
+        }
+        for (int64_t p = r - 1; p >= 0; --p) {
+          double s = beta[p];
+          for (int64_t k = p + 1; k < r; ++k) s -= M[k * r + p] * beta[k];
+          beta[p] = s / M[p * r + p];
+        }
+      }
+      free(M);
+    }
+    if (!ok) {
+      status = 2.0;
+    } else {
+      rss = 0.0;
+      for (int64_t i = 0; i < m; ++i) {
+        double s = -b[i];
+        for (int64_t p = 0; p < r; ++p) s += A[J[p] * lda + i] * beta[p];
+        rss += s * s;
+      }
+      const double md = (double)m;
+      gcv = (rss / md) / ((1.0 - nu / md) * (1.0 - nu / md));
+      ebic = log(rss / md) + (nu / md) * (log(md) + log((double)n));
+    }
+  }
+  if (beta_out) {
+    for (int64_t i = 0; i < n; ++i) beta_out[i] = 0.0;
+    if (status == 0.0)
+      for (int64_t p = 0; p < r; ++p) beta_out[J[p]] = beta[p];
+  }
+  out[0] = (double)r;
+  out[1] = nu;
+  out[2] = rss_en;
+  out[3] = rss;
+  out[4] = gcv;
+  out[5] = ebic;
+  out[6] = status;
+  free(beta);
+  free(G);
+  free(res);
+  free(J);
+}

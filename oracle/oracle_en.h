@@ -78,4 +78,9 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
                  double* x_out, orc_info* info, double* trace, int32_t trace_cap,
                  int32_t* trace_rows);
 
+/* Model selection at a solution x (Sec. "Parameter tuning", eq. gcv_bic):
+ * out[0..6] = r, nu, rss_en, rss (de-biased), gcv, ebic, status. */
+void orc_model_select(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
+                      double lambda2, const double* x, double* out, double* beta_out);
+
 #endif

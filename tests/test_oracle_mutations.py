@@ -32,6 +32,13 @@ MUTATIONS = {
     "psi_l2_term": ("return 0.5 * dot(y, y, m) + dot(b, y, m) + (1.0 + sigma * l2) / (2.0 * sigma) * pp -",
                     "return 0.5 * dot(y, y, m) + dot(b, y, m) + 1.0 / (2.0 * sigma) * pp -"),
     "conj_prox": ("if (v >= thr) return (v * l2 + l1) / den;", "if (v >= thr) return (v * l2 - l1) / den;"),
+    "df_ridge": ("for (int64_t p = 0; p < r; ++p) M[p * r + p] += lambda2;",
+                 "for (int64_t p = 0; p < r; ++p) M[p * r + p] += 2.0 * lambda2;"),
+    "gcv_square": ("gcv = (rss / md) / ((1.0 - nu / md) * (1.0 - nu / md));", "gcv = (rss / md) / (1.0 - nu / md);"),
+    "ebic_log_n": ("ebic = log(rss / md) + (nu / md) * (log(md) + log((double)n));",
+                   "ebic = log(rss / md) + (nu / md) * log(md);"),
+    "debias_rhs": ("for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * b[i];",
+                   "for (int64_t i = 1; i < m; ++i) s += A[J[p] * lda + i] * b[i];"),
 }
 
 

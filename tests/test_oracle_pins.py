@@ -358,3 +358,101 @@ def test_status_not_converged(orc):
     A, b, l1, l2 = pinlib.gaussian_problem(30, 200, 16)
     x, info = _solve(orc, A, b, l1, l2, tol=1e-14, max_outer=1)
     assert info["status"] == 1
+
+
+# ---------------------------------------------------------------- model selection
+# gcv / e-bic (Sec. "Parameter tuning", eq. gcv_bic): nu against the singular
+# values of A_J, closed forms and special cases; the de-biased fit against a
+# library least-squares solver.
+
+def _ms_problem(seed, m=40, n=120, r=6):
+    g = np.random.default_rng(seed)
+    AT = g.standard_normal((n, m))
+    x = np.zeros(n)
+    J = np.sort(g.choice(n, size=r, replace=False))
+    x[J] = g.standard_normal(r)
+    b = g.standard_normal(m)
+    return AT, b, x, J
+
+
+@pytest.mark.parametrize("seed,l2", [(1, 0.3), (2, 2.0), (3, 1e-3)])
+def test_model_select_nu_from_singular_values(orc, seed, l2):
+    """nu = tr(A_J (A_J^T A_J + l2 I)^{-1} A_J^T) = sum s_i^2 / (s_i^2 + l2)."""
+    AT, b, x, J = _ms_problem(seed)
+    s = np.linalg.svd(AT[J].T, compute_uv=False)
+    res = orc.model_select(AT, b, x, l2)
+    assert res["r"] == J.size
+    assert res["nu"] == pytest.approx(np.sum(s * s / (s * s + l2)), rel=1e-12)
+
+
+def test_model_select_orthonormal_columns(orc):
+    """Orthonormal selected columns: nu = r / (1 + l2) exactly."""
+    g = np.random.default_rng(4)
+    m, n, r = 30, 50, 5
+    Q, _ = np.linalg.qr(g.standard_normal((m, r)))
+    AT = g.standard_normal((n, m))
+    J = np.array([2, 7, 11, 30, 44])
+    AT[J] = Q.T
+    x = np.zeros(n)
+    x[J] = 1.0
+    res = orc.model_select(AT, g.standard_normal(m), x, 0.25)
+    assert res["nu"] == pytest.approx(r / 1.25, rel=1e-13)
+
+
+def test_model_select_least_squares(orc):
+    """The de-biased fit is least squares on J: b in span(A_J) gives rss = 0
+    and beta = the generating coefficients; otherwise rss and beta match a
+    library solver."""
+    AT, b, x, J = _ms_problem(5)
+    c = np.random.default_rng(6).standard_normal(J.size)
+    b_in = AT[J].T @ c
+    res = orc.model_select(AT, b_in, x, 0.5, want_beta=True)
+    assert res["status"] == 0
+    assert res["rss"] <= 1e-24 * np.sum(b_in ** 2)
+    assert np.allclose(res["beta"][J], c, rtol=1e-10, atol=1e-12)
+    res = orc.model_select(AT, b, x, 0.5, want_beta=True)
+    beta, *_ = np.linalg.lstsq(AT[J].T, b, rcond=None)
+    assert res["rss"] == pytest.approx(np.sum((AT[J].T @ beta - b) ** 2), rel=1e-12)
+    assert np.allclose(res["beta"][J], beta, rtol=1e-10, atol=1e-13)
+    assert np.all(np.delete(res["beta"], J) == 0.0)
+    assert res["rss_en"] == pytest.approx(np.sum((AT.T @ x - b) ** 2), rel=1e-13)
+
+
+def test_model_select_criteria_definitions(orc):
+    """x = 0: r = nu = 0, rss = |b|^2, gcv = |b|^2/m, e-bic = log(|b|^2/m);
+    and the criteria follow the (rss, nu) they are computed from."""
+    AT, b, x, J = _ms_problem(7)
+    m, n = AT.shape[1], AT.shape[0]
+    res = orc.model_select(AT, b, np.zeros(n), 0.5)
+    bb = float(np.sum(b * b))
+    assert (res["r"], res["nu"], res["status"]) == (0, 0.0, 0)
+    assert res["rss"] == pytest.approx(bb, rel=1e-14)
+    assert res["gcv"] == pytest.approx(bb / m, rel=1e-14)
+    assert res["ebic"] == pytest.approx(np.log(bb / m), rel=1e-13)
+    res = orc.model_select(AT, b, x, 0.5)
+    rss, nu = res["rss"], res["nu"]
+    assert 0 < nu < J.size
+    assert res["gcv"] == pytest.approx(rss / m / (1 - nu / m) ** 2, rel=1e-13)
+    assert res["ebic"] == pytest.approx(np.log(rss / m) + nu / m * (np.log(m) + np.log(n)), rel=1e-13)
+
+
+def test_model_select_degenerate(orc):
+    """r >= m leaves the least-squares fit undetermined; a repeated column
+    makes A_J^T A_J singular.  Both are reported, with NaN criteria."""
+    g = np.random.default_rng(8)
+    m, n = 10, 30
+    AT = g.standard_normal((n, m))
+    b = g.standard_normal(m)
+    x = np.zeros(n)
+    x[:12] = 1.0
+    res = orc.model_select(AT, b, x, 0.5)
+    assert res["status"] == 1 and np.isnan(res["rss"]) and np.isnan(res["gcv"])
+    s = np.linalg.svd(AT[:12].T, compute_uv=False)
+    assert res["nu"] == pytest.approx(np.sum(s * s / (s * s + 0.5)), rel=1e-12)
+    AT[3] = 0.0
+    AT[3, :4] = 1.0  # |a|^2 = 4: the second pivot of the repeated column is exactly 0
+    AT[5] = AT[3]
+    x = np.zeros(n)
+    x[[3, 5, 9]] = 1.0
+    res = orc.model_select(AT, b, x, 0.5)
+    assert res["status"] == 2 and np.isnan(res["ebic"])
