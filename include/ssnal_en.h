@@ -175,6 +175,36 @@ typedef struct {
   double* x_out;
 } ssnal_en_problem;
 
+/*
+ * Model selection at a solution (Sec. "Parameter tuning", eq. gcv_bic), for
+ * choosing (lambda1, lambda2) along a path:
+ *   J = {i : x_i != 0}, r = |J|;
+ *   nu   = tr(A_J (A_J^T A_J + lambda2 I_r)^{-1} A_J^T), the elastic-net degrees
+ *          of freedom, computed as r - lambda2 ||L^{-1}||_F^2 with L L^T =
+ *          A_J^T A_J + lambda2 I_r (r < m), or as m - lambda2 ||L^{-1}||_F^2 with
+ *          L L^T = A_J A_J^T + lambda2 I_m (r >= m);
+ *   beta = the least-squares fit of b on the columns J (the de-biased
+ *          estimate), by Cholesky of A_J^T A_J (needs 0 < r < m and A_J of full
+ *          column rank);
+ *   rss  = ||A_J beta - b||^2 (||b||^2 when r = 0), rss_en = ||A x - b||^2;
+ *   gcv  = (rss/m) / (1 - nu/m)^2,  ebic = log(rss/m) + (nu/m)(log m + log n).
+ * The Gram matrices read A with the storage's accumulation (FP32 for F32/BF16
+ * storage, as in the Newton matrix); the factorisations, solves and
+ * reductions are FP64.  x, b: device, n and m doubles; beta_out: device, n
+ * doubles (nullable; beta scattered to J, zero elsewhere); out: HOST.
+ * status in out: 0 ok; 1 r >= m (the least-squares fit is not determined:
+ * rss, gcv, ebic are NaN, beta_out zero); 2 A_J^T A_J not positive definite
+ * (likewise).  Needs lambda2 > 0 and m <= 4096.
+ */
+typedef struct {
+  int32_t status;
+  int32_t r;
+  double nu, rss_en, rss, gcv, ebic;
+} ssnal_en_select;
+int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                          const double* b, int64_t m, int64_t n, double lambda2, const double* x,
+                          hipStream_t stream, double* beta_out, ssnal_en_select* out);
+
 /* Independent solves, one after the other on `stream` with the context's
  * workspace (k-fold or grid-search style).  infos: HOST, nullable, count
  * entries.  Returns the most severe status; an error stops the batch. */

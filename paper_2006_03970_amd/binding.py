@@ -82,6 +82,8 @@ def lib():
         L.ssnal_ls_delta.argtypes = [_vp, _vp, _vp, _vp, _i64, _d, _d, _d, _d, _d, _i,
                                      C.POINTER(_d), C.POINTER(_d), _vp]
         L.ssnal_kkt.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _d, _d, C.POINTER(_d), _vp]
+        L.ssnal_en_model_select.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, _vp, _vp, _vp,
+                                            C.POINTER(Select)]
         L.ssnal_en_path.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, C.POINTER(_d), _i, _i64,
                                     _d, _vp, _vp, C.POINTER(Opts), C.POINTER(Info)]
         L.ssnal_en_solve_batch.argtypes = [_vp, C.POINTER(Problem), _i, C.POINTER(Opts), _vp,
@@ -275,6 +277,27 @@ def ssnal_kkt(ctx, A, b, x, lambda1, lambda2, m=None, stream=None):
     _check(lib().ssnal_kkt(ctx.ptr, pA, dt, lda, _ptr(b), m, n, _ptr(x), float(lambda1),
                            float(lambda2), out, _stream(stream)))
     return {"eta": out[0], "primal_obj": out[1], "dual_obj": out[2], "rel_gap": out[3]}
+
+
+class Select(C.Structure):
+    _fields_ = [("status", C.c_int32), ("r", C.c_int32), ("nu", C.c_double), ("rss_en", C.c_double),
+                ("rss", C.c_double), ("gcv", C.c_double), ("ebic", C.c_double)]
+
+
+def ssnal_en_model_select(ctx, A, b, x, lambda2, m=None, want_beta=False, stream=None):
+    """gcv / e-bic at a solution x: a dict with status, r, nu, rss_en, rss, gcv,
+    ebic and, on request, the de-biased coefficients (device tensor)."""
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    beta = torch.empty(n, dtype=torch.float64, device=x.device) if want_beta else None
+    s = Select()
+    _check(lib().ssnal_en_model_select(ctx.ptr, pA, dt, lda, _ptr(b), m, n, float(lambda2), _ptr(x),
+                                       _stream(stream), _ptr(beta) if want_beta else None,
+                                       C.byref(s)))
+    out = {k: getattr(s, k) for k, _ in Select._fields_}
+    if want_beta:
+        out["beta"] = beta
+    return out
 
 
 def workspace_bytes(m, n) -> int:

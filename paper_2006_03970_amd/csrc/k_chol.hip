@@ -214,8 +214,11 @@ __device__ __forceinline__ void trailing_tile(double* __restrict__ V, int N, int
 // row k is final once the rows above have updated it, then it updates the
 // rows below with column k of L, broadcast from LDS), then
 // W21 = -W22 (L21 W11) by all waves, two entries a thread per product.
+// A partial block (nk < 64: the last block of L, zero outside its nk x nk
+// lower triangle) is inverted with identity padding and written with zeros
+// outside nk x nk.
 __device__ __forceinline__ void invert_block(const double* __restrict__ Ls, double* __restrict__ Ws,
-                                             StepLds& L) {
+                                             StepLds& L, int nk = kNB) {
   constexpr int kH = kNB / 2;
   const int tid = threadIdx.x;
   const int wid = wave_id();
@@ -225,8 +228,10 @@ __device__ __forceinline__ void invert_block(const double* __restrict__ Ls, doub
 #pragma unroll
   for (int q = 0; q < kNB * kNB / kStepNT; ++q) {
     const int e = tid + kStepNT * q;
-    A[e / kNB][e % kNB] = Ls[e];
-    WI[e / kNB][e % kNB] = 0.0;
+    const int r = e / kNB, c = e % kNB;
+    const double v = Ls[e];
+    A[r][c] = r < nk ? v : (r == c ? 1.0 : 0.0);
+    WI[r][c] = 0.0;
   }
   __syncthreads();
   if (wid < 2) {
@@ -277,7 +282,8 @@ __device__ __forceinline__ void invert_block(const double* __restrict__ Ls, doub
 #pragma unroll
   for (int q = 0; q < kNB * kNB / kStepNT; ++q) {
     const int e = tid + kStepNT * q;
-    Ws[e] = WI[e / kNB][e % kNB];
+    const int r = e / kNB, c = e % kNB;
+    Ws[e] = (r < nk) & (c < nk) ? WI[r][c] : 0.0;
   }
 }
 
@@ -607,6 +613,146 @@ __global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, i
   if (fwd && wid == 2 && lane < nk) z[s0 + lane] = zv;
 }
 
+// Inverse of the last diagonal block of L (which the step launches leave
+// out), for the Frobenius norm of L^{-1}.
+__global__ __launch_bounds__(kStepNT) void k_invert_last(const double* __restrict__ Ld,
+                                                         double* __restrict__ Wd, int N) {
+  extern __shared__ double smem[];
+  StepLds& L = *reinterpret_cast<StepLds*>(smem);
+  const int T = (N + kNB - 1) / kNB;
+  const int nk = N - (T - 1) * kNB;
+  invert_block(Ld + (int64_t)(T - 1) * kNB * kNB, Wd + (int64_t)(T - 1) * kNB * kNB, L, nk);
+}
+
+// ||L^{-1}||_F^2 (= tr((L L^T)^{-1})) by block columns of X = L^{-1}: X_jj = W_jj
+// (the diagonal-block inverses) and, down the column, X_ij = -W_ii sum_{k=j}^{i-1}
+// L_ik X_kj on FP64 MFMA.  One workgroup (4 waves) per block column j writes
+// its partial sum to part[j]; X_kj, k > j, are kept in Xs (triangular block
+// index) for the later rows of the same column.  V holds L below the diagonal
+// blocks (row-major N x N), Wd the T inverses.
+struct InvLds {
+  double P[kNB][kBP];
+  double Q[kNB][kBP];
+};
+__device__ __forceinline__ int64_t tri_block(int i, int j, int T) {
+  return (int64_t)j * T - (int64_t)j * (j - 1) / 2 + (i - j);  // i >= j
+}
+__global__ __launch_bounds__(256) void k_inv_frob(const double* __restrict__ V, int N,
+                                                  const double* __restrict__ Wd,
+                                                  double* __restrict__ Xs, double* __restrict__ part) {
+  extern __shared__ double smem[];
+  InvLds& S = *reinterpret_cast<InvLds*>(smem);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = wave_id();
+  const int wi = wid >> 1, wj = wid & 1;
+  const int T = (N + kNB - 1) / kNB;
+  const int j = blockIdx.x;
+  constexpr int kE = kNB * kNB / 256;
+  double frob = 0.0;
+  {
+    const double* W = Wd + (int64_t)j * kNB * kNB;
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const double v = W[tid + 256 * q];
+      frob = fma(v, v, frob);
+    }
+  }
+  for (int i = j + 1; i < T; ++i) {
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][c] = dbl4{0, 0, 0, 0};
+    for (int k = j; k < i; ++k) {
+      // P = L_ik transposed (zero past N), Q = X_kj
+      double lv[kE], xv[kE];
+      load_tile<256>(V, N, i * kNB, k * kNB, tid, lv);
+      const double* X = k == j ? Wd + (int64_t)j * kNB * kNB : Xs + tri_block(k, j, T) * kNB * kNB;
+#pragma unroll
+      for (int q = 0; q < kE; ++q) xv[q] = X[tid + 256 * q];
+      __builtin_amdgcn_sched_barrier(0);
+      mask_tile<256>(N, i * kNB, k * kNB, tid, lv);
+      __syncthreads();  // the previous product's reads of P, Q are done
+      store_t<256>(lv, tid, S.P);
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const int e = tid + 256 * q;
+        S.Q[e / kNB][e % kNB] = xv[q];
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int ks = 0; ks < kNB; ks += 4) {
+        const int kr = ks + lane / 16;
+        double a[2], b[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) a[p] = S.P[kr][wi * 32 + p * 16 + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) b[q] = S.Q[kr][wj * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p][q], 0, 0, 0);
+      }
+    }
+    // X_ij = -W_ii acc: P = W_ii transposed, Q = acc
+    {
+      const double* W = Wd + (int64_t)i * kNB * kNB;
+      double wv[kE];
+#pragma unroll
+      for (int q = 0; q < kE; ++q) wv[q] = W[tid + 256 * q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const int e = tid + 256 * q;
+        S.P[e % kNB][e / kNB] = wv[q];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            S.Q[wi * 32 + p * 16 + lane / 16 + 4 * v][wj * 32 + q * 16 + (lane & 15)] = acc[p][q][v];
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = dbl4{0, 0, 0, 0};
+#pragma unroll 4
+      for (int ks = 0; ks < kNB; ks += 4) {
+        const int kr = ks + lane / 16;
+        double a[2], b[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) a[p] = S.P[kr][wi * 32 + p * 16 + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) b[q] = S.Q[kr][wj * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p][q], 0, 0, 0);
+      }
+      double* X = Xs + tri_block(i, j, T) * kNB * kNB;
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double x = -acc[p][q][v];
+            X[(wi * 32 + p * 16 + lane / 16 + 4 * v) * kNB + wj * 32 + q * 16 + (lane & 15)] = x;
+            frob = fma(x, x, frob);
+          }
+      __syncthreads();  // X_ij in place before the next row reads it
+    }
+  }
+  __shared__ double red[256 / kWave];
+  frob = block_sum<256>(frob, red);
+  if (tid == 0) part[j] = frob;
+}
+
 // Backward substitution L^T x = z by one workgroup of 1024 threads, left-
 // looking by blocks of 64 rows from the last: block s needs
 // c_s = sum_{r below} L[r][s0 + j] x_r, then solves L_ss^T x_s = z_s - c_s.
@@ -841,6 +987,12 @@ hipError_t chol_init() {
   e = hipFuncSetAttribute((const void*)k_chol_back<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)back_lds(4096));
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_invert_last, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          sizeof(StepLds));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_inv_frob, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          sizeof(InvLds));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_chol_back<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)back_lds(4096));
 }
@@ -873,6 +1025,18 @@ hipError_t cholesky(double* V, int N, double* Ld, int* info_dev, hipStream_t st)
   hipError_t e = chol_factor_solve(V, N, nullptr, 1.0, nullptr, nullptr, Ld, info_dev, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_diag, dim3((N + kNB - 1) / kNB), dim3(256), 0, st, V, N, Ld);
+  return hipGetLastError();
+}
+
+hipError_t chol_inv_frob(const double* V, int N, double* Ld, double* part, hipStream_t st) {
+  if (N < 1 || N > 4096) return hipErrorInvalidValue;
+  const int T = (N + kNB - 1) / kNB;
+  double* Wd = Ld + (int64_t)T * kNB * kNB;
+  double* Xs = Wd + (int64_t)T * kNB * kNB;
+  hipLaunchKernelGGL(k_invert_last, dim3(1), dim3(kStepNT), sizeof(StepLds), st, Ld, Wd, N);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_inv_frob, dim3(T), dim3(256), sizeof(InvLds), st, V, N, Wd, Xs, part);
   return hipGetLastError();
 }
 

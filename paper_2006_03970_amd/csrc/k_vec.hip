@@ -799,6 +799,24 @@ hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t 
   hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, st, src, alpha, dst, n);
   return hipGetLastError();
 }
+__global__ __launch_bounds__(kNT) void k_scatter(const int32_t* __restrict__ J,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ r_dev,
+                                                  double* __restrict__ out) {
+  const int64_t r = (int64_t)*r_dev;
+  for (int64_t k = (int64_t)blockIdx.x * kNT + threadIdx.x; k < r; k += (int64_t)gridDim.x * kNT)
+    out[J[k]] = v[k];
+}
+
+hipError_t scatter(const int32_t* J, const double* v, const double* r_dev, int64_t r_bound,
+                   double* out, hipStream_t st) {
+  int64_t nb = (r_bound + kNT - 1) / kNT;
+  if (nb < 1) nb = 1;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kNT), 0, st, J, v, r_dev, out);
+  return hipGetLastError();
+}
+
 hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, dst, v, n);
   return hipGetLastError();

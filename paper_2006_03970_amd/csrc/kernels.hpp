@@ -97,6 +97,9 @@ hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, doub
 // Small helpers
 hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st);
 hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st);
+// out[J[k]] = v[k] for k < r (r read from r_dev; r_bound >= r).
+hipError_t scatter(const int32_t* J, const double* v, const double* r_dev, int64_t r_bound,
+                   double* out, hipStream_t st);
 hipError_t nonfinite_count(const double* v, int64_t n, double* scal_slot, double* part,
                            hipStream_t st);
 
@@ -134,6 +137,10 @@ hipError_t chol_factor_solve(double* V, int N, const double* rhs, double alpha, 
 // Factor only, with the diagonal blocks of L copied back into V (lower
 // triangle = L; the strict upper triangle keeps stale values).
 hipError_t cholesky(double* V, int N, double* Ld, int* info_dev, hipStream_t st);
+// After chol_factor_solve with a right-hand side (Ld: 2T blocks, then room for
+// T(T+1)/2 more): part[j] = the squares of block column j of L^{-1}, j < T,
+// so that their sum is ||L^{-1}||_F^2 = tr((L L^T)^{-1}).
+hipError_t chol_inv_frob(const double* V, int N, double* Ld, double* part, hipStream_t st);
 // Zero the strict upper triangle (for callers that want L alone).
 hipError_t zero_upper(double* V, int N, hipStream_t st);
 

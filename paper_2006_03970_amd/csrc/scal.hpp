@@ -25,6 +25,10 @@ enum Scal : int {
   SC_AMAX = 17,    // max_i |v_i| (path: ||A^T b||_inf)
   SC_COLSQ = 18,   // sum_j ||a_j||^2 (default sigma0)
   SC_BB = 19,      // ||b||^2
+  SC_MS_RSSEN = 20,  // model selection: ||A x - b||^2
+  SC_MS_FROB = 21,   // ||L^{-1}||_F^2
+  SC_MS_RSS = 22,    // ||A_J beta - b||^2
+  SC_MS_NONE = 23,   // sink of an empty sum
   SC_DELTA = 32,   // 33 slots: line-search increments Delta_k (+ second-order sum)
   SC_BLK = 80,     // per-block partials of the m-vector finishers (<= 16 blocks x 3)
   SC_SIZE = 160

@@ -1063,6 +1063,95 @@ int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, i
   return 0;
 }
 
+int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                          const double* b, int64_t m, int64_t n, double lambda2, const double* x,
+                          hipStream_t stream, double* beta_out, ssnal_en_select* out) {
+  g_err[0] = 0;
+  if (!ctx || !x || !out) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
+  if (!(lambda2 > 0.0) || !std::isfinite(lambda2)) return fail(SSNAL_EINVAL, "lambda2 must be > 0");
+  if (m > 4096) return fail(SSNAL_EINVAL, "model selection needs m <= 4096 (dense systems)");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace w;
+  if (int rc = prepare(ctx, m, n, w)) return rc;
+  const int dt = (int)a_dtype;
+  const int mi = (int)m;
+  hipStream_t st = stream;
+  double* hs = ctx->h_scal;
+  std::memset(out, 0, sizeof(*out));
+  // support of x and the residual of the elastic-net fit
+  HIPCHK(support_count(x, n, w.counts, st));
+  HIPCHK(support_write(x, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
+  HIPCHK(gather_gemv_partial(A, dt, lda, mi, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, mi, 2, nullptr, b, nullptr, w.t1, w.scal, st));
+  HIPCHK(sum_parts(w.part, 0, w.scal + SC_MS_NONE, w.t1, mi, w.scal + SC_MS_RSSEN, st));
+  HIPCHK(sum_parts(w.part, 0, w.scal + SC_MS_NONE, b, mi, w.scal + SC_BB, st));
+  if (int rc = readback(ctx, w, st, nullptr)) return rc;
+  const int64_t r = (int64_t)hs[SC_R];
+  out->r = (int32_t)r;
+  out->rss_en = hs[SC_MS_RSSEN];
+  const double bb = hs[SC_BB];
+  const double md = (double)m;
+  auto criteria = [&](double rss) {
+    out->rss = rss;
+    out->gcv = (rss / md) / ((1.0 - out->nu / md) * (1.0 - out->nu / md));
+    out->ebic = std::log(rss / md) + (out->nu / md) * (std::log(md) + std::log((double)n));
+  };
+  if (beta_out) HIPCHK(vec_fill(beta_out, 0.0, n, st));
+  if (r == 0) {
+    out->nu = 0.0;
+    criteria(bb);
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+  }
+  // degrees of freedom: N - lambda2 ||L^{-1}||_F^2, L L^T = lambda2 I_N + Gram
+  const int form = r < m ? 1 : 0;
+  const int N = (int)(r < m ? r : m);
+  HIPCHK(syrk(A, dt, lda, mi, w.J, r, form, lambda2, 1.0, w.V, w.syrk, st));
+  HIPCHK(vec_fill(w.t2, 0.0, N, st));
+  HIPCHK(hipMemsetAsync(w.info, 0, sizeof(double), st));
+  HIPCHK(chol_factor_solve(w.V, N, w.t2, 1.0, w.t3, w.d, (double*)w.syrk, w.info, st));
+  HIPCHK(chol_inv_frob(w.V, N, (double*)w.syrk, w.part, st));
+  HIPCHK(sum_parts(w.part, (N + 63) / 64, w.scal + SC_MS_FROB, nullptr, 0, nullptr, st));
+  if (int rc = readback(ctx, w, st, nullptr)) return rc;
+  {
+    int cinfo = 0;
+    std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
+    if (cinfo != 0) return fail(SSNAL_ENUMERIC, "lambda2 I + Gram: non-positive pivot at row %d", cinfo - 1);
+  }
+  out->nu = (double)N - lambda2 * hs[SC_MS_FROB];
+  const double nan = std::nan("");
+  if (r >= m) {
+    out->status = 1;
+    out->rss = out->gcv = out->ebic = nan;
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+  }
+  // least squares on the selected features: A_J^T A_J beta = A_J^T b
+  HIPCHK(syrk(A, dt, lda, mi, w.J, r, 1, 0.0, 1.0, w.V, w.syrk, st));
+  HIPCHK(gemv_t(A, dt, lda, mi, r, w.J, b, w.wd, true, st));
+  HIPCHK(hipMemsetAsync(w.info, 0, sizeof(double), st));
+  HIPCHK(chol_factor_solve(w.V, (int)r, w.wd, 1.0, w.t3, w.wy, (double*)w.syrk, w.info, st));
+  HIPCHK(gather_gemv_partial(A, dt, lda, mi, w.J, w.wy, w.scal + SC_R, n, w.gpart, st));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, mi, 2, nullptr, b, nullptr, w.t1, w.scal, st));
+  HIPCHK(sum_parts(w.part, 0, w.scal + SC_MS_NONE, w.t1, mi, w.scal + SC_MS_RSS, st));
+  if (int rc = readback(ctx, w, st, nullptr)) return rc;
+  {
+    int cinfo = 0;
+    std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
+    if (cinfo != 0) {
+      out->status = 2;
+      out->rss = out->gcv = out->ebic = nan;
+      HIPCHK(hipStreamSynchronize(st));
+      return 0;
+    }
+  }
+  criteria(hs[SC_MS_RSS]);
+  if (beta_out) HIPCHK(scatter(w.J, w.wy, w.scal + SC_R, n, beta_out, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return 0;
+}
+
 int ssnal_ls_delta(ssnal_ctx* ctx, const double* x, const double* w, const double* wd, int64_t n,
                    double sigma, double lambda1, double lambda2, double gd, double dd, int K,
                    const double* s, double* delta_out, hipStream_t stream) {
