@@ -113,6 +113,55 @@ def large_bench(reps=3):
     return out
 
 
+def path_bench(reps=2):
+    """The warm-started path of the SNP-like workload (m=500, n=2e5, alpha=0.7,
+    100 points c_lambda 1 -> 0.01, FP32 storage, tol 1e-6): points/s of the
+    path, then gcv / e-bic at every point (degrees of freedom, least squares
+    on the selected features) and the selected point."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+
+    p = datagen.make_problem("c4", seed=1, store="f32", want_f64=False)
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    A = design_to_device(p.AT, "f32")
+    b = vec_to_device(p.b)
+    alpha = 0.7
+    cl = datagen.path_grid(100)
+    X, infos, status = binding.ssnal_en_path(ctx, A, b, alpha, cl, tol=1e-6, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        X, infos, status = binding.ssnal_en_path(ctx, A, b, alpha, cl, tol=1e-6, X_out=X, stream=stream)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    lam_max = float(torch.max(torch.abs(binding.ssnal_gemv_t(ctx, A, b, acc64=True)))) / alpha
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sel = []
+    for k in range(len(cl)):
+        l2 = (1 - alpha) * cl[k] * lam_max
+        sel.append(binding.ssnal_en_model_select(ctx, A, b, X[k], l2, stream=stream))
+    torch.cuda.synchronize()
+    el_sel = time.perf_counter() - t
+    gcv = [s["gcv"] if s["status"] == 0 else np.inf for s in sel]
+    ebic = [s["ebic"] if s["status"] == 0 else np.inf for s in sel]
+    kg, ke = int(np.argmin(gcv)), int(np.argmin(ebic))
+    out = {"workload": "SNP-like elastic-net path, m=500, n=200000, k=30, snr=5, alpha=0.7, "
+                       "100 points c_lambda 1 -> 0.01, FP32 storage, tol 1e-6",
+           "status": status, "points_per_s": len(cl) / el, "ms_per_path": el * 1e3,
+           "newton_iters": int(sum(i["newton_iters"] for i in infos)),
+           "model_select_ms_per_point": el_sel / len(cl) * 1e3,
+           "gcv_point": kg, "gcv_nnz": sel[kg]["r"], "ebic_point": ke, "ebic_nnz": sel[ke]["r"]}
+    print(f"[bench] path: {out['ms_per_path']:.1f} ms/path, model selection "
+          f"{out['model_select_ms_per_point']:.2f} ms/point", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_bench(nreq, nmax, slots, seed=7):
     """p50/p99 latency and solves/s of the serving loop over a request stream."""
     import numpy as np
@@ -199,6 +248,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the m=1000, n=1e6 single-solve section")
+    ap.add_argument("--no-path", action="store_true", help="skip the path + model selection section")
     ap.add_argument("--serving", type=int, default=64, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-nmax", type=float, default=5e5)
     ap.add_argument("--serving-slots", type=int, default=4)
@@ -337,6 +387,8 @@ def main():
 
     if not args.no_c3:
         out["large_single_solve"] = large_bench()
+    if not args.no_path:
+        out["path"] = path_bench()
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
 
