@@ -60,8 +60,14 @@ double orc_prox_pstar(double v, double sigma, double l1, double l2) {
 }
 
 /* p*(z) of the elastic-net penalty (Prop. 1, eq. p_star).
- * Pinned: numeric sup_x (z x - p(x)) in 1-D. */
+ * Pinned: numeric sup_x (z x - p(x)) in 1-D.  lambda2 = 0 (the Lasso): the
+ * conjugate of lambda1 |.|_1 is the indicator of |z|_inf <= lambda1. */
 double orc_pstar(const double* z, int64_t n, double l1, double l2) {
+  if (l2 == 0.0) {
+    for (int64_t i = 0; i < n; ++i)
+      if (fabs(z[i]) > l1) return INFINITY;
+    return 0.0;
+  }
   double s = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     double zi = z[i], e = 0.0;
@@ -123,12 +129,22 @@ double orc_primal_obj(const double* A, int64_t lda, const double* b, int64_t m, 
 /* Dual objective of (D): -h*(y) - p*(z) with z = -A^T y (the constraint
  * A^T y + z = 0), h*(y) = 1/2||y||^2 + b^T y (Sec. 3).  Every y is feasible
  * for lambda2 > 0 because p* is finite (Prop. 1). */
+/* lambda2 = 0: D is evaluated at theta*y, theta = min(1, lambda1/|A^T y|_inf),
+ * the largest multiple of y inside the dual feasible set (p* is an
+ * indicator), so that it stays a finite lower bound of F. */
 double orc_dual_obj(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
                     const double* y, double l1, double l2) {
   double* z = (double*)malloc(sizeof(double) * (size_t)n);
   orc_gemv_t(A, lda, m, n, y, z);
   for (int64_t j = 0; j < n; ++j) z[j] = -z[j];
-  double hs = 0.5 * dot(y, y, m) + dot(b, y, m);
+  double theta = 1.0;
+  if (l2 == 0.0) {
+    double amax = 0.0;
+    for (int64_t j = 0; j < n; ++j) amax = fabs(z[j]) > amax ? fabs(z[j]) : amax;
+    if (amax > l1) theta = l1 / amax;
+    for (int64_t j = 0; j < n; ++j) z[j] *= theta;
+  }
+  double hs = 0.5 * theta * theta * dot(y, y, m) + theta * dot(b, y, m);
   double ps = orc_pstar(z, n, l1, l2);
   free(z);
   return -hs - ps;
@@ -335,7 +351,7 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
                  double l1, double l2, const double* x0, double tol, const orc_opts* o,
                  double* x_out, orc_info* info, double* trace, int32_t trace_cap,
                  int32_t* trace_rows) {
-  if (m < 1 || n < 1 || lda < m || !(l1 >= 0.0) || !(l2 > 0.0) || !(tol > 0.0)) return -1;
+  if (m < 1 || n < 1 || lda < m || !(l1 >= 0.0) || !(l2 >= 0.0) || !(tol > 0.0)) return -1;
   orc_opts opt = {0};
   if (o) opt = *o;
   if (!(opt.sigma_factor > 0.0)) opt.sigma_factor = 5.0;

@@ -37,6 +37,7 @@ MUTATIONS = {
     "gcv_square": ("gcv = (rss / md) / ((1.0 - nu / md) * (1.0 - nu / md));", "gcv = (rss / md) / (1.0 - nu / md);"),
     "ebic_log_n": ("ebic = log(rss / md) + (nu / md) * (log(md) + log((double)n));",
                    "ebic = log(rss / md) + (nu / md) * log(md);"),
+    "lasso_theta": ("if (amax > l1) theta = l1 / amax;", "if (amax > l1) theta = 1.0;"),
     "debias_rhs": ("for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * b[i];",
                    "for (int64_t i = 1; i < m; ++i) s += A[J[p] * lda + i] * b[i];"),
 }

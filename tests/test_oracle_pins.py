@@ -456,3 +456,49 @@ def test_model_select_degenerate(orc):
     x[[3, 5, 9]] = 1.0
     res = orc.model_select(AT, b, x, 0.5)
     assert res["status"] == 2 and np.isnan(res["ebic"])
+
+
+# ---------------------------------------------------------------- Lasso limit
+# lambda2 = 0 (alpha -> 1): p* is the indicator of |z|_inf <= lambda1 (the
+# conjugate of a norm), so the dual objective is taken at the scaled feasible
+# point theta*rho, theta = min(1, lambda1/|A^T rho|_inf).
+
+def test_lasso_coordinate_descent_cross_check(orc):
+    """lambda2 = 0: the solve reaches the minimiser an independent cyclic
+    coordinate descent finds (unique for a Gaussian design in general position)."""
+    A, b, l1, _ = pinlib.gaussian_problem(60, 400, 12, k=8, c_lam=0.3)
+    x, info = _solve(orc, A, b, l1, 0.0, tol=1e-10)
+    assert info["status"] == 0
+    xc = pinlib.coordinate_descent_en(A, b, l1, 0.0)
+    Fo, Fc = pinlib.primal_objective(A, b, x, l1, 0.0), pinlib.primal_objective(A, b, xc, l1, 0.0)
+    assert abs(Fo - Fc) <= 1e-12 * Fc
+    assert np.max(np.abs(x - xc)) <= 1e-7
+    assert pinlib.kkt_violation(A, b, x, l1, 0.0) <= 1e-9
+    assert abs(info["rel_gap"]) <= 1e-9
+
+
+def test_lasso_conjugate_and_dual_bound(orc):
+    """p* with lambda2 = 0 is an indicator; the dual objective of any point is
+    a finite lower bound of F (weak duality through the feasible scaling),
+    attained at the minimiser."""
+    lam = 0.7
+    assert orc.pstar(np.array([0.3, -0.7, 0.0]), lam, 0.0) == 0.0
+    assert orc.pstar(np.array([0.3, -0.71]), lam, 0.0) == np.inf
+    A, b, l1, _ = pinlib.gaussian_problem(50, 200, 3, k=5, c_lam=0.2)
+    AT = np.ascontiguousarray(A.T)
+    g = np.random.default_rng(9)
+    for _ in range(5):
+        x = np.where(g.random(200) < 0.05, g.standard_normal(200), 0.0)
+        rho = A @ x - b
+        assert np.max(np.abs(A.T @ rho)) > l1  # an infeasible dual point
+        D = orc.dual_obj(AT, b, rho, l1, 0.0)
+        assert np.isfinite(D)
+        assert D <= pinlib.primal_objective(A, b, x, l1, 0.0)
+        # the bound is the dual objective at the scaled point, by hand
+        th = l1 / np.max(np.abs(A.T @ rho))
+        assert D == pytest.approx(-(0.5 * th * th * rho @ rho + th * b @ rho), rel=1e-12)
+    xs, info = _solve(orc, A, b, l1, 0.0, tol=1e-10)
+    assert info["status"] == 0
+    rho = A @ xs - b
+    assert orc.dual_obj(AT, b, rho, l1, 0.0) == pytest.approx(
+        pinlib.primal_objective(A, b, xs, l1, 0.0), rel=1e-10)
