@@ -122,8 +122,12 @@ const char* ssnal_last_error(void);
  *   A, a_dtype, lda, m, n : the design (see conventions); m >= 1, n >= 1,
  *                           m <= 4096 (the Newton system is dense m x m).
  *   b                     : m responses.
- *   lambda1 >= 0, lambda2 > 0: the penalty of eq. objective_function (unscaled;
- *                           callers using a 1/m-scaled loss multiply by m).
+ *   lambda1 >= 0, lambda2 >= 0: the penalty of eq. objective_function (unscaled;
+ *                           callers using a 1/m-scaled loss multiply by m);
+ *                           lambda2 = 0 is the Lasso limit, whose certificate
+ *                           takes the dual objective at theta*(A x - b), theta =
+ *                           min(1, lambda1/|A^T(A x - b)|_inf) (p* is then the
+ *                           indicator of |z|_inf <= lambda1).
  *   x0                    : n starting coefficients (warm start) or NULL for 0.
  *   tol > 0               : stop when kkt1 <= tol, kkt3 <= tol and eta <= tol.
  *   x_out                 : n coefficients on return (may alias x0).
@@ -141,7 +145,7 @@ int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t l
 /*
  * Regularisation path with warm starts (Sec. 3.3: each solve starts from the
  * solution at the previous, larger lambda).
- *   alpha in (0, 1)       : mixing weight; point k solves lambda1 = alpha*lam_k,
+ *   alpha in (0, 1]       : mixing weight (1: the Lasso); point k solves lambda1 = alpha*lam_k,
  *                           lambda2 = (1 - alpha)*lam_k with lam_k = c_lambda[k]*lam_max,
  *                           lam_max = ||A^T b||_inf / alpha (the smallest lam with
  *                           solution 0), computed with FP64 accumulation over the
@@ -194,7 +198,8 @@ typedef struct {
  * doubles (nullable; beta scattered to J, zero elsewhere); out: HOST.
  * status in out: 0 ok; 1 r >= m (the least-squares fit is not determined:
  * rss, gcv, ebic are NaN, beta_out zero); 2 A_J^T A_J not positive definite
- * (likewise).  Needs lambda2 > 0 and m <= 4096.
+ * (likewise).  Needs lambda2 >= 0 and m <= 4096; with lambda2 = 0 a singular
+ * Gram matrix returns SSNAL_ENUMERIC.
  */
 typedef struct {
   int32_t status;

@@ -335,14 +335,25 @@ int certify(const void* A, int dt, int64_t lda, int m, int64_t n, const double* 
   HIPCHK(gemv_t(A, dt, lda, m, n, nullptr, w.rho, w.wd, true, st, tm.e0, tm.e1));
   ++*gemv_calls;
   HIPCHK(eta_pass(x, w.wd, n, l1, l2, w.part, w.scal, st));
+  // the Lasso (lambda2 = 0) bounds D at a scaled feasible point: |A^T rho|_inf
+  if (l2 == 0.0) HIPCHK(absmax(w.wd, n, w.part, w.scal + SC_AMAX, st));
   return 0;
 }
 
+// D(rho) with p* of Prop. 1; for the Lasso (lambda2 = 0) p* is the indicator
+// of |z|_inf <= lambda1 and D is taken at theta*rho, theta = min(1,
+// lambda1/|A^T rho|_inf), the largest feasible multiple of rho.
 void certificate_values(const double* hs, double l1, double l2, double* eta, double* F, double* D) {
   const double RR = hs[SC_RR], BR = hs[SC_BR];
   *eta = std::sqrt(hs[SC_ETA_E]) / (1.0 + std::sqrt(hs[SC_ETA_XX]) + std::sqrt(RR));
   *F = 0.5 * RR + l1 * hs[SC_ETA_X1] + 0.5 * l2 * hs[SC_ETA_XX];
-  *D = -0.5 * RR - BR - hs[SC_ETA_PS] / (2.0 * l2);
+  if (l2 == 0.0) {
+    const double amax = hs[SC_AMAX];
+    const double th = amax > l1 ? l1 / amax : 1.0;
+    *D = -(0.5 * th * th * RR + th * BR);
+  } else {
+    *D = -0.5 * RR - BR - hs[SC_ETA_PS] / (2.0 * l2);
+  }
 }
 
 int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int64_t m64,
@@ -352,7 +363,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   if (int rc = check_args(A, dt, lda, b, m64, n)) return rc;
   if (!x) return fail(SSNAL_EINVAL, "x_out must be a non-null device pointer");
   if (!(l1 >= 0.0) || !std::isfinite(l1)) return fail(SSNAL_EINVAL, "lambda1 must be finite and >= 0");
-  if (!(l2 > 0.0) || !std::isfinite(l2)) return fail(SSNAL_EINVAL, "lambda2 must be finite and > 0");
+  if (!(l2 >= 0.0) || !std::isfinite(l2)) return fail(SSNAL_EINVAL, "lambda2 must be finite and >= 0");
   if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
   const int m = (int)m64;
   ssnal_en_opts o;
@@ -653,7 +664,7 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
   if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
   if (!X_out || !c_lambda) return fail(SSNAL_EINVAL, "X_out and c_lambda must be non-null");
   if (nlam < 1) return fail(SSNAL_EINVAL, "nlam must be >= 1");
-  if (!(alpha > 0.0 && alpha < 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1) (lambda2 > 0)");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1] (1: the Lasso)");
   if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
   if (max_active < 0) return fail(SSNAL_EINVAL, "max_active must be >= 0");
   for (int k = 0; k < nlam; ++k)
@@ -916,8 +927,8 @@ int ssnal_srv_submit(ssnal_srv* s, const ssnal_en_problem* p, uint64_t* ticket) 
   if (!s || !p || !ticket) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(p->A, (int)p->a_dtype, p->lda, p->b, p->m, p->n)) return rc;
   if (!p->x_out) return fail(SSNAL_EINVAL, "x_out must be non-null");
-  if (!(p->lambda1 >= 0.0) || !(p->lambda2 > 0.0) || !(p->tol > 0.0))
-    return fail(SSNAL_EINVAL, "need lambda1 >= 0, lambda2 > 0, tol > 0");
+  if (!(p->lambda1 >= 0.0) || !(p->lambda2 >= 0.0) || !(p->tol > 0.0))
+    return fail(SSNAL_EINVAL, "need lambda1 >= 0, lambda2 >= 0, tol > 0");
   const size_t need = ssnal_workspace_bytes(p->m, p->n);
   if (need > s->budget)
     return fail(SSNAL_ENOMEM, "request needs %zu workspace bytes, budget is %zu", need, s->budget);
@@ -1069,7 +1080,7 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
   g_err[0] = 0;
   if (!ctx || !x || !out) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
-  if (!(lambda2 > 0.0) || !std::isfinite(lambda2)) return fail(SSNAL_EINVAL, "lambda2 must be > 0");
+  if (!(lambda2 >= 0.0) || !std::isfinite(lambda2)) return fail(SSNAL_EINVAL, "lambda2 must be >= 0");
   if (m > 4096) return fail(SSNAL_EINVAL, "model selection needs m <= 4096 (dense systems)");
   HIPCHK(hipSetDevice(ctx->device));
   Workspace w;
@@ -1184,7 +1195,7 @@ int ssnal_kkt(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, c
   g_err[0] = 0;
   if (!ctx || !x || !out4) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
-  if (!(lambda2 > 0)) return fail(SSNAL_EINVAL, "lambda2 must be > 0");
+  if (!(lambda2 >= 0)) return fail(SSNAL_EINVAL, "lambda2 must be >= 0");
   HIPCHK(hipSetDevice(ctx->device));
   Workspace ws;
   if (int rc = prepare(ctx, m, n, ws)) return rc;

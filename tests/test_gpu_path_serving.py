@@ -108,7 +108,7 @@ def test_path_truncation_and_errors(gpu, ctx):
     assert np.all(Xh[k + 1:] == 0)
     assert np.count_nonzero(Xh[k]) > 5
     with pytest.raises(gpu.SsnalError):
-        gpu.ssnal_en_path(ctx, A, b, 1.0, grid)  # alpha = 1 is the lasso limit (lambda2 = 0)
+        gpu.ssnal_en_path(ctx, A, b, 1.5, grid)  # alpha outside (0, 1]
     with pytest.raises(gpu.SsnalError):
         gpu.ssnal_en_path(ctx, A, b, 0.5, [1.0, -0.1])
 

@@ -155,7 +155,7 @@ def test_errors(gpu, ctx):
     A, b = _upload(p)
     _say("errors")
     with pytest.raises(gpu.SsnalError) as e:
-        gpu.ssnal_en_solve(ctx, A, b, p.lam1, 0.0)
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, -0.1)  # lambda2 < 0 (0 is the Lasso limit)
     assert e.value.code == -1
     with pytest.raises(gpu.SsnalError) as e:
         gpu.ssnal_en_solve(ctx, A, b, -1.0, 0.5)
