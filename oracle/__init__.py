@@ -85,6 +85,8 @@ def lib():
         L.orc_ls_delta.restype = _d
         L.orc_ls_delta.argtypes = [_D, _D, _i64, _d, _d, _d, _d, _d, _d]
         L.orc_model_select.argtypes = [_D, _i64, _D, _i64, _i64, _d, _D, _D, _D]
+        L.orc_cv.restype = C.c_int
+        L.orc_cv.argtypes = [_D, _i64, _D, _i64, _i64, _I32, C.c_int, _d, _D, C.c_int, _d, _D]
         L.orc_en_solve.restype = C.c_int
         L.orc_en_solve.argtypes = [_D, _i64, _D, _i64, _i64, _d, _d, _D, _d, C.POINTER(Opts),
                                    _D, C.POINTER(Info), _D, C.c_int32, _I32]
@@ -257,3 +259,16 @@ def model_select(AT, b, x, l2, want_beta=False):
     if want_beta:
         res["beta"] = beta
     return res
+
+
+def cv(AT, b, fold, k, alpha, c_lambda, tol=1e-10):
+    """k-fold cross validation on the full data's grid lam_q = c_lambda[q] *
+    ||A^T b||_inf / alpha: (err (k, nlam) mean squared validation errors, status)."""
+    AT, m, n = _design(AT)
+    b = _f64(b)
+    fold = np.ascontiguousarray(fold, dtype=np.int32)
+    c = _f64(c_lambda)
+    err = np.empty((k, c.size))
+    rc = lib().orc_cv(_dp(AT), m, _dp(b), m, n, fold.ctypes.data_as(_I32), int(k), float(alpha),
+                      _dp(c), int(c.size), float(tol), _dp(err))
+    return err, rc

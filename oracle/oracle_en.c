@@ -605,3 +605,55 @@ void orc_model_select(const double* A, int64_t lda, const double* b, int64_t m, 
   free(res);
   free(J);
 }
+
+/* k-fold cross validation on a lambda grid (Sec. "Parameter tuning": the
+ * k-fold criterion costs k extra solves per (lambda1, lambda2)).
+ * fold[i] in [0, k) assigns row i to a validation fold.  The grid is the
+ * full data's: lam_q = c_lambda[q] * ||A^T b||_inf / alpha, lambda1 = alpha
+ * lam_q, lambda2 = (1 - alpha) lam_q.  For each fold f: the rows with
+ * fold != f form the training problem, solved along the grid in order, each
+ * point warm-started from the previous one (tol as given, default options);
+ * err[f*nlam + q] = mean over the rows of fold f of (A x_q - b)^2.
+ * Returns 0, or the first failing solve's status. */
+int orc_cv(const double* A, int64_t lda, const double* b, int64_t m, int64_t n, const int32_t* fold,
+           int k, double alpha, const double* c_lambda, int nlam, double tol, double* err) {
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  orc_gemv_t(A, lda, m, n, b, w);
+  double amax = 0.0;
+  for (int64_t j = 0; j < n; ++j) amax = fabs(w[j]) > amax ? fabs(w[j]) : amax;
+  free(w);
+  const double lam_max = amax / alpha;
+  int worst = 0;
+  double* At = (double*)malloc(sizeof(double) * (size_t)(m * n));
+  double* bt = (double*)malloc(sizeof(double) * (size_t)m);
+  double* x = (double*)malloc(sizeof(double) * (size_t)n);
+  double* xprev = (double*)malloc(sizeof(double) * (size_t)n);
+  double* res = (double*)malloc(sizeof(double) * (size_t)m);
+  for (int f = 0; f < k; ++f) {
+    int64_t mt = 0, mv = 0;
+    for (int64_t i = 0; i < m; ++i) {
+      if (fold[i] == f) { ++mv; continue; }
+      bt[mt++] = b[i];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      int64_t r = 0;
+      for (int64_t i = 0; i < m; ++i)
+        if (fold[i] != f) At[j * mt + r++] = A[j * lda + i];
+    }
+    for (int q = 0; q < nlam; ++q) {
+      const double lam = c_lambda[q] * lam_max;
+      orc_info info;
+      const int rc = orc_en_solve(At, mt, bt, mt, n, alpha * lam, (1.0 - alpha) * lam,
+                                  q > 0 ? xprev : NULL, tol, NULL, x, &info, NULL, 0, NULL);
+      if (rc != 0 && worst == 0) worst = rc;
+      orc_gemv_n(A, lda, m, n, x, res);
+      double s = 0.0;
+      for (int64_t i = 0; i < m; ++i)
+        if (fold[i] == f) s += (res[i] - b[i]) * (res[i] - b[i]);
+      err[(int64_t)f * nlam + q] = mv > 0 ? s / (double)mv : NAN;
+      memcpy(xprev, x, sizeof(double) * (size_t)n);
+    }
+  }
+  free(At); free(bt); free(x); free(xprev); free(res);
+  return worst;
+}

@@ -83,4 +83,9 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
 void orc_model_select(const double* A, int64_t lda, const double* b, int64_t m, int64_t n,
                       double lambda2, const double* x, double* out, double* beta_out);
 
+/* k-fold cross validation on the full data's lambda grid: err (k x nlam) =
+ * mean squared validation error per fold and point. */
+int orc_cv(const double* A, int64_t lda, const double* b, int64_t m, int64_t n, const int32_t* fold,
+           int k, double alpha, const double* c_lambda, int nlam, double tol, double* err);
+
 #endif

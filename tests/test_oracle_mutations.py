@@ -38,6 +38,8 @@ MUTATIONS = {
     "ebic_log_n": ("ebic = log(rss / md) + (nu / md) * (log(md) + log((double)n));",
                    "ebic = log(rss / md) + (nu / md) * log(md);"),
     "lasso_theta": ("if (amax > l1) theta = l1 / amax;", "if (amax > l1) theta = 1.0;"),
+    "cv_validation_rows": ("if (fold[i] == f) s += (res[i] - b[i]) * (res[i] - b[i]);",
+                           "if (fold[i] != f) s += (res[i] - b[i]) * (res[i] - b[i]);"),
     "debias_rhs": ("for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * b[i];",
                    "for (int64_t i = 1; i < m; ++i) s += A[J[p] * lda + i] * b[i];"),
 }

@@ -502,3 +502,29 @@ def test_lasso_conjugate_and_dual_bound(orc):
     rho = A @ xs - b
     assert orc.dual_obj(AT, b, rho, l1, 0.0) == pytest.approx(
         pinlib.primal_objective(A, b, xs, l1, 0.0), rel=1e-10)
+
+
+# ---------------------------------------------------------------- k-fold CV
+# k-fold cross validation (Sec. "Parameter tuning") on the full data's grid.
+
+def test_cv_zero_solution_and_composition(orc):
+    """Far above lambda_max every fold's solution is 0 and its error is the
+    mean of b^2 over its rows; at an interior point a fold's error equals the
+    validation error of a cold solve on that fold's training rows."""
+    A, b, _, _ = pinlib.gaussian_problem(60, 300, 3, k=5, c_lam=0.3)
+    AT = np.ascontiguousarray(A.T)
+    k, alpha = 4, 0.6
+    fold = (np.arange(60) * 7) % k
+    grid = [20.0, 0.4, 0.15]
+    err, rc = orc.cv(AT, b, fold, k, alpha, grid, tol=1e-11)
+    assert rc == 0
+    for f in range(k):
+        assert err[f, 0] == pytest.approx(np.mean(b[fold == f] ** 2), rel=1e-14)
+    lam_max = np.max(np.abs(A.T @ b)) / alpha
+    for f in (0, 3):
+        tr = fold != f
+        lam = grid[2] * lam_max
+        x, info = _solve(orc, A[tr], b[tr], alpha * lam, (1 - alpha) * lam, tol=1e-11)
+        assert info["status"] == 0
+        e = np.mean((A[~tr] @ x - b[~tr]) ** 2)
+        assert err[f, 2] == pytest.approx(e, rel=1e-8)
