@@ -167,6 +167,25 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
                   int64_t max_active, double tol, hipStream_t stream, double* X_out,
                   const ssnal_en_opts* opts, ssnal_en_info* infos);
 
+/*
+ * k-fold cross validation on a lambda grid (Sec. "Parameter tuning": k extra
+ * solves per (lambda1, lambda2) and fold), as k warm-started paths over the
+ * full data's grid lam_q = c_lambda[q] * ||A^T b||_inf / alpha (lambda1 = alpha
+ * lam_q, lambda2 = (1 - alpha) lam_q):
+ *   fold     : device, m int32 labels in [0, k); fold f validates its rows and
+ *              trains on the others (each fold needs both).
+ *   err_out  : HOST, k x nlam (row f = fold f): mean over the rows of fold f of
+ *              (A x_q - b)^2, x_q the fold's solution at point q.
+ *   infos    : HOST, nullable, k x nlam.
+ * The training rows of a fold are copied into a context buffer ((m-1) x n
+ * elements of A's storage type); m <= 4096; alpha in (0, 1].  Returns the
+ * most severe status over the solves (an error stops).
+ */
+int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                int64_t m, int64_t n, const int32_t* fold, int k, double alpha,
+                const double* c_lambda, int nlam, double tol, hipStream_t stream,
+                const ssnal_en_opts* opts, double* err_out, ssnal_en_info* infos);
+
 /* One problem of a batch or of the serving loop (fields as in ssnal_en_solve). */
 typedef struct {
   const void* A;

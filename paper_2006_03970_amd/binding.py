@@ -84,6 +84,8 @@ def lib():
         L.ssnal_kkt.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _d, _d, C.POINTER(_d), _vp]
         L.ssnal_en_model_select.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, _vp, _vp, _vp,
                                             C.POINTER(Select)]
+        L.ssnal_en_cv.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _i, _d, C.POINTER(_d), _i,
+                                  _d, _vp, C.POINTER(Opts), C.POINTER(_d), C.POINTER(Info)]
         L.ssnal_en_path.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, C.POINTER(_d), _i, _i64,
                                     _d, _vp, _vp, C.POINTER(Opts), C.POINTER(Info)]
         L.ssnal_en_solve_batch.argtypes = [_vp, C.POINTER(Problem), _i, C.POINTER(Opts), _vp,
@@ -298,6 +300,26 @@ def ssnal_en_model_select(ctx, A, b, x, lambda2, m=None, want_beta=False, stream
     if want_beta:
         out["beta"] = beta
     return out
+
+
+def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, m=None, opts=None, stream=None):
+    """k-fold cross validation over the full data's grid: (err (k, nlam) mean
+    squared validation errors, infos (k, nlam) dicts, status).  fold: device
+    int32 tensor of m labels in [0, k)."""
+    import numpy as np
+    pA, dt, lda, m, n = _design(A, m)
+    nlam = len(c_lambda)
+    cl = (C.c_double * nlam)(*[float(v) for v in c_lambda])
+    err = (C.c_double * (k * nlam))()
+    infos = (Info * (k * nlam))()
+    o = opts if opts is not None else make_opts()
+    rc = lib().ssnal_en_cv(ctx.ptr, pA, dt, lda, _ptr(b), m, n, _ptr(fold), int(k), float(alpha), cl,
+                           nlam, float(tol), _stream(stream), C.byref(o), err, infos)
+    if rc < 0:
+        _check(rc)
+    E = np.array(err[:], dtype=np.float64).reshape(k, nlam)
+    I = [[infos[f * nlam + q].as_dict() for q in range(nlam)] for f in range(k)]
+    return E, I, rc
 
 
 def workspace_bytes(m, n) -> int:

@@ -3,6 +3,8 @@
 // feature of the A^T v pass, so they are sized for few launches rather than
 // for bandwidth: 256 threads, 8 elements per thread, one block per 2048
 // features, and "last block finishes" reductions instead of extra launches.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "scal.hpp"
@@ -814,6 +816,99 @@ hipError_t scatter(const int32_t* J, const double* v, const double* r_dev, int64
   if (nb < 1) nb = 1;
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kNT), 0, st, J, v, r_dev, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k-fold
+// Folds of m <= 4096 rows, one workgroup of 1024 threads: thread t owns the
+// contiguous rows [t*c, t*c + c), c = ceil(m / 1024), so a block scan of the
+// per-thread counts orders the compacted rows.
+constexpr int kFoldNT = 1024;
+__global__ __launch_bounds__(kFoldNT) void k_fold_rows(const int32_t* __restrict__ fold, int m, int k,
+                                                       int f, int32_t* __restrict__ rows,
+                                                       double* __restrict__ scal) {
+  __shared__ int cnt[kFoldNT];
+  __shared__ double red[kFoldNT / kWave];
+  const int t = threadIdx.x;
+  const int c = (m + kFoldNT - 1) / kFoldNT;
+  const int r0 = t * c, r1 = min(r0 + c, m);
+  int mine = 0, bad = 0, val = 0;
+  for (int i = r0; i < r1; ++i) {
+    const int fi = fold[i];
+    bad += (fi < 0) | (fi >= k);
+    val += fi == f;
+    mine += fi != f;
+  }
+  cnt[t] = mine;
+  __syncthreads();
+  // exclusive scan of cnt (Hillis-Steele over 1024 entries)
+  for (int d = 1; d < kFoldNT; d *= 2) {
+    const int v = t >= d ? cnt[t - d] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int pos = cnt[t] - mine;
+  for (int i = r0; i < r1; ++i)
+    if (fold[i] != f) rows[pos++] = i;
+  const double nbad = block_sum<kFoldNT>((double)bad, red);
+  const double nval = block_sum<kFoldNT>((double)val, red);
+  if (t == 0) {
+    scal[SC_CV_MT] = (double)cnt[kFoldNT - 1];
+    scal[SC_CV_MV] = nval;
+    scal[SC_CV_BAD] = nbad;
+  }
+}
+
+hipError_t fold_rows(const int32_t* fold, int m, int k, int f, int32_t* rows, double* scal,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_fold_rows, dim3(1), dim3(kFoldNT), 0, st, fold, m, k, f, rows, scal);
+  return hipGetLastError();
+}
+
+// A_t[:, j] = A[rows, j] (mt rows, leading dimension mt) and b_t = b[rows].
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_gather_rows(const T* __restrict__ A, int64_t lda,
+                                                     int64_t n, const int32_t* __restrict__ rows,
+                                                     int mt, const double* __restrict__ b,
+                                                     T* __restrict__ At, double* __restrict__ bt) {
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const T* a = A + j * lda;
+    T* o = At + j * mt;
+    for (int i = threadIdx.x; i < mt; i += kNT) o[i] = a[rows[i]];
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < mt; i += kNT) bt[i] = b[rows[i]];
+}
+
+hipError_t gather_rows(const void* A, int dtype, int64_t lda, int64_t n, const int32_t* rows, int mt,
+                       const double* b, void* At, double* bt, hipStream_t st) {
+  const unsigned nb = (unsigned)std::min<int64_t>(n, 8192);
+  if (dtype == kF64)
+    hipLaunchKernelGGL(k_gather_rows<double>, dim3(nb), dim3(kNT), 0, st, (const double*)A, lda, n,
+                       rows, mt, b, (double*)At, bt);
+  else if (dtype == kF32)
+    hipLaunchKernelGGL(k_gather_rows<float>, dim3(nb), dim3(kNT), 0, st, (const float*)A, lda, n,
+                       rows, mt, b, (float*)At, bt);
+  else
+    hipLaunchKernelGGL(k_gather_rows<uint16_t>, dim3(nb), dim3(kNT), 0, st, (const uint16_t*)A, lda,
+                       n, rows, mt, b, (uint16_t*)At, bt);
+  return hipGetLastError();
+}
+
+// *out = sum over the rows of fold f of res_i^2 (one workgroup, fixed order).
+__global__ __launch_bounds__(kFoldNT) void k_fold_sq(const double* __restrict__ res,
+                                                     const int32_t* __restrict__ fold, int m, int f,
+                                                     double* __restrict__ out) {
+  __shared__ double red[kFoldNT / kWave];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += kFoldNT) s += fold[i] == f ? res[i] * res[i] : 0.0;
+  s = block_sum<kFoldNT>(s, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t fold_sq(const double* res, const int32_t* fold, int m, int f, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold_sq, dim3(1), dim3(kFoldNT), 0, st, res, fold, m, f, out);
   return hipGetLastError();
 }
 

@@ -97,6 +97,15 @@ hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, doub
 // Small helpers
 hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st);
 hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st);
+// k-fold (m <= 4096): rows = the rows with fold != f in ascending order; scal
+// slots get their count, the count of fold f, and the labels outside [0, k).
+hipError_t fold_rows(const int32_t* fold, int m, int k, int f, int32_t* rows, double* scal,
+                     hipStream_t st);
+// At (mt x n, leading dimension mt, same storage type as A) = A[rows, :], bt = b[rows].
+hipError_t gather_rows(const void* A, int dtype, int64_t lda, int64_t n, const int32_t* rows, int mt,
+                       const double* b, void* At, double* bt, hipStream_t st);
+// *out = sum of res_i^2 over the rows of fold f.
+hipError_t fold_sq(const double* res, const int32_t* fold, int m, int f, double* out, hipStream_t st);
 // out[J[k]] = v[k] for k < r (r read from r_dev; r_bound >= r).
 hipError_t scatter(const int32_t* J, const double* v, const double* r_dev, int64_t r_bound,
                    double* out, hipStream_t st);

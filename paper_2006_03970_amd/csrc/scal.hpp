@@ -29,6 +29,9 @@ enum Scal : int {
   SC_MS_FROB = 21,   // ||L^{-1}||_F^2
   SC_MS_RSS = 22,    // ||A_J beta - b||^2
   SC_MS_NONE = 23,   // sink of an empty sum
+  SC_CV_MT = 24,     // k-fold: training rows of the current fold
+  SC_CV_MV = 25,     // validation rows of the current fold
+  SC_CV_BAD = 26,    // fold labels outside [0, k)
   SC_DELTA = 32,   // 33 slots: line-search increments Delta_k (+ second-order sum)
   SC_BLK = 80,     // per-block partials of the m-vector finishers (<= 16 blocks x 3)
   SC_SIZE = 160

@@ -58,6 +58,7 @@ struct DevBuf {
 struct ssnal_ctx {
   int device = 0;
   DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal;
+  DevBuf cv_a, cv_x, cv_m;  // k-fold: a fold's training design, its path, rows / b / errors
   double* h_scal = nullptr;  // coherent pinned: SC_SIZE doubles, then the publish flag
   double* d_scal = nullptr;  // the same memory as the device addresses it
   unsigned long long pub_seq = 0;
@@ -637,7 +638,7 @@ void ssnal_ctx_destroy(ssnal_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart,
-                    &c->V, &c->syrk, &c->mvec, &c->scal};
+                    &c->V, &c->syrk, &c->mvec, &c->scal, &c->cv_a, &c->cv_x, &c->cv_m};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -654,6 +655,11 @@ int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t l
   return solve_impl(ctx, A, (int)a_dtype, lda, b, m, n, lambda1, lambda2, x0, tol, stream, x_out,
                     opts, info);
 }
+
+static int path_impl(ssnal_ctx* ctx, const void* A, int dt, int64_t lda, const double* b, int64_t m,
+                     int64_t n, double alpha, double lam_max, const double* c_lambda, int nlam,
+                     int64_t max_active, double tol, hipStream_t stream, double* X_out,
+                     const ssnal_en_opts* opts, ssnal_en_info* infos);
 
 int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
                   int64_t m, int64_t n, double alpha, const double* c_lambda, int nlam,
@@ -684,7 +690,16 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
     if (ctx->h_scal[SC_NONFIN] != 0.0) return fail(SSNAL_ENONFINITE, "A^T b holds non-finite entries");
     amax = ctx->h_scal[SC_AMAX];
   }
-  const double lam_max = amax / alpha;
+  return path_impl(ctx, A, dt, lda, b, m, n, alpha, amax / alpha, c_lambda, nlam, max_active, tol,
+                   stream, X_out, opts, infos);
+}
+
+// The path at lam_k = c_lambda[k] * lam_max (lam_max given; 0: x = 0 throughout).
+static int path_impl(ssnal_ctx* ctx, const void* A, int dt, int64_t lda, const double* b, int64_t m,
+                     int64_t n, double alpha, double lam_max, const double* c_lambda, int nlam,
+                     int64_t max_active, double tol, hipStream_t stream, double* X_out,
+                     const ssnal_en_opts* opts, ssnal_en_info* infos) {
+  const double amax = lam_max;
   // Each point starts from the previous point's x and, unless the caller fixes
   // sigma0, from its final penalty sigma: the warm start then usually ends
   // after one multiplier update.  The carried sigma is capped at the value a
@@ -734,6 +749,79 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
   }
   HIPCHK(hipStreamSynchronize(stream));
   if (worst == SSNAL_PATH_TRUNCATED) snprintf(g_err, sizeof(g_err), "path truncated at max_active");
+  return worst;
+}
+
+int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                int64_t m, int64_t n, const int32_t* fold, int k, double alpha,
+                const double* c_lambda, int nlam, double tol, hipStream_t stream,
+                const ssnal_en_opts* opts, double* err_out, ssnal_en_info* infos) {
+  g_err[0] = 0;
+  if (!ctx || !fold || !err_out || !c_lambda) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
+  if (k < 2 || k > m) return fail(SSNAL_EINVAL, "need 2 <= k <= m folds");
+  if (m > 4096) return fail(SSNAL_EINVAL, "k-fold cross validation needs m <= 4096");
+  if (nlam < 1) return fail(SSNAL_EINVAL, "nlam must be >= 1");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1]");
+  if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
+  for (int q = 0; q < nlam; ++q)
+    if (!(c_lambda[q] > 0.0) || !std::isfinite(c_lambda[q]))
+      return fail(SSNAL_EINVAL, "c_lambda[%d] must be finite and > 0", q);
+  HIPCHK(hipSetDevice(ctx->device));
+  const int dt = (int)a_dtype;
+  const int mi = (int)m;
+  hipStream_t st = stream;
+  double* hs = ctx->h_scal;
+  // the full data's grid: lam_max = ||A^T b||_inf / alpha
+  double amax = 0.0;
+  {
+    Workspace w;
+    if (int rc = prepare(ctx, m, n, w)) return rc;
+    HIPCHK(gemv_t(A, dt, lda, mi, n, nullptr, b, w.wd, true, st));
+    HIPCHK(absmax(w.wd, n, w.part, w.scal + SC_AMAX, st));
+    if (int rc = readback(ctx, w, st, nullptr)) return rc;
+    amax = hs[SC_AMAX];
+  }
+  const double lam_max = amax / alpha;
+  // fold buffers: the training design (at most m - 1 rows), its path, row list, b and errors
+  const size_t sa = (size_t)dtype_size(dt);
+  if (int rc = ensure(ctx->cv_a, (size_t)(m - 1) * (size_t)n * sa)) return rc;
+  if (int rc = ensure(ctx->cv_x, (size_t)nlam * (size_t)n * 8)) return rc;
+  if (int rc = ensure(ctx->cv_m, (size_t)m * 4 + (size_t)(m + nlam + 2) * 8)) return rc;
+  int32_t* rows = (int32_t*)ctx->cv_m.p;
+  double* bt = (double*)((char*)ctx->cv_m.p + ((size_t)m * 4 + 7) / 8 * 8);
+  double* errd = bt + m;
+  double* X = (double*)ctx->cv_x.p;
+  int worst = 0;
+  for (int f = 0; f < k; ++f) {
+    Workspace w;
+    if (int rc = prepare(ctx, m, n, w)) return rc;
+    HIPCHK(fold_rows(fold, mi, k, f, rows, w.scal, st));
+    if (int rc = readback(ctx, w, st, nullptr)) return rc;
+    if (hs[SC_CV_BAD] != 0.0) return fail(SSNAL_EINVAL, "%g fold labels outside [0, %d)", hs[SC_CV_BAD], k);
+    const int mt = (int)hs[SC_CV_MT];
+    const double mv = hs[SC_CV_MV];
+    if (mt < 1 || mv < 1) return fail(SSNAL_EINVAL, "fold %d leaves no training or no validation rows", f);
+    HIPCHK(gather_rows(A, dt, lda, n, rows, mt, b, ctx->cv_a.p, bt, st));
+    ssnal_en_info* inf = infos ? infos + (int64_t)f * nlam : nullptr;
+    const int rc = path_impl(ctx, ctx->cv_a.p, dt, mt, bt, mt, n, alpha, lam_max, c_lambda, nlam, 0,
+                             tol, st, X, opts, inf);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    // validation errors: residual of the full design, summed over fold f
+    if (int rc2 = prepare(ctx, m, n, w)) return rc2;
+    for (int q = 0; q < nlam; ++q) {
+      const double* xq = X + (int64_t)q * n;
+      HIPCHK(support_count(xq, n, w.counts, st));
+      HIPCHK(support_write(xq, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
+      HIPCHK(gather_gemv_partial(A, dt, lda, mi, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
+      HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, mi, 2, nullptr, b, nullptr, w.t1, w.scal, st));
+      HIPCHK(fold_sq(w.t1, fold, mi, f, errd + q, st));
+    }
+    HIPCHK(hipMemcpyAsync(err_out + (int64_t)f * nlam, errd, (size_t)nlam * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < nlam; ++q) err_out[(int64_t)f * nlam + q] /= mv;
+  }
   return worst;
 }
 
