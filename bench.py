@@ -117,7 +117,8 @@ def path_bench(reps=2):
     """The warm-started path of the SNP-like workload (m=500, n=2e5, alpha=0.7,
     100 points c_lambda 1 -> 0.01, FP32 storage, tol 1e-6): points/s of the
     path, then gcv / e-bic at every point (degrees of freedom, least squares
-    on the selected features) and the selected point."""
+    on the selected features), 10-fold cross validation over the same grid,
+    and the point each criterion selects."""
     import numpy as np
     import torch
 
@@ -151,14 +152,26 @@ def path_bench(reps=2):
     gcv = [s["gcv"] if s["status"] == 0 else np.inf for s in sel]
     ebic = [s["ebic"] if s["status"] == 0 else np.inf for s in sel]
     kg, ke = int(np.argmin(gcv)), int(np.argmin(ebic))
+    # 10-fold cross validation over the same grid: ten warm-started paths on the
+    # training rows of each fold, validation error at every point
+    fold = torch.from_numpy(np.random.default_rng(5).permutation(np.arange(p.m) % 10).astype(np.int32))
+    fold = fold.to(A.device)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    E, _, cv_status = binding.ssnal_en_cv(ctx, A, b, fold, 10, alpha, cl, tol=1e-6, stream=stream)
+    el_cv = time.perf_counter() - t
+    kc = int(np.argmin(E.mean(axis=0)))
     out = {"workload": "SNP-like elastic-net path, m=500, n=200000, k=30, snr=5, alpha=0.7, "
                        "100 points c_lambda 1 -> 0.01, FP32 storage, tol 1e-6",
            "status": status, "points_per_s": len(cl) / el, "ms_per_path": el * 1e3,
            "newton_iters": int(sum(i["newton_iters"] for i in infos)),
            "model_select_ms_per_point": el_sel / len(cl) * 1e3,
-           "gcv_point": kg, "gcv_nnz": sel[kg]["r"], "ebic_point": ke, "ebic_nnz": sel[ke]["r"]}
+           "gcv_point": kg, "gcv_nnz": sel[kg]["r"], "ebic_point": ke, "ebic_nnz": sel[ke]["r"],
+           "cv10_status": cv_status, "cv10_ms": el_cv * 1e3, "cv10_point": kc,
+           "cv10_nnz": int(torch.count_nonzero(X[kc]))}
     print(f"[bench] path: {out['ms_per_path']:.1f} ms/path, model selection "
-          f"{out['model_select_ms_per_point']:.2f} ms/point", file=sys.stderr, flush=True)
+          f"{out['model_select_ms_per_point']:.2f} ms/point, 10-fold cv {out['cv10_ms']:.0f} ms",
+          file=sys.stderr, flush=True)
     return out
 
 
