@@ -32,14 +32,16 @@ def build(force: bool = True) -> str:
 class Opts(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("sigma_factor", C.c_double), ("sigma_max", C.c_double),
                 ("mu", C.c_double), ("delta", C.c_double), ("max_outer", C.c_int32),
-                ("max_inner", C.c_int32), ("max_backtrack", C.c_int32)]
+                ("max_inner", C.c_int32), ("max_backtrack", C.c_int32), ("newton_cg", C.c_int32),
+                ("cg_maxit", C.c_int32), ("cg_eta", C.c_double), ("cg_tau", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer_iters", C.c_int32), ("newton_iters", C.c_int32),
                 ("r_final", C.c_int32), ("nnz", C.c_int64), ("eta", C.c_double),
                 ("kkt1", C.c_double), ("kkt3", C.c_double), ("primal_obj", C.c_double),
-                ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double)]
+                ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double),
+                ("cg_iters", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +84,9 @@ def lib():
         L.orc_cholesky.argtypes = [_D, _i64]
         L.orc_newton_direction.restype = C.c_int
         L.orc_newton_direction.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D, _D]
+        L.orc_newton_matvec.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D, _D]
+        L.orc_newton_cg.restype = C.c_int
+        L.orc_newton_cg.argtypes = [_D, _i64, _i64, _I32, _i64, _d, _D, _d, C.c_int32, _D]
         L.orc_ls_delta.restype = _d
         L.orc_ls_delta.argtypes = [_D, _D, _i64, _d, _d, _d, _d, _d, _d]
         L.orc_model_select.argtypes = [_D, _i64, _D, _i64, _i64, _d, _D, _D, _D]
@@ -215,6 +220,28 @@ def newton_direction(AT, J, kappa, g):
     if rc != 0:
         raise np.linalg.LinAlgError("Newton matrix not positive definite")
     return d
+
+
+def newton_matvec(AT, J, kappa, p):
+    """V p with V = I + kappa A_J A_J^T, never formed (eq. AJ_system)."""
+    AT, m, n = _design(AT)
+    J = np.ascontiguousarray(J, dtype=np.int32)
+    p = _f64(p)
+    q = np.empty(m)
+    lib().orc_newton_matvec(_dp(AT), m, m, J.ctypes.data_as(_I32), J.size, kappa, _dp(p), _dp(q))
+    return q
+
+
+def newton_cg(AT, J, kappa, g, eps, maxit=500):
+    """Conjugate gradients on V d = -g from d = 0 (the approximate solve of
+    eq. newton_direction).  Returns (d, iterations)."""
+    AT, m, n = _design(AT)
+    J = np.ascontiguousarray(J, dtype=np.int32)
+    g = _f64(g)
+    d = np.empty(m)
+    it = lib().orc_newton_cg(_dp(AT), m, m, J.ctypes.data_as(_I32), J.size, kappa, _dp(g), eps,
+                             int(maxit), _dp(d))
+    return d, it
 
 
 def ls_delta(t, wd, s, sigma, l1, l2, gd, dd):

@@ -6,7 +6,8 @@
  * the paper (Boschi, Reimherr, Chiaromonte, "An Efficient Semi-smooth Newton
  * Augmented Lagrangian Method for Elastic Net"):
  *   - no blocking, no fusion, no Sherman-Morrison-Woodbury branch: the Newton
- *     system is always the dense m x m one;
+ *     system is always the m x m one, solved by Cholesky or, on request, by
+ *     plain conjugate gradients;
  *   - A^T y is recomputed from scratch every Newton iteration;
  *   - plain loops, left-to-right sums, no BLAS.
  * It is pinned by tests that do not use it (closed forms, brute force,
@@ -24,6 +25,10 @@
  *   - the multiplier update x - sigma (A^T y + z) is evaluated as
  *     prox_{sigma p}(x - sigma A^T y), its value by the Moreau decomposition
  *     (Sec. 2.2); this keeps exact zeros in x.
+ *   - conjugate gradients (the approximate solve for large m and r) start
+ *     from d = 0 and stop at ||V d + g|| <= min(0.1, kkt1^0.5) ||g|| or after
+ *     500 iterations (the paper fixes no rule; this is an inexact-Newton
+ *     forcing term of order 1.5).
  *   - sigma0 defaults to 2.5 / mean_j ||a_j||^2 (= 5e-3 when the columns have
  *     squared norm m = 500, the setting of Sec. 4.1), factor 5, capped 1e8.
  */
@@ -311,6 +316,62 @@ int orc_newton_direction(const double* A, int64_t lda, int64_t m, const int32_t*
   return rc;
 }
 
+/* V p for V = I_m + kappa A_J A_J^T (eq. AJ_system) without forming V: the r
+ * products A_J^T p, then p + kappa A_J (A_J^T p).  Pinned: equals the dense
+ * matrix of orc_newton_matrix times p. */
+void orc_newton_matvec(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                       double kappa, const double* p, double* q) {
+  double* s = (double*)malloc(sizeof(double) * (size_t)(r > 0 ? r : 1));
+  for (int64_t k = 0; k < r; ++k) s[k] = dot(COL(A, lda, J[k]), p, m);
+  for (int64_t i = 0; i < m; ++i) q[i] = 0.0;
+  for (int64_t k = 0; k < r; ++k) {
+    const double* a = COL(A, lda, J[k]);
+    for (int64_t i = 0; i < m; ++i) q[i] += a[i] * s[k];
+  }
+  for (int64_t i = 0; i < m; ++i) q[i] = p[i] + kappa * q[i];
+  free(s);
+}
+
+/* Approximate Newton direction by conjugate gradients (Sec. 3.2: the
+ * approximate solve of eq. newton_direction when m and r are large): textbook
+ * CG on V d = -g from d = 0 with the product above, stopping once the
+ * recursive residual satisfies ||res||^2 <= eps^2 ||g||^2 or after maxit
+ * iterations.  Returns the number of iterations.  Pinned: finite
+ * termination (V has at most r + 1 distinct eigenvalues), agreement with the
+ * Cholesky direction, the V-norm error never growing, and the stopping point
+ * being the first iterate that meets the test. */
+int orc_newton_cg(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                  double kappa, const double* g, double eps, int32_t maxit, double* d) {
+  double* res = (double*)malloc(sizeof(double) * (size_t)m);
+  double* p = (double*)malloc(sizeof(double) * (size_t)m);
+  double* q = (double*)malloc(sizeof(double) * (size_t)m);
+  for (int64_t i = 0; i < m; ++i) {
+    d[i] = 0.0;
+    res[i] = -g[i];
+    p[i] = res[i];
+  }
+  double rr = dot(res, res, m);
+  const double stop = eps * eps * dot(g, g, m);
+  int it = 0;
+  while (it < maxit && rr > stop) {
+    orc_newton_matvec(A, lda, m, J, r, kappa, p, q);
+    const double alpha = rr / dot(p, q, m);
+    for (int64_t i = 0; i < m; ++i) {
+      d[i] += alpha * p[i];
+      res[i] -= alpha * q[i];
+    }
+    const double rr_new = dot(res, res, m);
+    const double beta = rr_new / rr;
+    for (int64_t i = 0; i < m; ++i) p[i] = res[i] + beta * p[i];
+    rr = rr_new;
+    ++it;
+  }
+  free(res);
+  free(p);
+  free(q);
+  return it;
+}
+
 /* Armijo quantity for eq. line_search:  psi(y + s d) - psi(y).
  * With t = x - sigma A^T y, wd = A^T d, u = prox(t), t(s) = t - s sigma wd,
  * gd = <grad psi(y), d>, dd = ||d||^2, the identity
@@ -361,6 +422,9 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
   if (opt.max_outer <= 0) opt.max_outer = 100;
   if (opt.max_inner <= 0) opt.max_inner = 50;
   if (opt.max_backtrack <= 0) opt.max_backtrack = 30;
+  if (opt.cg_maxit <= 0) opt.cg_maxit = 500;
+  if (!(opt.cg_eta > 0.0)) opt.cg_eta = 0.1;
+  if (!(opt.cg_tau > 0.0)) opt.cg_tau = 0.5;
   if (!(opt.sigma0 > 0.0)) {
     double s = 0.0;
     for (int64_t j = 0; j < n; ++j) { const double* a = COL(A, lda, j); s += dot(a, a, m); }
@@ -392,7 +456,7 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
    * iteration that met kkt1 and kkt3 but not eta; the decreasing inner
    * tolerances of the criteria the paper refers to for the inner stop. */
   double eps_in = tol;
-  int status = 1, stalled = 0, newton = 0, outer = 0, outer_done = 0, rows = 0;
+  int status = 1, stalled = 0, newton = 0, outer = 0, outer_done = 0, rows = 0, cg_iters = 0;
   int64_t r = 0;
 
   for (outer = 0; outer < opt.max_outer; ++outer) {
@@ -408,7 +472,15 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
       for (int64_t i = 0; i < m; ++i) g[i] = y[i] + b[i] - Au[i]; /* eq. grad_phy */
       kkt1 = nrm2(g, m) / (1.0 + normb);                          /* eq. kkt_res */
       if (kkt1 <= eps_in || inner >= opt.max_inner) break;
-      if (orc_newton_direction(A, lda, m, J, r, kappa, g, d) != 0) { stalled = 1; break; }
+      if (opt.newton_cg && r > 0) {
+        /* CG to the relative residual min(cg_eta, kkt1^cg_tau) */
+        double eps = pow(kkt1, opt.cg_tau);
+        if (eps > opt.cg_eta) eps = opt.cg_eta;
+        cg_iters += orc_newton_cg(A, lda, m, J, r, kappa, g, eps, opt.cg_maxit, d);
+      } else if (orc_newton_direction(A, lda, m, J, r, kappa, g, d) != 0) {
+        stalled = 1;
+        break;
+      }
       orc_gemv_t(A, lda, m, n, d, wd);
       double gd = dot(g, d, m), dd = dot(d, d, m);
       double s = 1.0;
@@ -458,6 +530,7 @@ int orc_en_solve(const double* A, int64_t lda, const double* b, int64_t m, int64
     info->status = status;
     info->outer_iters = outer_done;
     info->newton_iters = newton;
+    info->cg_iters = cg_iters;
     info->r_final = (int32_t)r;
     int64_t nnz = 0;
     for (int64_t j = 0; j < n; ++j) nnz += (x[j] != 0.0);

@@ -30,6 +30,10 @@ typedef struct {
   int32_t max_outer;   /* <= 0: 100 */
   int32_t max_inner;   /* <= 0: 50 */
   int32_t max_backtrack; /* <= 0: 30 */
+  int32_t newton_cg;   /* 0: Cholesky of the m x m system; 1: conjugate gradients */
+  int32_t cg_maxit;    /* <= 0: 500 */
+  double cg_eta;       /* <= 0: 0.1; CG stops at ||V d + g|| <= min(cg_eta, kkt1^cg_tau) ||g|| */
+  double cg_tau;       /* <= 0: 0.5 */
 } orc_opts;
 
 typedef struct {
@@ -39,6 +43,7 @@ typedef struct {
   int32_t r_final;
   int64_t nnz;
   double eta, kkt1, kkt3, primal_obj, dual_obj, rel_gap, sigma_final;
+  int32_t cg_iters;    /* conjugate-gradient iterations over all Newton steps */
 } orc_info;
 
 /* One row per Newton iteration: outer, inner, r, sigma, step, kkt1 */
@@ -69,6 +74,10 @@ void orc_smw_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, i
 int orc_cholesky(double* V, int64_t m);
 int orc_newton_direction(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
                          double kappa, const double* g, double* d);
+void orc_newton_matvec(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                       double kappa, const double* p, double* q);
+int orc_newton_cg(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
+                  double kappa, const double* g, double eps, int32_t maxit, double* d);
 double orc_ls_delta(const double* t, const double* wd, int64_t n, double s, double sigma,
                     double l1, double l2, double gd, double dd);
 

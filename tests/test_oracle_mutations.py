@@ -40,6 +40,13 @@ MUTATIONS = {
     "lasso_theta": ("if (amax > l1) theta = l1 / amax;", "if (amax > l1) theta = 1.0;"),
     "cv_validation_rows": ("if (fold[i] == f) s += (res[i] - b[i]) * (res[i] - b[i]);",
                            "if (fold[i] != f) s += (res[i] - b[i]) * (res[i] - b[i]);"),
+    "cg_beta": ("const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),
+    "cg_matvec_kappa": ("for (int64_t i = 0; i < m; ++i) q[i] = p[i] + kappa * q[i];",
+                        "for (int64_t i = 0; i < m; ++i) q[i] = p[i] + q[i];"),
+    "cg_stop_square": ("const double stop = eps * eps * dot(g, g, m);", "const double stop = eps * dot(g, g, m);"),
+    "cg_residual": ("      res[i] -= alpha * q[i];", "      res[i] -= alpha * p[i];"),
+    "cg_steepest": ("for (int64_t i = 0; i < m; ++i) p[i] = res[i] + beta * p[i];",
+                    "for (int64_t i = 0; i < m; ++i) p[i] = res[i] + 0.0 * beta * p[i];"),
     "debias_rhs": ("for (int64_t i = 0; i < m; ++i) s += A[J[p] * lda + i] * b[i];",
                    "for (int64_t i = 1; i < m; ++i) s += A[J[p] * lda + i] * b[i];"),
 }

@@ -528,3 +528,87 @@ def test_cv_zero_solution_and_composition(orc):
         assert info["status"] == 0
         e = np.mean((A[~tr] @ x - b[~tr]) ** 2)
         assert err[f, 2] == pytest.approx(e, rel=1e-8)
+
+
+# ------------------------------------------- conjugate-gradient Newton direction
+
+def _cg_setup(seed, m=30, n=80, nJ=40):
+    g = np.random.default_rng(seed)
+    A, _, _, _ = pinlib.gaussian_problem(m, n, seed, k=4, c_lam=0.4)
+    J = np.sort(g.choice(n, nJ, replace=False)).astype(np.int32)
+    kappa = g.uniform(0.2, 2.0)
+    grad = g.standard_normal(m)
+    return A, J, kappa, grad
+
+
+def test_newton_matvec_is_matrix_product(orc):
+    """The matrix-free product equals the (pinned) Newton matrix times p."""
+    A, J, kappa, _ = _cg_setup(31, nJ=17)
+    V = orc.newton_matrix(A.T, J, kappa)
+    p = np.random.default_rng(32).standard_normal(A.shape[0])
+    np.testing.assert_allclose(orc.newton_matvec(A.T, J, kappa, p), V @ p, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("nJ", [1, 3, 6])
+def test_newton_cg_finite_termination(orc, nJ):
+    """V = I + kappa A_J A_J^T has at most |J| + 1 distinct eigenvalues, so
+    conjugate gradients solve V d = -g in at most |J| + 1 steps."""
+    A, J, kappa, g = _cg_setup(40 + nJ, nJ=nJ)
+    d, it = orc.newton_cg(A.T, J, kappa, g, 1e-12, maxit=200)
+    assert 1 <= it <= nJ + 1
+    V = orc.newton_matrix(A.T, J, kappa)
+    assert np.linalg.norm(V @ d + g) <= 1e-11 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_newton_cg_matches_cholesky_direction(orc, seed):
+    """Run to a tiny residual, CG gives the direction of the dense solve."""
+    A, J, kappa, g = _cg_setup(seed)
+    d_ch = orc.newton_direction(A.T, J, kappa, g)
+    d_cg, it = orc.newton_cg(A.T, J, kappa, g, 1e-14, maxit=1000)
+    assert it <= 200
+    assert np.linalg.norm(d_cg - d_ch) <= 1e-10 * np.linalg.norm(d_ch)
+    assert g @ d_cg < 0
+
+
+def test_newton_cg_error_decay_and_first_stop(orc):
+    """The V-norm error never grows and obeys the Chebyshev bound
+    2((sqrt(c)-1)/(sqrt(c)+1))^k of conjugate gradients (c = cond V); the
+    returned iterate is the first whose residual meets the test."""
+    A, J, kappa, g = _cg_setup(23)
+    V = orc.newton_matrix(A.T, J, kappa)
+    dstar = np.linalg.solve(V, -g)
+    c = np.linalg.cond(V)
+    rho = (np.sqrt(c) - 1) / (np.sqrt(c) + 1)
+    errs = []
+    for k in range(0, 20):
+        d, it = orc.newton_cg(A.T, J, kappa, g, 0.0, maxit=k)
+        assert it == k
+        e = d - dstar
+        errs.append(np.sqrt(e @ V @ e))
+    for k in range(1, len(errs)):
+        assert errs[k] <= errs[k - 1] * (1 + 1e-10) + 1e-14
+        assert errs[k] <= 2 * rho ** k * errs[0] * (1 + 1e-9) + 1e-14
+    assert errs[-1] < 1e-3 * errs[0]
+    eps = 1e-3
+    d, it = orc.newton_cg(A.T, J, kappa, g, eps)
+    assert np.linalg.norm(V @ d + g) <= eps * np.linalg.norm(g) * (1 + 1e-9)
+    d1, it1 = orc.newton_cg(A.T, J, kappa, g, eps, maxit=it - 1)
+    assert it1 == it - 1
+    assert np.linalg.norm(V @ d1 + g) > eps * np.linalg.norm(g)
+
+
+def test_newton_cg_solve_reaches_cd_minimiser(orc):
+    """The whole solve with CG directions reaches the coordinate-descent
+    minimiser, in at most three times the Newton iterations of the exact-direction
+    solve (early directions are inexact by design)."""
+    A, b, l1, l2 = pinlib.gaussian_problem(60, 400, 12, k=8, c_lam=0.3)
+    x, info = _solve(orc, A, b, l1, l2, newton_cg=1)
+    assert info["status"] == 0 and info["cg_iters"] > 0
+    xc = pinlib.coordinate_descent_en(A, b, l1, l2)
+    Fo, Fc = pinlib.primal_objective(A, b, x, l1, l2), pinlib.primal_objective(A, b, xc, l1, l2)
+    assert abs(Fo - Fc) <= 1e-12 * Fc
+    assert np.max(np.abs(x - xc)) <= 1e-7
+    _, info_ch = _solve(orc, A, b, l1, l2)
+    assert info_ch["cg_iters"] == 0
+    assert info["newton_iters"] <= 3 * info_ch["newton_iters"]
