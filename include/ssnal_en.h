@@ -78,6 +78,12 @@ typedef struct {
   int32_t trace_cap;     /* rows available in `trace` (0 = no trace) */
   double* trace;         /* HOST, nullable: one row per Newton iteration:
                             outer, inner, r, sigma, step, kkt1 (6 doubles) */
+  int32_t newton_cg;     /* 0 = factor the Newton system while it fits (m <= 4096, or
+                            r < m and r <= 4096 for the Woodbury form), conjugate
+                            gradients beyond (default); 1 = conjugate gradients always */
+  int32_t cg_maxit;      /* <= 0: 500 conjugate-gradient iterations per Newton step */
+  double cg_eta;         /* <= 0: 0.1; CG stops at ||V d + g|| <= min(cg_eta, kkt1^cg_tau) ||g|| */
+  double cg_tau;         /* <= 0: 0.5 */
 } ssnal_en_opts;
 
 typedef struct {
@@ -100,6 +106,7 @@ typedef struct {
   double solve_ms;       /* host wall time of the call */
   int32_t atd_launches;  /* with opts.timing: launches of the Newton pass w_d = A^T d ... */
   double atd_ms;         /* ... and their summed durations (HIP events on the solve's stream) */
+  int32_t cg_iters;      /* conjugate-gradient iterations over all Newton steps */
 } ssnal_en_info;
 
 /* Fill *opts with the defaults listed above. */
@@ -108,8 +115,9 @@ void ssnal_en_opts_init(ssnal_en_opts* opts);
 /*
  * Create a context on `device` (HIP ordinal).  The context owns the device
  * workspace, sized lazily to the largest problem seen; it holds O(n) FP64
- * vectors, an m x m FP64 matrix and split-K partial sums (bounded by
- * (2048 + (m/64)^2) * 32 KiB).  Returns 0 or an error code.
+ * vectors, an N x N FP64 matrix (N = min(m, 4096)), split-K partial sums
+ * (bounded by (2048 + (N/64)^2) * 32 KiB) and up to 1025 m-vectors of gathered
+ * partial sums.  Returns 0 or an error code.
  */
 int ssnal_ctx_create(int device, ssnal_ctx** out);
 void ssnal_ctx_destroy(ssnal_ctx* ctx);
@@ -119,8 +127,11 @@ const char* ssnal_last_error(void);
 
 /*
  * One elastic-net solve (Algorithm 1).
- *   A, a_dtype, lda, m, n : the design (see conventions); m >= 1, n >= 1,
- *                           m <= 4096 (the Newton system is dense m x m).
+ *   A, a_dtype, lda, m, n : the design (see conventions); 1 <= m <= 2^20, n >= 1.
+ *                           The Newton system (eq. newton_direction) is factored
+ *                           while it fits 4096 x 4096 (m x m, or r x r by eq.
+ *                           smw_formula when r < m) and solved by conjugate
+ *                           gradients beyond (Sec. 3.2), see opts.newton_cg.
  *   b                     : m responses.
  *   lambda1 >= 0, lambda2 >= 0: the penalty of eq. objective_function (unscaled;
  *                           callers using a 1/m-scaled loss multiply by m);
@@ -298,6 +309,17 @@ int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream);
 int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
                            int64_t m, const int32_t* J, int64_t r, double kappa, const double* g,
                            double* d, int form, hipStream_t stream);
+
+/* Approximate Newton direction by conjugate gradients (Sec. 3.2, the
+ * approximate solve of eq. newton_direction for large m and r): CG on
+ * (I + kappa A_J A_J^T) d = -g from d = 0, with the product applied as
+ * p + kappa A_J (A_J^T p) (never formed), stopping once the recursive residual
+ * has ||res|| <= eps ||g|| or after maxit iterations.  Any m <= 2^20, any r.
+ * J: device, r ascending column indices; g, d: device, m doubles;
+ * iters: HOST, nullable, the iterations taken.  Synchronises the stream. */
+int ssnal_newton_cg(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,
+                    const int32_t* J, int64_t r, double kappa, const double* g, double eps,
+                    int32_t maxit, hipStream_t stream, double* d, int32_t* iters);
 
 /* Line-search increments psi(y + s_k d) - psi(y) (Prop. 2 (1), eq. line_search)
  * for K <= 32 trial steps s (HOST), from x, w = A^T y, wd = A^T d (n doubles

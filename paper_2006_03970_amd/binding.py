@@ -30,7 +30,8 @@ class Opts(C.Structure):
                 ("mu", C.c_double), ("delta", C.c_double), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("max_backtrack", C.c_int32), ("no_refine", C.c_int32),
                 ("no_smw", C.c_int32), ("timing", C.c_int32), ("trace_cap", C.c_int32),
-                ("trace", C.POINTER(C.c_double))]
+                ("trace", C.POINTER(C.c_double)), ("newton_cg", C.c_int32), ("cg_maxit", C.c_int32),
+                ("cg_eta", C.c_double), ("cg_tau", C.c_double)]
 
 
 class Info(C.Structure):
@@ -39,7 +40,8 @@ class Info(C.Structure):
                 ("kkt1", C.c_double), ("kkt3", C.c_double), ("primal_obj", C.c_double),
                 ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double),
                 ("gemv_calls", C.c_int32), ("syncs", C.c_int32), ("gemv_ms", C.c_double),
-                ("solve_ms", C.c_double), ("atd_launches", C.c_int32), ("atd_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("atd_launches", C.c_int32), ("atd_ms", C.c_double),
+                ("cg_iters", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +81,8 @@ def lib():
         L.ssnal_cholesky.argtypes = [_vp, _vp, _i64, _vp]
         L.ssnal_newton_direction.argtypes = [_vp, _vp, _i, _i64, _i64, _vp, _i64, _d, _vp, _vp, _i,
                                              _vp]
+        L.ssnal_newton_cg.argtypes = [_vp, _vp, _i, _i64, _i64, _vp, _i64, _d, _vp, _d, C.c_int32, _vp,
+                                      _vp, C.POINTER(C.c_int32)]
         L.ssnal_ls_delta.argtypes = [_vp, _vp, _vp, _vp, _i64, _d, _d, _d, _d, _d, _i,
                                      C.POINTER(_d), C.POINTER(_d), _vp]
         L.ssnal_kkt.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _d, _d, C.POINTER(_d), _vp]
@@ -102,7 +106,7 @@ def lib():
             getattr(L, name).restype = _i
         for name in ("ssnal_ctx_create", "ssnal_en_solve", "ssnal_gemv_t", "ssnal_active_prox",
                      "ssnal_newton_matrix", "ssnal_cholesky", "ssnal_newton_direction",
-                     "ssnal_ls_delta", "ssnal_kkt"):
+                     "ssnal_newton_cg", "ssnal_ls_delta", "ssnal_kkt"):
             getattr(L, name).restype = _i
         _lib = L
     return _lib
@@ -261,6 +265,17 @@ def ssnal_newton_direction(ctx, A, J, kappa, g, form=-1, m=None, stream=None):
     _check(lib().ssnal_newton_direction(ctx.ptr, pA, dt, lda, m, _ptr(J), J.numel(), float(kappa),
                                         _ptr(g), _ptr(d), int(form), _stream(stream)))
     return d
+
+
+def ssnal_newton_cg(ctx, A, J, kappa, g, eps, maxit=500, m=None, stream=None):
+    """Conjugate-gradient Newton direction.  Returns (d, iterations)."""
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    d = torch.empty(m, dtype=torch.float64, device=A.device)
+    it = C.c_int32(0)
+    _check(lib().ssnal_newton_cg(ctx.ptr, pA, dt, lda, m, _ptr(J), J.numel(), float(kappa), _ptr(g),
+                                 float(eps), int(maxit), _stream(stream), _ptr(d), C.byref(it)))
+    return d, it.value
 
 
 def ssnal_ls_delta(ctx, x, w, wd, sigma, lambda1, lambda2, gd, dd, steps, stream=None):

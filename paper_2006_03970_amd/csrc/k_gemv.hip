@@ -96,12 +96,92 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
   }
 }
 
+// Long or gathered columns: the rows go in panels of PR = ITERS*64*VN, each
+// with its slice of v in registers (as above); a block owns at most
+// kLongCols consecutive columns (or entries of J) and carries their partial
+// sums from panel to panel in LDS, each column in the same wave and lane in
+// every panel, so the panels add up in a fixed order.
+constexpr int kLongCols = 256;
+template <typename T, typename ACC, int ITERS, int VB, bool GATHER>
+__global__ __launch_bounds__(256) void k_gemv_t_long(const T* __restrict__ A, int64_t lda, int m,
+                                                     int64_t ncols, const int32_t* __restrict__ J,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ w, int64_t cpb,
+                                                     const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
+  constexpr int VN = VB / (int)sizeof(T);
+  constexpr int COLS = ColsFor<ITERS>::value;
+  constexpr int PR = ITERS * kWave * VN;
+  __shared__ double lw[kLongCols];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int64_t c0 = (int64_t)blockIdx.x * cpb;
+  const int64_t c1 = c0 + cpb < ncols ? c0 + cpb : ncols;
+  for (int p0 = 0; p0 < m; p0 += PR) {
+    const int mp = m - p0 < PR ? m - p0 : PR;
+    const bool first = p0 == 0, last = p0 + PR >= m;
+    ACC vr[ITERS][VN];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int r0 = (it * kWave + lane) * VN;
+#pragma unroll
+      for (int q = 0; q < VN; ++q) {
+        const ACC x = (ACC)v[p0 + (r0 + q < mp ? r0 + q : mp - 1)];
+        vr[it][q] = (r0 + q < mp) ? x : (ACC)0;
+      }
+    }
+    for (int64_t cb = c0 + (int64_t)wid * COLS; cb < c1; cb += 4 * COLS) {
+      ACC e[COLS][ITERS][VN];
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        const int64_t j = cb + c < c1 ? cb + c : c0;
+        const int64_t col = GATHER ? (int64_t)J[j] : j;
+        // r0 + VN <= lda - p0 whenever r0 < mp: lda is a multiple of VN
+        const T* a = A + col * lda + p0;
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+          const int r0 = (it * kWave + lane) * VN;
+          loadv<VB>(a + (r0 < mp ? r0 : 0), e[c][it]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+          const int r0 = (it * kWave + lane) * VN;
+          if (r0 + VN > mp) {
+#pragma unroll
+            for (int q = 0; q < VN; ++q)
+              if (r0 + q >= mp) e[c][it][q] = (ACC)0;
+          }
+        }
+        ACC acc = (ACC)0;
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it)
+#pragma unroll
+          for (int q = 0; q < VN; ++q) acc += e[c][it][q] * vr[it][q];
+        const double sp = (double)wave_sum(acc);
+        if (lane == 0 && cb + c < c1) {
+          const int k = (int)(cb + c - c0);
+          const double t = first ? sp : lw[k] + sp;
+          if (last)
+            w[cb + c] = t;
+          else
+            lw[k] = t;
+        }
+      }
+    }
+  }
+}
+
 // Any alignment, any m, optional column index list: one element per lane.
 template <typename T, typename ACC, bool GATHER>
 __global__ __launch_bounds__(256) void k_gemv_t_gen(const T* __restrict__ A, int64_t lda, int m,
                                                     int64_t ncols, const int32_t* __restrict__ J,
                                                     const double* __restrict__ v,
-                                                    double* __restrict__ w) {
+                                                    double* __restrict__ w,
+                                                    const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -137,6 +217,19 @@ __global__ __launch_bounds__(256) void k_colsq_gen(const T* __restrict__ A, int6
 
 namespace {
 
+// Loads per lane and panel: the slice of v held in registers stays within 64
+// VGPRs (beyond that the kernels spill).
+template <typename T, typename ACC, int VB>
+constexpr int max_iters() {
+  constexpr int v = 256 / ((VB / (int)sizeof(T)) * (int)sizeof(ACC));
+  return v < 16 ? v : 16;
+}
+template <typename T, typename ACC>
+bool fits_fast(int vb, int m) {
+  const int cap = vb == 16 ? max_iters<T, ACC, 16>() : max_iters<T, ACC, 8>();
+  return m <= cap * kWave * (vb / (int)sizeof(T));
+}
+
 // ev0/ev1 (nullable): events stamped by the dispatch itself around the kernel.
 template <typename T, typename ACC, bool COLSQ, int VB>
 hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
@@ -157,12 +250,16 @@ hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* 
   dim3 g((unsigned)nb), b(256);
 #define SSNAL_GEMV_CASE(IT)                                                                  \
   case IT:                                                                                   \
-    if (ev0)                                                                                 \
-      hipExtLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, ev0, ev1, 0, A, lda, \
-                            m, n, v, w, cpb, colsq_part);                                    \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, A, lda, m, n, v, w,   \
-                         cpb, colsq_part);                                                   \
+    if constexpr (IT <= max_iters<T, ACC, VB>()) {                                           \
+      if (ev0)                                                                               \
+        hipExtLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, ev0, ev1, 0, A,  \
+                              lda, m, n, v, w, cpb, colsq_part);                             \
+      else                                                                                   \
+        hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, A, lda, m, n, v, w, \
+                           cpb, colsq_part);                                                 \
+    } else {                                                                                 \
+      return hipErrorInvalidValue;                                                           \
+    }                                                                                        \
     break;
   switch (iters) {
     SSNAL_GEMV_CASE(1)
@@ -177,27 +274,76 @@ hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* 
 
 template <typename T, typename ACC>
 hipError_t launch_gen(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
-                      double* w, hipStream_t st) {
+                      double* w, hipStream_t st, const double* skip) {
   int64_t nb = (n + 3) / 4;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   if (J)
     hipLaunchKernelGGL((k_gemv_t_gen<T, ACC, true>), dim3((unsigned)nb), dim3(256), 0, st, A, lda, m,
-                       n, J, v, w);
+                       n, J, v, w, skip);
   else
     hipLaunchKernelGGL((k_gemv_t_gen<T, ACC, false>), dim3((unsigned)nb), dim3(256), 0, st, A, lda,
-                       m, n, J, v, w);
+                       m, n, J, v, w, skip);
+  return hipGetLastError();
+}
+
+// Panels of up to 16 loads per lane; a block owns cpb <= kLongCols columns:
+// up to 8 column groups per wave, fewer while that leaves under 1024 blocks.
+template <typename T, typename ACC, int VB, bool GATHER>
+hipError_t launch_long(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
+                       double* w, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                       const double* skip) {
+  constexpr int VN = VB / (int)sizeof(T);
+  const int need = (m + kWave * VN - 1) / (kWave * VN);
+  int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+  if (iters > max_iters<T, ACC, VB>()) iters = max_iters<T, ACC, VB>();
+  const int cols = iters <= 2 ? 8 : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1));
+  const int64_t step = 4 * (int64_t)cols;
+  const int64_t nsteps = (n + step - 1) / step;
+  int64_t spb = (nsteps + 1023) / 1024;
+  if (spb > 8) spb = 8;
+  if (spb * step > kLongCols) spb = kLongCols / step;
+  if (spb < 1) spb = 1;
+  const int64_t cpb = spb * step;
+  const int64_t nb = (n + cpb - 1) / cpb;
+  dim3 g((unsigned)nb), b(256);
+#define SSNAL_LONG_CASE(IT)                                                                      \
+  case IT:                                                                                       \
+    if constexpr (IT <= max_iters<T, ACC, VB>()) {                                               \
+      if (ev0)                                                                                   \
+        hipExtLaunchKernelGGL((k_gemv_t_long<T, ACC, IT, VB, GATHER>), g, b, 0, st, ev0, ev1, 0,   \
+                              A, lda, m, n, J, v, w, cpb, skip);                                 \
+      else                                                                                       \
+        hipLaunchKernelGGL((k_gemv_t_long<T, ACC, IT, VB, GATHER>), g, b, 0, st, A, lda, m, n, J,  \
+                           v, w, cpb, skip);                                                     \
+    }                                                                                            \
+    break;
+  switch (iters) {
+    SSNAL_LONG_CASE(1)
+    SSNAL_LONG_CASE(2)
+    SSNAL_LONG_CASE(4)
+    SSNAL_LONG_CASE(8)
+    SSNAL_LONG_CASE(16)
+  }
+#undef SSNAL_LONG_CASE
   return hipGetLastError();
 }
 
 // Widest vector load (16 or 8 bytes) that every column start allows, with
-// the column held in at most 16 loads per lane; 0 = the element-wise kernel.
+// the column held in at most 16 loads per lane; 0 = no such width.
 int fast_vb(const void* A, int dtype, int64_t lda, int m) {
   const int es = dtype_size(dtype);
   for (int vb = 16; vb >= 8; vb /= 2) {
     if (((uintptr_t)A) % vb != 0 || (lda * es) % vb != 0) continue;
     if (m <= 16 * kWave * (vb / es)) return vb;
   }
+  return 0;
+}
+// Widest vector load that every column start allows, for any m (panels).
+int align_vb(const void* A, int dtype, int64_t lda) {
+  const int es = dtype_size(dtype);
+  for (int vb = 16; vb >= 8; vb /= 2)
+    if (((uintptr_t)A) % vb == 0 && (lda * es) % vb == 0) return vb;
   return 0;
 }
 
@@ -210,20 +356,38 @@ hipError_t launch_vb(int vb, const T* A, int64_t lda, int m, int64_t n, const do
   return launch_fast<T, ACC, COLSQ, 8>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
 }
 
+template <typename T, typename ACC>
+hipError_t dispatch_long(int lvb, const T* A, int64_t lda, int m, int64_t n, const int32_t* J,
+                         const double* v, double* w, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                         const double* skip) {
+  if (lvb == 16)
+    return J ? launch_long<T, ACC, 16, true>(A, lda, m, n, J, v, w, st, ev0, ev1, skip)
+             : launch_long<T, ACC, 16, false>(A, lda, m, n, J, v, w, st, ev0, ev1, skip);
+  return J ? launch_long<T, ACC, 8, true>(A, lda, m, n, J, v, w, st, ev0, ev1, skip)
+           : launch_long<T, ACC, 8, false>(A, lda, m, n, J, v, w, st, ev0, ev1, skip);
+}
+
 template <typename T>
 hipError_t dispatch(const T* A, int64_t lda, int m, int64_t n, const int32_t* J, const double* v,
-                    double* w, bool acc64, int vb, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                    double* w, bool acc64, int vb, int lvb, hipStream_t st, hipEvent_t ev0,
+                    hipEvent_t ev1, const double* skip) {
   if (n <= 0) return hipSuccess;
-  if (vb && !J) {
-    if (acc64) return launch_vb<T, double, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
-    return launch_vb<T, float, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
+  if (vb && !J && !skip) {
+    if (acc64 && fits_fast<T, double>(vb, m))
+      return launch_vb<T, double, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
+    if (!acc64 && fits_fast<T, float>(vb, m))
+      return launch_vb<T, float, false>(vb, A, lda, m, n, v, w, nullptr, nullptr, st, ev0, ev1);
+  }
+  if (lvb) {
+    if (acc64) return dispatch_long<T, double>(lvb, A, lda, m, n, J, v, w, st, ev0, ev1, skip);
+    return dispatch_long<T, float>(lvb, A, lda, m, n, J, v, w, st, ev0, ev1, skip);
   }
   if (ev0) {
     hipError_t e = hipEventRecord(ev0, st);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = acc64 ? launch_gen<T, double>(A, lda, m, n, J, v, w, st)
-                       : launch_gen<T, float>(A, lda, m, n, J, v, w, st);
+  hipError_t e = acc64 ? launch_gen<T, double>(A, lda, m, n, J, v, w, st, skip)
+                       : launch_gen<T, float>(A, lda, m, n, J, v, w, st, skip);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, st);
   return e;
 }
@@ -232,15 +396,19 @@ hipError_t dispatch(const T* A, int64_t lda, int m, int64_t n, const int32_t* J,
 
 hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
                   const double* v, double* w, bool acc64, hipStream_t st, hipEvent_t ev0,
-                  hipEvent_t ev1) {
+                  hipEvent_t ev1, const double* skip) {
   const int vb = fast_vb(A, dtype, lda, m);
+  const int lvb = align_vb(A, dtype, lda);
   switch (dtype) {
     case kF64:
-      return dispatch<double>((const double*)A, lda, m, ncols, J, v, w, true, vb, st, ev0, ev1);
+      return dispatch<double>((const double*)A, lda, m, ncols, J, v, w, true, vb, lvb, st, ev0, ev1,
+                              skip);
     case kF32:
-      return dispatch<float>((const float*)A, lda, m, ncols, J, v, w, acc64, vb, st, ev0, ev1);
+      return dispatch<float>((const float*)A, lda, m, ncols, J, v, w, acc64, vb, lvb, st, ev0, ev1,
+                             skip);
     case kBF16:
-      return dispatch<uint16_t>((const uint16_t*)A, lda, m, ncols, J, v, w, acc64, vb, st, ev0, ev1);
+      return dispatch<uint16_t>((const uint16_t*)A, lda, m, ncols, J, v, w, acc64, vb, lvb, st, ev0,
+                                ev1, skip);
   }
   return hipErrorInvalidValue;
 }
@@ -248,7 +416,12 @@ hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, c
 hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n, const double* v,
                         double* w, double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
                         hipEvent_t ev1) {
-  const int vb = fast_vb(A, dtype, lda, m);
+  int vb = fast_vb(A, dtype, lda, m);
+  // the pass with column sums accumulates in FP64
+  if (vb && !(dtype == kF64   ? fits_fast<double, double>(vb, m)
+              : dtype == kF32 ? fits_fast<float, double>(vb, m)
+                              : fits_fast<uint16_t, double>(vb, m)))
+    vb = 0;
   if (!vb) {
     hipError_t e = gemv_t(A, dtype, lda, m, n, nullptr, v, w, true, st, ev0, ev1);
     if (e != hipSuccess) return e;

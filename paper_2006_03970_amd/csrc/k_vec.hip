@@ -202,15 +202,19 @@ int gather_chunks(int64_t r_bound) {
   return (int)(c < 1024 ? c : 1024);
 }
 
-// Block b sums columns [b*ck, (b+1)*ck) of A_J weighted by c, for every row;
-// a thread keeps the loads of 16 columns in flight.
+// Block (b, p) sums columns [b*ck, (b+1)*ck) of A_J weighted by c, for the
+// rows [p*NQ*kNT, (p+1)*NQ*kNT); a thread keeps the loads of 16 columns in
+// flight.  skip (nullable): the block returns at once while *skip != 0.
 template <typename T, int NQ>
 __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A, int64_t lda, int m,
                                                          const int32_t* __restrict__ J,
                                                          const double* __restrict__ c,
                                                          const double* __restrict__ r_dev,
-                                                         int64_t r_host, double* __restrict__ part) {
+                                                         int64_t r_host, double* __restrict__ part,
+                                                         const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
+  const int rbase = (int)blockIdx.y * (NQ * kNT);
   int nc;
   int64_t ck;
   chunk_plan(r, nc, ck);
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int row = threadIdx.x + q * kNT;
+      const int row = rbase + threadIdx.x + q * kNT;
       if (row < m) {
         double v[16];
 #pragma unroll
@@ -246,42 +250,55 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
   }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int row = threadIdx.x + q * kNT;
+    const int row = rbase + threadIdx.x + q * kNT;
     if (row < m) part[(int64_t)blockIdx.x * m + row] = acc[q];
   }
 }
 
+// Rows past 16 * kNT go to further row panels (grid.y).
 template <typename T>
 static hipError_t launch_gather(const T* A, int64_t lda, int m, const int32_t* J, const double* c,
-                                const double* r_dev, int64_t r_bound, double* part, hipStream_t st) {
+                                const double* r_dev, int64_t r_bound, double* part, hipStream_t st,
+                                const double* skip) {
   const int nb = gather_chunks(r_bound);
   if (nb == 0) return hipSuccess;
   const int nq = (m + kNT - 1) / kNT;
 #define SSNAL_GATHER_CASE(Q)                                                                   \
   if (nq <= Q) {                                                                               \
     hipLaunchKernelGGL((k_gather_partial<T, Q>), dim3(nb), dim3(kNT), 0, st, A, lda, m, J, c,     \
-                       r_dev, r_bound, part);                                                  \
+                       r_dev, r_bound, part, skip);                                            \
     return hipGetLastError();                                                                  \
   }
   SSNAL_GATHER_CASE(1)
   SSNAL_GATHER_CASE(2)
   SSNAL_GATHER_CASE(4)
   SSNAL_GATHER_CASE(8)
-  SSNAL_GATHER_CASE(16)
 #undef SSNAL_GATHER_CASE
-  return hipErrorInvalidValue;
+  const unsigned np = (unsigned)((m + 16 * kNT - 1) / (16 * kNT));
+  hipLaunchKernelGGL((k_gather_partial<T, 16>), dim3(nb, np), dim3(kNT), 0, st, A, lda, m, J, c,
+                     r_dev, r_bound, part, skip);
+  return hipGetLastError();
 }
 
 hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, const int32_t* J,
                                const double* c, const double* r_dev, int64_t r_bound, double* part,
-                               hipStream_t st) {
+                               hipStream_t st, const double* skip) {
   switch (dtype) {
-    case kF64: return launch_gather<double>((const double*)A, lda, m, J, c, r_dev, r_bound, part, st);
-    case kF32: return launch_gather<float>((const float*)A, lda, m, J, c, r_dev, r_bound, part, st);
+    case kF64:
+      return launch_gather<double>((const double*)A, lda, m, J, c, r_dev, r_bound, part, st, skip);
+    case kF32:
+      return launch_gather<float>((const float*)A, lda, m, J, c, r_dev, r_bound, part, st, skip);
     case kBF16:
-      return launch_gather<uint16_t>((const uint16_t*)A, lda, m, J, c, r_dev, r_bound, part, st);
+      return launch_gather<uint16_t>((const uint16_t*)A, lda, m, J, c, r_dev, r_bound, part, st, skip);
   }
   return hipErrorInvalidValue;
+}
+
+int gather_nchunks(int64_t r) {
+  int nc;
+  int64_t ck;
+  chunk_plan(r, nc, ck);
+  return nc;
 }
 
 __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict__ part,
@@ -291,7 +308,7 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
                                                         const double* __restrict__ b,
                                                         double* __restrict__ g,
                                                         double* __restrict__ out2,
-                                                        double* __restrict__ scal) {
+                                                        double* __restrict__ blk) {
   const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
   int nchunks;
   int64_t ck;
@@ -331,9 +348,9 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
   const double s2 = block_sum<kNT>(v2, red);
   const double s3 = block_sum<kNT>(v3, red);
   if (threadIdx.x == 0) {
-    scal[SC_BLK + 3 * blockIdx.x + 0] = s1;
-    scal[SC_BLK + 3 * blockIdx.x + 1] = s2;
-    scal[SC_BLK + 3 * blockIdx.x + 2] = s3;
+    blk[3 * blockIdx.x + 0] = s1;
+    blk[3 * blockIdx.x + 1] = s2;
+    blk[3 * blockIdx.x + 2] = s3;
   }
 }
 
@@ -387,18 +404,23 @@ __global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __rest
 
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         hipStream_t st, Pub pub) {
+                         hipStream_t st, Pub pub, double* blk) {
   if (mode == 0 && r_dev && m <= kFin1Max) {
     hipLaunchKernelGGL(k_gather_finish1, dim3(1), dim3(kFin1NT), 0, st, part, r_dev, m, y, b, g, out2,
                        scal, pub);
     return hipGetLastError();
   }
   const int nb = (m + kNT - 1) / kNT;
+  // the block partials of mode 0 fit the scalar block up to kScalBlocks blocks
+  if (mode == 0 && !blk) {
+    if (nb > kScalBlocks) return hipErrorInvalidValue;
+    blk = scal + SC_BLK;
+  }
   hipLaunchKernelGGL(k_gather_finish, dim3(nb), dim3(kNT), 0, st, part, r_dev, r_host, m, mode, y, b,
-                     g, out2, scal);
+                     g, out2, blk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode != 0) return e;
-  hipLaunchKernelGGL((k_final<3>), dim3(1), dim3(kNT), 0, st, scal + SC_BLK, nb, scal + SC_GG,
+  hipLaunchKernelGGL((k_final<3>), dim3(1), dim3(kNT), 0, st, blk, nb, scal + SC_GG,
                      (const double*)nullptr, 0, (double*)nullptr, (const double*)scal, pub);
   return hipGetLastError();
 }

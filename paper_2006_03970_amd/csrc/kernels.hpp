@@ -24,9 +24,13 @@ inline int dtype_size(int dt) { return dt == kF64 ? 8 : (dt == kF32 ? 4 : 2); }
 // acc64: accumulate in FP64 (always for F64 storage); else FP32.
 // ev0/ev1 (nullable): timing events, stamped by the kernel dispatch itself
 // (hipExtLaunchKernel) so that their interval is the kernel's duration.
+// Columns longer than one register-resident slice of v (4096 FP32, 2048 FP64,
+// 8192 BF16 rows) and gathered columns go through row panels.  skip
+// (nullable, honoured by the gathered and long-column forms): nothing is done
+// while *skip != 0.
 hipError_t gemv_t(const void* A, int dtype, int64_t lda, int m, int64_t ncols, const int32_t* J,
                   const double* v, double* w, bool acc64, hipStream_t st,
-                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const double* skip = nullptr);
 // Same pass also accumulating sum_j ||a_j||^2 into colsq (FP64, one value).
 hipError_t gemv_t_colsq(const void* A, int dtype, int64_t lda, int m, int64_t n,
                         const double* v, double* w, double* colsq_part, int* nparts,
@@ -53,18 +57,41 @@ hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t*
 // A_J c as per-chunk partial m-vectors: part[chunk*m + i].  r is read from
 // r_dev when non-null (the grid is sized for r_bound >= r), else r = r_bound.
 // gather_chunks(r_bound) bounds the chunk count of every r <= r_bound; the
-// partial buffer holds that many m-vectors.
+// partial buffer holds that many m-vectors.  gather_nchunks(r) is the chunk
+// count of exactly r columns.  skip (nullable): nothing is done while *skip != 0.
 int gather_chunks(int64_t r_bound);
+int gather_nchunks(int64_t r);
 hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, const int32_t* J,
                                const double* c, const double* r_dev, int64_t r_bound, double* part,
-                               hipStream_t st);
+                               hipStream_t st, const double* skip = nullptr);
 // Finishers over the partial sums S = sum_chunks part:
 //  mode 0 (gradient): g = y + b - S, out2 = rho = S - b; |g|^2, |rho|^2, b^T rho into scal
 //  mode 1 (Woodbury): out2 = d = -g + S
 //  mode 2 (residual): out2 = y = S - b
+// blk (mode 0, nullable): 3 * ceil(m/256) doubles for the block partials; null
+// uses the scalar block, which holds them for m <= 4096 only.
 hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host, int m, int mode,
                          const double* y, const double* b, double* g, double* out2, double* scal,
-                         hipStream_t st, Pub pub = Pub{});
+                         hipStream_t st, Pub pub = Pub{}, double* blk = nullptr);
+
+// ---- conjugate gradients on V d = -g, V = I + kappa A_J A_J^T  (k_cg.hip) --
+// State on the device: d, res (residual -g - V d), p (search direction), q
+// (V p), s (A_J^T p, r entries); scalars in scal: SC_CG_RR (two slots,
+// alternating by iteration parity), SC_CG_STOP, SC_CG_DONE, SC_CG_IT.
+// cg_init: d = 0, res = p = -g, rr = |g|^2, stop = eps2 * rr,
+// done = (rr <= stop), it = 0.
+// blk: 2 * cg_blocks(m) doubles (block partials).
+hipError_t cg_init(const double* g, double* d, double* res, double* p, int m, double eps2,
+                   double* blk, double* scal, hipStream_t st);
+// One iteration (a no-op once done is set): s = A_J^T p, q = p + kappa A_J s,
+// alpha = rr/(p^T q), d += alpha p, res -= alpha q, beta = rr_new/rr,
+// p = res + beta p; done once rr_new <= stop.  par = iteration parity.
+// gpart: gather_chunks(r) m-vectors; blk: 2 * cg_blocks(m) doubles.
+int cg_blocks(int m);
+hipError_t cg_iteration(const void* A, int dtype, int64_t lda, int m, const int32_t* J, int64_t r,
+                        double kappa, bool acc64, double* d, double* res, double* p, double* q,
+                        double* s, double* gpart, double* blk, int par, double* scal,
+                        hipStream_t st);
 
 // Line search: for the K trial steps s_k, Delta_k = psi(y + s_k d) - psi(y);
 // a one-block follow-up kernel picks the first k with Delta_k <= mu s_k g^T d,

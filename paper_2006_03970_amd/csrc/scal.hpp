@@ -32,9 +32,15 @@ enum Scal : int {
   SC_CV_MT = 24,     // k-fold: training rows of the current fold
   SC_CV_MV = 25,     // validation rows of the current fold
   SC_CV_BAD = 26,    // fold labels outside [0, k)
+  SC_CG_RR = 27,     // conjugate gradients: |res|^2, two slots by iteration parity
+  SC_CG_STOP = 29,   // eps^2 |g|^2
+  SC_CG_DONE = 30,   // 1 once |res|^2 <= stop
+  SC_CG_IT = 31,     // iterations taken
   SC_DELTA = 32,   // 33 slots: line-search increments Delta_k (+ second-order sum)
   SC_BLK = 80,     // per-block partials of the m-vector finishers (<= 16 blocks x 3)
   SC_SIZE = 160
 };
+// Block partials (3 each) the scalar block holds from SC_BLK on: m <= 16 * 256.
+constexpr int kScalBlocks = 16;
 
 }  // namespace ssnal

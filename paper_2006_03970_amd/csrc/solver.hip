@@ -105,18 +105,28 @@ struct Workspace {
 struct WsPlan {
   size_t bytes[10];
 };
+// Largest dense Newton system (m x m, or r x r in the Woodbury form) that is
+// factored; beyond it on both sides the direction comes from conjugate
+// gradients.
+constexpr int64_t kDenseMax = 4096;
+// Largest m a solve accepts (the m-vectors and the gathered partial sums grow
+// with m; the finishers that sweep them are single-block).
+constexpr int64_t kMaxRows = 1 << 20;
+
 WsPlan plan_ws(int64_t m, int64_t n) {
   const int nb = prox_blocks(n);
-  const int64_t T = (m + 63) / 64;
+  const int64_t md = std::min<int64_t>(m, kDenseMax);  // dense systems stay within kDenseMax
+  const int64_t T = (md + 63) / 64;
+  const size_t m_part = std::max<size_t>(3 * (size_t)((m + 255) / 256), 2 * (size_t)cg_blocks((int)m));
   WsPlan p;
   p.bytes[0] = (size_t)n * 8;  // wy
   p.bytes[1] = (size_t)n * 8;  // wd
   p.bytes[2] = (size_t)n * 8;  // uJ
   p.bytes[3] = (size_t)n * 4;  // J
   p.bytes[4] = (size_t)nb * 4;  // counts
-  p.bytes[5] = (std::max(ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb) + 64) * 8;  // part
+  p.bytes[5] = (std::max({ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb, m_part}) + 64) * 8;  // part
   p.bytes[6] = (size_t)(gather_chunks(n) + 1) * m * 8;  // gpart
-  p.bytes[7] = (size_t)m * m * 8;  // V
+  p.bytes[7] = (size_t)md * md * 8;  // V
   p.bytes[8] = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);  // syrk split-K
   p.bytes[9] = (size_t)MV_COUNT * m * 8;  // m-vectors
   for (size_t& b : p.bytes) b = b < 256 ? 256 : b;
@@ -223,7 +233,7 @@ int check_args(const void* A, int dt, int64_t lda, const double* b, int64_t m, i
   if (!A || !b) return fail(SSNAL_EINVAL, "A and b must be non-null device pointers");
   if (dt < 0 || dt > 2) return fail(SSNAL_EINVAL, "a_dtype %d is not SSNAL_F64/F32/BF16", dt);
   if (m < 1 || n < 1) return fail(SSNAL_EINVAL, "m=%lld and n=%lld must be >= 1", (long long)m, (long long)n);
-  if (m > 4096) return fail(SSNAL_EINVAL, "m=%lld exceeds 4096 (dense m x m Newton system)", (long long)m);
+  if (m > kMaxRows) return fail(SSNAL_EINVAL, "m=%lld exceeds %lld", (long long)m, (long long)kMaxRows);
   if (n > 2147483647LL) return fail(SSNAL_EINVAL, "n=%lld exceeds 2^31-1", (long long)n);
   if (lda < m) return fail(SSNAL_EINVAL, "lda=%lld < m=%lld", (long long)lda, (long long)m);
   return 0;
@@ -307,6 +317,38 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   return 0;
 }
 
+// d ~ -(I + kappa A_J A_J^T)^{-1} g by conjugate gradients (Sec. 3.2, the
+// approximate solve for large m and r), to ||V d + g|| <= eps ||g|| or maxit
+// iterations.  The iterations are queued in growing chunks between
+// read-backs of the done flag (kernels of an iteration after the flag is set
+// return at once).  Iterations taken go to *iters.
+int newton_cg(ssnal_ctx* c, const void* A, int dt, int64_t lda, int m, const int32_t* J, int64_t r,
+              double kappa, const double* g, double* d, double eps, int maxit, const Workspace& w,
+              hipStream_t st, int* syncs, int* iters) {
+  *iters = 0;
+  if (r == 0) {
+    HIPCHK(vec_scale_copy(g, -1.0, d, m, st));
+    return 0;
+  }
+  double* res = w.t1;
+  double* p = w.t2;
+  double* q = w.t3;
+  double* s = w.wd;  // r entries; the A^T d pass rewrites it after the direction
+  HIPCHK(cg_init(g, d, res, p, m, eps * eps, w.part, w.scal, st));
+  int launched = 0, chunk = 4;
+  for (;;) {
+    const int k = std::min(chunk, maxit - launched);
+    for (int i = 0; i < k; ++i, ++launched)
+      HIPCHK(cg_iteration(A, dt, lda, m, J, r, kappa, true, d, res, p, q, s, w.gpart, w.part,
+                          launched & 1, w.scal, st));
+    if (int rc = readback(c, w, st, syncs)) return rc;
+    if (c->h_scal[SC_CG_DONE] != 0.0 || launched >= maxit) break;
+    chunk = std::min(2 * chunk, 32);
+  }
+  *iters = (int)c->h_scal[SC_CG_IT];
+  return 0;
+}
+
 #pragma clang fp contract(off)
 ProxArgs prox_args(double sigma, double l1, double l2) {
   ProxArgs pa;
@@ -325,7 +367,8 @@ int prox_grad(const void* A, int dt, int64_t lda, const double* b, int m, int64_
   HIPCHK(prox_count(x, w.wy, w.wd, pending ? w.scal + SC_S : nullptr, n, pa, w.counts, st));
   HIPCHK(prox_write(x, w.wy, n, pa, w.counts, w.J, w.uJ, w.scal + SC_R, st));
   HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
-  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal, st, pub));
+  HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 0, w.y, b, w.g, w.rho, w.scal, st, pub,
+                       m > kDenseMax ? w.part : nullptr));
   return 0;
 }
 
@@ -380,6 +423,10 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     if (user_opts->max_backtrack > 0) o.max_backtrack = user_opts->max_backtrack;
     o.no_refine = user_opts->no_refine;
     o.no_smw = user_opts->no_smw;
+    o.newton_cg = user_opts->newton_cg;
+    if (user_opts->cg_maxit > 0) o.cg_maxit = user_opts->cg_maxit;
+    if (user_opts->cg_eta > 0) o.cg_eta = user_opts->cg_eta;
+    if (user_opts->cg_tau > 0) o.cg_tau = user_opts->cg_tau;
     o.timing = user_opts->timing;
     o.trace = user_opts->trace;
     o.trace_cap = user_opts->trace_cap;
@@ -439,7 +486,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   // iteration that met kkt1 and kkt3 but not eta (decreasing inner
   // tolerances, as in the inner stopping criteria the method refers to).
   double eps_in = tol;
-  int status = SSNAL_NOT_CONVERGED, newton = 0, outer_done = 0, rows = 0;
+  int status = SSNAL_NOT_CONVERGED, newton = 0, outer_done = 0, rows = 0, cg_iters = 0;
   int64_t r = 0;
   bool stalled = false, pending = false, converged = false;
   int pending_row = -1;
@@ -499,8 +546,20 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       }
       if (inner >= o.max_inner) break;
       refreshed = false;
-      // Newton direction
-      int rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, o.no_smw ? 0 : -1, w, st);
+      // Newton direction: a dense factorisation (m x m, or r x r in the
+      // Woodbury form when r < m) while one fits kDenseMax, else conjugate
+      // gradients (always with opts.newton_cg)
+      const bool dense_m = m <= kDenseMax;
+      const bool dense_r = !o.no_smw && r < m && r <= kDenseMax;
+      int rc;
+      if (r > 0 && (o.newton_cg || !(dense_m || dense_r))) {
+        const double eps = std::min(o.cg_eta, std::pow(kkt1, o.cg_tau));
+        int it = 0;
+        rc = newton_cg(c, A, dt, lda, m, w.J, r, kappa, w.g, w.d, eps, o.cg_maxit, w, st, &syncs, &it);
+        cg_iters += it;
+      } else {
+        rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, dense_r ? 1 : 0, w, st);
+      }
       if (rc) return rc;
       // w_d = A^T d, the HBM pass
       if ((rc = tm.next(1))) return rc;
@@ -567,6 +626,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     info->sigma_final = sigma;
     info->gemv_calls = gemv_calls;
     info->syncs = syncs;
+    info->cg_iters = cg_iters;
     double gms = 0.0, dms = 0.0;
     int dn = 0;
     if (int rc = tm.total_ms(&gms, &dms, &dn)) return rc;
@@ -600,6 +660,9 @@ void ssnal_en_opts_init(ssnal_en_opts* o) {
   o->max_outer = 100;
   o->max_inner = 50;
   o->max_backtrack = 30;
+  o->cg_maxit = 500;
+  o->cg_eta = 0.1;
+  o->cg_tau = 0.5;
 }
 
 const char* ssnal_last_error(void) { return g_err; }
@@ -1110,7 +1173,8 @@ int ssnal_newton_matrix(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int6
   if (!ctx || !out || (r > 0 && !J)) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(A, (int)a_dtype, lda, out, m, 1)) return rc;
   if (form != 0 && form != 1) return fail(SSNAL_EINVAL, "form must be 0 or 1");
-  if (form == 1 && (r < 1 || r > 4096)) return fail(SSNAL_EINVAL, "form 1 needs 1 <= r <= 4096");
+  if (form == 0 && m > kDenseMax) return fail(SSNAL_EINVAL, "form 0 needs m <= 4096");
+  if (form == 1 && (r < 1 || r > kDenseMax)) return fail(SSNAL_EINVAL, "form 1 needs 1 <= r <= 4096");
   if (!(kappa > 0)) return fail(SSNAL_EINVAL, "kappa must be > 0");
   HIPCHK(hipSetDevice(ctx->device));
   Workspace ws;
@@ -1149,6 +1213,9 @@ int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, i
   if (int rc = check_args(A, (int)a_dtype, lda, g, m, 1)) return rc;
   if (!(kappa > 0)) return fail(SSNAL_EINVAL, "kappa must be > 0");
   if (form == 1 && r >= m) return fail(SSNAL_EINVAL, "form 1 needs r < m");
+  if (form < 0) form = r < m ? 1 : 0;
+  if (r > 0 && form == 0 && m > kDenseMax) return fail(SSNAL_EINVAL, "the m x m system needs m <= 4096");
+  if (r > 0 && form == 1 && r > kDenseMax) return fail(SSNAL_EINVAL, "the r x r system needs r <= 4096");
   HIPCHK(hipSetDevice(ctx->device));
   Workspace ws;
   if (int rc = prepare(ctx, m, r > 0 ? r : 1, ws)) return rc;
@@ -1159,6 +1226,28 @@ int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, i
   int hinfo = 0;
   std::memcpy(&hinfo, &ctx->h_scal[SC_CHOL], sizeof(int));
   if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
+  return 0;
+}
+
+int ssnal_newton_cg(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, int64_t m,
+                    const int32_t* J, int64_t r, double kappa, const double* g, double eps,
+                    int32_t maxit, hipStream_t stream, double* d, int32_t* iters) {
+  g_err[0] = 0;
+  if (!ctx || !g || !d || (r > 0 && !J)) return fail(SSNAL_EINVAL, "null argument");
+  if (int rc = check_args(A, (int)a_dtype, lda, g, m, 1)) return rc;
+  if (!(kappa > 0)) return fail(SSNAL_EINVAL, "kappa must be > 0");
+  if (!(eps >= 0.0)) return fail(SSNAL_EINVAL, "eps must be >= 0");
+  if (maxit < 0) return fail(SSNAL_EINVAL, "maxit must be >= 0");
+  if (r < 0) return fail(SSNAL_EINVAL, "r must be >= 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  Workspace ws;
+  if (int rc = prepare(ctx, m, r > 0 ? r : 1, ws)) return rc;
+  int it = 0;
+  if (int rc = newton_cg(ctx, A, (int)a_dtype, lda, (int)m, J, r, kappa, g, d, eps, maxit, ws, stream,
+                         nullptr, &it))
+    return rc;
+  HIPCHK(hipStreamSynchronize(stream));
+  if (iters) *iters = it;
   return 0;
 }
 
@@ -1293,7 +1382,8 @@ int ssnal_kkt(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, c
   HIPCHK(gather_gemv_partial(A, dt, lda, (int)m, ws.J, ws.uJ, ws.scal + SC_R, n, ws.gpart, stream));
   // mode 0 with y = 0 gives rho = A x - b and its norms
   HIPCHK(vec_fill(ws.y, 0.0, m, stream));
-  HIPCHK(gather_finish(ws.gpart, ws.scal + SC_R, 0, (int)m, 0, ws.y, b, ws.g, ws.rho, ws.scal, stream));
+  HIPCHK(gather_finish(ws.gpart, ws.scal + SC_R, 0, (int)m, 0, ws.y, b, ws.g, ws.rho, ws.scal, stream,
+                       Pub{}, m > kDenseMax ? ws.part : nullptr));
   Timer tm{ctx, stream, false};
   int calls = 0;
   if (int rc = certify(A, dt, lda, (int)m, n, x, lambda1, lambda2, ws, stream, tm, &calls)) return rc;
