@@ -175,6 +175,58 @@ def path_bench(reps=2):
     return out
 
 
+def cg_bench(reps=2, r_fixed=16000):
+    """Newton-CG on long columns: Gaussian design m=20000, n=200000 (FP32
+    storage, 16 GB, drawn on the device), alpha=0.5, lambda = 0.005 lambda_max,
+    tol 1e-6, where the active set and m both exceed 4096 for most Newton
+    steps, so the directions come from conjugate gradients.  Reports the solve,
+    then the CG iteration rate at a fixed r = 16000 (random columns): two
+    gathered passes over A_J (2 m r 4 bytes) per iteration against HBM peak."""
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+
+    m, n = 20000, 200000
+    cfg = dict(m=m, n=n, design="gauss", k=50, snr=5.0, alpha=0.5, c_lam=0.005)
+    dev = torch.device("cuda:0")
+    p = datagen.make_problem_device(cfg, seed=1, store="f32", device=dev)
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    x, info = binding.ssnal_en_solve(ctx, p["AT"], p["b"], p["lam1"], p["lam2"], tol=1e-6, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        x, info = binding.ssnal_en_solve(ctx, p["AT"], p["b"], p["lam1"], p["lam2"], tol=1e-6,
+                                         x_out=x, stream=stream)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    g = torch.randn(m, generator=torch.Generator(device=dev).manual_seed(5), device=dev,
+                    dtype=torch.float64)
+    perm = torch.randperm(n, generator=torch.Generator(device=dev).manual_seed(6), device=dev)
+    J = torch.sort(perm[:r_fixed])[0].to(torch.int32)
+    best = float("inf")
+    iters = 0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, iters = binding.ssnal_newton_cg(ctx, p["AT"], J, 5e-4, g, 0.0, maxit=40, stream=stream)
+        best = min(best, (time.perf_counter() - t) / max(iters, 1))
+    gbs = 2.0 * m * r_fixed * 4 / best / 1e9
+    out = {"workload": "Gaussian elastic net, m=20000, n=200000, k=50, snr=5, alpha=0.5, "
+                       "c_lambda=0.005, FP32 storage, tol 1e-6 (Newton-CG directions)",
+           "status": info["status"], "ms_per_solve": el * 1e3, "newton_iters": info["newton_iters"],
+           "cg_iters": info["cg_iters"], "nnz": info["nnz"], "eta": info["kkt_rel"],
+           "cg_iteration": {"r": r_fixed, "iterations": iters, "us_per_iter": best * 1e6,
+                            "alg_bytes_per_iter": 2 * m * r_fixed * 4, "alg_gbs": gbs,
+                            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}}
+    print(f"[bench] newton-cg: {out['ms_per_solve']:.0f} ms/solve, {info['cg_iters']} CG iterations; "
+          f"{best * 1e6:.0f} us per CG iteration at r={r_fixed} ({gbs:.0f} GB/s)", file=sys.stderr, flush=True)
+    del p, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(nreq, nmax, slots, seed=7):
     """p50/p99 latency and solves/s of the serving loop over a request stream."""
     import numpy as np
@@ -262,6 +314,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the m=1000, n=1e6 single-solve section")
     ap.add_argument("--no-path", action="store_true", help="skip the path + model selection section")
+    ap.add_argument("--no-cg", action="store_true", help="skip the Newton-CG (m=20000) section")
+    ap.add_argument("--cg-only", action="store_true", help="run only the Newton-CG section")
     ap.add_argument("--serving", type=int, default=64, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-nmax", type=float, default=5e5)
     ap.add_argument("--serving-slots", type=int, default=4)
@@ -283,6 +337,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.cg_only:
+        print(json.dumps({"newton_cg": cg_bench()}), flush=True)
+        return
     cfg = datagen.CONFIGS["c2"]
     t0 = time.time()
     p64 = datagen.make_problem("c2", seed=args.seed, store="f64")
@@ -402,6 +459,8 @@ def main():
         out["large_single_solve"] = large_bench()
     if not args.no_path:
         out["path"] = path_bench()
+    if not args.no_cg:
+        out["newton_cg"] = cg_bench()
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
 

@@ -66,35 +66,31 @@ __global__ __launch_bounds__(kCgNT) void k_cg_start(const double* __restrict__ b
 }
 
 // q = p + kappa sum_c part[c*m + i] (the nc chunk sums of A_J s, in chunk
-// order); block partials of p^T q.
+// order), one row per thread; block partials of p^T q.
 __global__ __launch_bounds__(kCgNT) void k_cg_q(const double* __restrict__ part, int nc, int m,
                                                 double kappa, const double* __restrict__ p,
                                                 double* __restrict__ q, double* __restrict__ blk,
                                                 const double* __restrict__ scal) {
   if (cg_done(scal)) return;
   __shared__ double red[kCgNT / kWave];
-  const int base = blockIdx.x * kCgRows + threadIdx.x;
+  const int i = blockIdx.x * kCgNT + threadIdx.x;
+  const int ic = i < m ? i : m - 1;
+  double S = 0.0;
+  int c = 0;
+  for (; c + 8 <= nc; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + ic];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) S += v[u];
+  }
+  for (; c < nc; ++c) S += part[(int64_t)c * m + ic];
   double t = 0.0;
-#pragma unroll
-  for (int k = 0; k < kCgEPT; ++k) {
-    const int i = base + k * kCgNT;
-    const int ic = i < m ? i : m - 1;
-    double S = 0.0;
-    int c = 0;
-    for (; c + 8 <= nc; c += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + ic];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) S += v[u];
-    }
-    for (; c < nc; ++c) S += part[(int64_t)c * m + ic];
-    if (i < m) {
-      const double pi = p[i];
-      const double qi = pi + kappa * S;
-      q[i] = qi;
-      t += pi * qi;
-    }
+  if (i < m) {
+    const double pi = p[i];
+    const double qi = pi + kappa * S;
+    q[i] = qi;
+    t = pi * qi;
   }
   t = block_sum<kCgNT>(t, red);
   if (threadIdx.x == 0) blk[blockIdx.x] = t;
@@ -171,13 +167,14 @@ hipError_t cg_iteration(const void* A, int dtype, int64_t lda, int m, const int3
   e = gather_gemv_partial(A, dtype, lda, m, J, s, nullptr, r, gpart, st, done);
   if (e != hipSuccess) return e;
   const int nb = cg_blocks(m);
-  const int nc = gather_nchunks(r);
-  hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(kCgNT), 0, st, gpart, nc, m, kappa, p, q, blk, scal);
+  const int nbq = (m + kCgNT - 1) / kCgNT;
+  const int nc = gather_nchunks(r, m);
+  hipLaunchKernelGGL(k_cg_q, dim3(nbq), dim3(kCgNT), 0, st, gpart, nc, m, kappa, p, q, blk, scal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kCgNT), 0, st, blk, nb, m, p, q, d, res, blk + nb,
+  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kCgNT), 0, st, blk, nbq, m, p, q, d, res, blk + nbq,
                      scal, par);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(kCgNT), 0, st, blk + nb, nb, m, res, p, scal, par);
+  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(kCgNT), 0, st, blk + nbq, nb, m, res, p, scal, par);
   return hipGetLastError();
 }
 

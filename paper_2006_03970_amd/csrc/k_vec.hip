@@ -182,20 +182,28 @@ hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t*
 // adds the partials in chunk order, so the sum is reproducible.  r may live
 // on the device (it comes from the compaction pass): the grid is sized for
 // the largest possible r and blocks past the last chunk return at once.
-__host__ __device__ __forceinline__ void chunk_plan(int64_t r, int& nc, int64_t& ck) {
+__host__ __device__ __forceinline__ void chunk_plan(int64_t r, int m, int& nc, int64_t& ck) {
   if (r <= 0) {
     nc = 0;
     ck = 0;
     return;
   }
-  int64_t c = (r + 1023) / 1024;
+  // at most 1024 chunks; columns longer than 4096 rows already multiply the
+  // blocks by their row panels and take fewer (>= 64), which keeps the
+  // partial sums (nc m-vectors) small next to A_J
+  int64_t maxc = 1024;
+  if (m > 4096) {
+    maxc = (int64_t)1024 * 4096 / m;
+    if (maxc < 64) maxc = 64;
+  }
+  int64_t c = (r + maxc - 1) / maxc;
   c = (c + 15) / 16 * 16;  // whole groups of 16 columns
   nc = (int)((r + c - 1) / c);
   ck = c;
 }
 
-// Upper bound of the chunk count for any r <= r_bound: nc(r) = ceil(r/16)
-// while r <= 16384 and nc(r) <= 1024 beyond (nc itself is not monotone in r).
+// Upper bound of the chunk count for any r <= r_bound and any m: nc(r, m) <=
+// ceil(r/16) and <= 1024 (nc itself is not monotone in r).
 int gather_chunks(int64_t r_bound) {
   if (r_bound <= 0) return 0;
   const int64_t c = (r_bound + 15) / 16;
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
   const int rbase = (int)blockIdx.y * (NQ * kNT);
   int nc;
   int64_t ck;
-  chunk_plan(r, nc, ck);
+  chunk_plan(r, m, nc, ck);
   if ((int)blockIdx.x >= nc) return;
   const int64_t k0 = (int64_t)blockIdx.x * ck;
   const int64_t k1 = k0 + ck < r ? k0 + ck : r;
@@ -294,10 +302,10 @@ hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, con
   return hipErrorInvalidValue;
 }
 
-int gather_nchunks(int64_t r) {
+int gather_nchunks(int64_t r, int m) {
   int nc;
   int64_t ck;
-  chunk_plan(r, nc, ck);
+  chunk_plan(r, m, nc, ck);
   return nc;
 }
 
@@ -312,7 +320,7 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
   const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
   int nchunks;
   int64_t ck;
-  chunk_plan(r, nchunks, ck);
+  chunk_plan(r, m, nchunks, ck);
   const int row = blockIdx.x * kNT + threadIdx.x;
   double S = 0.0;
   if (row < m) {
@@ -368,7 +376,7 @@ __global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __rest
                                                             double* __restrict__ scal, Pub pub) {
   int nchunks;
   int64_t ck;
-  chunk_plan((int64_t)(*r_dev), nchunks, ck);
+  chunk_plan((int64_t)(*r_dev), m, nchunks, ck);
   double v1 = 0.0, v2 = 0.0, v3 = 0.0;
   for (int row = threadIdx.x; row < m; row += kFin1NT) {
     double S = 0.0;
