@@ -4,6 +4,7 @@
 // for bandwidth: 256 threads, 8 elements per thread, one block per 2048
 // features, and "last block finishes" reductions instead of extra launches.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -263,6 +264,68 @@ __global__ __launch_bounds__(kNT) void k_gather_partial(const T* __restrict__ A,
   }
 }
 
+// The same sums with 16-byte loads (VN consecutive rows per load) for FP32
+// and FP64 designs whose columns start 16-byte aligned; each row adds the chunk's
+// columns in the same order as above, so the sums are the same.  Loads of
+// FP32/BF16 values go to FP32 registers (exact) and widen to FP64 at use.
+template <typename T, int NQ>
+__global__ __launch_bounds__(kNT) void k_gather_partial_v(const T* __restrict__ A, int64_t lda, int m,
+                                                           const int32_t* __restrict__ J,
+                                                           const double* __restrict__ c,
+                                                           const double* __restrict__ r_dev,
+                                                           int64_t r_host, double* __restrict__ part,
+                                                           const double* __restrict__ skip) {
+  using LT = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+  constexpr int VN = 16 / (int)sizeof(T);
+  if (skip && *skip != 0.0) return;
+  const int64_t r = r_dev ? (int64_t)(*r_dev) : r_host;
+  int nc;
+  int64_t ck;
+  chunk_plan(r, m, nc, ck);
+  if ((int)blockIdx.x >= nc) return;
+  const int64_t k0 = (int64_t)blockIdx.x * ck;
+  const int64_t k1 = k0 + ck < r ? k0 + ck : r;
+  double acc[NQ][VN];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[q][e] = 0.0;
+  for (int64_t kb = k0; kb < k1; kb += 16) {
+    int64_t col[16];
+    double cv[16];
+    bool ok[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t k = kb + u;
+      ok[u] = k < k1;
+      const int64_t kc = ok[u] ? k : k1 - 1;  // past the chunk: a valid column, weight 0
+      col[u] = (int64_t)J[kc] * lda;
+      cv[u] = c[kc];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      // rows row0 .. row0 + VN - 1 < lda: lda is a multiple of VN
+      const int row0 = (q * kNT + (int)threadIdx.x) * VN;
+      if (row0 < m) {
+        LT v[16][VN];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) loadv<16>(A + col[u] + row0, v[u]);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[q][e] += ok[u] ? (double)v[u][e] * cv[u] : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int row0 = (q * kNT + (int)threadIdx.x) * VN;
+#pragma unroll
+    for (int e = 0; e < VN; ++e)
+      if (row0 + e < m) part[(int64_t)blockIdx.x * m + row0 + e] = acc[q][e];
+  }
+}
+
 // Rows past 16 * kNT go to further row panels (grid.y).
 template <typename T>
 static hipError_t launch_gather(const T* A, int64_t lda, int m, const int32_t* J, const double* c,
@@ -270,6 +333,23 @@ static hipError_t launch_gather(const T* A, int64_t lda, int m, const int32_t* J
                                 const double* skip) {
   const int nb = gather_chunks(r_bound);
   if (nb == 0) return hipSuccess;
+  constexpr int VN = 16 / (int)sizeof(T);
+  const int nv = (m + kNT * VN - 1) / (kNT * VN);  // row groups of kNT * VN
+  // FP32/FP64 columns of one row panel (16 BF16 columns of 8 rows would not
+  // fit the registers; over several row panels the element loads measured
+  // faster)
+  if (sizeof(T) >= 4 && nv <= 4 && ((uintptr_t)A) % 16 == 0 && lda % VN == 0) {
+    if (nv <= 1)
+      hipLaunchKernelGGL((k_gather_partial_v<T, 1>), dim3(nb), dim3(kNT), 0, st, A, lda, m, J, c, r_dev,
+                         r_bound, part, skip);
+    else if (nv <= 2)
+      hipLaunchKernelGGL((k_gather_partial_v<T, 2>), dim3(nb), dim3(kNT), 0, st, A, lda, m, J, c, r_dev,
+                         r_bound, part, skip);
+    else
+      hipLaunchKernelGGL((k_gather_partial_v<T, 4>), dim3(nb), dim3(kNT), 0, st, A, lda, m, J, c, r_dev,
+                         r_bound, part, skip);
+    return hipGetLastError();
+  }
   const int nq = (m + kNT - 1) / kNT;
 #define SSNAL_GATHER_CASE(Q)                                                                   \
   if (nq <= Q) {                                                                               \
