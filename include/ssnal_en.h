@@ -228,7 +228,8 @@ typedef struct {
  * doubles (nullable; beta scattered to J, zero elsewhere); out: HOST.
  * status in out: 0 ok; 1 r >= m (the least-squares fit is not determined:
  * rss, gcv, ebic are NaN, beta_out zero); 2 A_J^T A_J not positive definite
- * (likewise).  Needs lambda2 >= 0 and m <= 4096; with lambda2 = 0 a singular
+ * (likewise).  Needs lambda2 >= 0 and min(r, m) <= 4096 (any m when the support
+ * has at most 4096 features); with lambda2 = 0 a singular
  * Gram matrix returns SSNAL_ENUMERIC.
  */
 typedef struct {

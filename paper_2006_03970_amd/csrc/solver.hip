@@ -1258,7 +1258,6 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
   if (!ctx || !x || !out) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
   if (!(lambda2 >= 0.0) || !std::isfinite(lambda2)) return fail(SSNAL_EINVAL, "lambda2 must be >= 0");
-  if (m > 4096) return fail(SSNAL_EINVAL, "model selection needs m <= 4096 (dense systems)");
   HIPCHK(hipSetDevice(ctx->device));
   Workspace w;
   if (int rc = prepare(ctx, m, n, w)) return rc;
@@ -1276,6 +1275,9 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
   HIPCHK(sum_parts(w.part, 0, w.scal + SC_MS_NONE, b, mi, w.scal + SC_BB, st));
   if (int rc = readback(ctx, w, st, nullptr)) return rc;
   const int64_t r = (int64_t)hs[SC_R];
+  if (std::min<int64_t>(r, m) > kDenseMax)
+    return fail(SSNAL_EINVAL, "model selection needs min(r, m) <= 4096 (r=%lld, m=%lld): its systems are dense",
+                (long long)r, (long long)m);
   out->r = (int32_t)r;
   out->rss_en = hs[SC_MS_RSSEN];
   const double bb = hs[SC_BB];

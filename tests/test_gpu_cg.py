@@ -149,7 +149,7 @@ def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc):
           f"ms {info['solve_ms']:.1f} (factored: newton {infod['newton_iters']} ms {infod['solve_ms']:.1f})")
 
 
-@pytest.mark.parametrize("store", ["f32", "f64"])
+@pytest.mark.parametrize("store", ["f32", "bf16", "f64"])
 def test_solve_long_rows_auto_cg(gpu, ctx, orc, store):
     """m=5000 > 4096 rows, n=40000 Gaussian design, lambda = 0.05 lambda_max:
     the first active sets exceed 4096 columns, so the solve switches to CG by
@@ -177,3 +177,28 @@ def test_solve_long_rows_auto_cg(gpu, ctx, orc, store):
     assert (F - D) / (1 + abs(F)) <= 1e-5
     print(f"[report] m=5000 {store}: nnz {info['nnz']} newton {info['newton_iters']} "
           f"cg {info['cg_iters']} eta {eta:.2e} ms {info['solve_ms']:.1f}")
+
+
+def test_path_long_rows(gpu, ctx, orc):
+    """A warm-started path at m=5000 > 4096 rows (FP32 storage, 6 points
+    c_lambda 1 -> 0.05): x = 0 at lambda_max, every point certified by the
+    oracle's KKT residual on the stored design."""
+    import datagen
+    import torch
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    cfg = dict(m=5000, n=20000, design="gauss", k=30, snr=5.0, alpha=0.7, c_lam=1.0, tol=1e-6)
+    p = datagen.make_problem(cfg, seed=8, store="f32", want_f64=True)
+    _say("path m=5000")
+    A, b = design_to_device(p.AT, "f32"), vec_to_device(p.b)
+    cl = np.geomspace(1.0, 0.05, 6)
+    X, infos, status = gpu.ssnal_en_path(ctx, A, b, 0.7, cl, tol=1e-6)
+    del A
+    torch.cuda.empty_cache()
+    assert status == 0, [i["status"] for i in infos]
+    X = X.cpu().numpy()
+    assert np.all(X[0] == 0.0)
+    lam_max = np.max(np.abs(orc.gemv_t(p.AT64, p.b))) / 0.7  # over the stored design, as the path
+    for k in range(1, len(cl)):
+        lam = cl[k] * lam_max
+        eta = orc.eta(p.AT64, p.b, X[k], 0.7 * lam, 0.3 * lam)
+        assert eta <= 1.5e-6, (k, eta)

@@ -108,3 +108,33 @@ def test_model_select_on_path(gpu, ctx, orc, store):
         gcv.append(res["gcv"] if res["status"] == 0 else np.inf)
         gcv_ref.append(ref["gcv"] if ref["status"] == 0 else np.inf)
     assert int(np.argmin(gcv)) == int(np.argmin(gcv_ref))
+
+
+@pytest.mark.parametrize("m,n,r,store", [(5000, 8000, 120, "f64"), (5000, 8000, 300, "f32")])
+def test_model_select_long_rows(gpu, ctx, orc, m, n, r, store):
+    """m > 4096 rows with a support of r < 4096 columns: the r x r systems."""
+    import datagen
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    _say("model_select long rows", m, n, r, store)
+    AT, AT64 = datagen.make_design("gauss", m, n, 91 + r, store)
+    g = np.random.default_rng(r + 9)
+    x = np.zeros(n)
+    x[g.choice(n, size=r, replace=False)] = g.standard_normal(r)
+    b = g.standard_normal(m)
+    ref = orc.model_select(AT64, b, x, 0.4, want_beta=True)
+    res = gpu.ssnal_en_model_select(ctx, design_to_device(AT, store), vec_to_device(b),
+                                    vec_to_device(x), 0.4, want_beta=True)
+    _check(res, ref, 1e-9 if store == "f64" else 2e-3)
+
+
+def test_model_select_long_rows_wide_support(gpu, ctx):
+    """m > 4096 and a support above 4096 columns: no dense system fits."""
+    import datagen
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    _say("model_select long rows, wide support")
+    AT, _ = datagen.make_design("gauss", 4200, 5000, 3, "f32")
+    x = np.zeros(5000)
+    x[:4100] = 1.0
+    b = np.ones(4200)
+    with pytest.raises(gpu.SsnalError):
+        gpu.ssnal_en_model_select(ctx, design_to_device(AT, "f32"), vec_to_device(b), vec_to_device(x), 0.4)
