@@ -188,13 +188,19 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
  *   err_out  : HOST, k x nlam (row f = fold f): mean over the rows of fold f of
  *              (A x_q - b)^2, x_q the fold's solution at point q.
  *   infos    : HOST, nullable, k x nlam.
- * The training rows of a fold are copied into a context buffer ((m-1) x n
- * elements of A's storage type); m <= 4096; alpha in (0, 1].  Returns the
- * most severe status over the solves (an error stops).
+ *   slots    : folds run concurrently on min(slots, k) workers (1..64), each
+ *              with its own context and stream, created on first use and kept
+ *              by ctx (1: every fold in turn on `stream`).  Each fold's work is
+ *              independent of the others, so the results do not depend on slots.
+ * The training rows of a fold are copied into a buffer of its worker ((m-1) x n
+ * elements of A's storage type, plus the path: nlam x n doubles); m <= 4096;
+ * alpha in (0, 1].  `stream` orders the call after the caller's earlier work
+ * (the call synchronises it before the workers start).  Returns the most
+ * severe status over the solves (an error stops).
  */
 int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
                 int64_t m, int64_t n, const int32_t* fold, int k, double alpha,
-                const double* c_lambda, int nlam, double tol, hipStream_t stream,
+                const double* c_lambda, int nlam, double tol, int slots, hipStream_t stream,
                 const ssnal_en_opts* opts, double* err_out, ssnal_en_info* infos);
 
 /* One problem of a batch or of the serving loop (fields as in ssnal_en_solve). */

@@ -89,7 +89,7 @@ def lib():
         L.ssnal_en_model_select.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, _vp, _vp, _vp,
                                             C.POINTER(Select)]
         L.ssnal_en_cv.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _vp, _i, _d, C.POINTER(_d), _i,
-                                  _d, _vp, C.POINTER(Opts), C.POINTER(_d), C.POINTER(Info)]
+                                  _d, _i, _vp, C.POINTER(Opts), C.POINTER(_d), C.POINTER(Info)]
         L.ssnal_en_path.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, C.POINTER(_d), _i, _i64,
                                     _d, _vp, _vp, C.POINTER(Opts), C.POINTER(Info)]
         L.ssnal_en_solve_batch.argtypes = [_vp, C.POINTER(Problem), _i, C.POINTER(Opts), _vp,
@@ -317,10 +317,11 @@ def ssnal_en_model_select(ctx, A, b, x, lambda2, m=None, want_beta=False, stream
     return out
 
 
-def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, m=None, opts=None, stream=None):
+def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, slots=4, m=None, opts=None, stream=None):
     """k-fold cross validation over the full data's grid: (err (k, nlam) mean
     squared validation errors, infos (k, nlam) dicts, status).  fold: device
-    int32 tensor of m labels in [0, k)."""
+    int32 tensor of m labels in [0, k); folds run on min(slots, k) concurrent
+    workers."""
     import numpy as np
     pA, dt, lda, m, n = _design(A, m)
     nlam = len(c_lambda)
@@ -329,7 +330,7 @@ def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, m=None, opts=None
     infos = (Info * (k * nlam))()
     o = opts if opts is not None else make_opts()
     rc = lib().ssnal_en_cv(ctx.ptr, pA, dt, lda, _ptr(b), m, n, _ptr(fold), int(k), float(alpha), cl,
-                           nlam, float(tol), _stream(stream), C.byref(o), err, infos)
+                           nlam, float(tol), int(slots), _stream(stream), C.byref(o), err, infos)
     if rc < 0:
         _check(rc)
     E = np.array(err[:], dtype=np.float64).reshape(k, nlam)

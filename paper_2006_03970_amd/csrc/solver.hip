@@ -8,10 +8,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <cstdarg>
@@ -59,6 +61,8 @@ struct ssnal_ctx {
   int device = 0;
   DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal;
   DevBuf cv_a, cv_x, cv_m;  // k-fold: a fold's training design, its path, rows / b / errors
+  std::vector<ssnal_ctx*> cv_sub;      // k-fold worker contexts (created on first use)
+  std::vector<hipStream_t> cv_streams;  // their streams (default priority)
   double* h_scal = nullptr;  // coherent pinned: SC_SIZE doubles, then the publish flag
   double* d_scal = nullptr;  // the same memory as the device addresses it
   unsigned long long pub_seq = 0;
@@ -706,6 +710,8 @@ void ssnal_ctx_destroy(ssnal_ctx* c) {
     if (b->p) (void)hipFree(b->p);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (ssnal_ctx* s : c->cv_sub) ssnal_ctx_destroy(s);
+  for (hipStream_t s : c->cv_streams) (void)hipStreamDestroy(s);
   delete c;
 }
 
@@ -815,9 +821,55 @@ static int path_impl(ssnal_ctx* ctx, const void* A, int dt, int64_t lda, const d
   return worst;
 }
 
+// Fold f of k-fold cross validation on context c and stream st: the
+// training rows (fold != f, in order) copied into c's buffer, the path over
+// the full data's grid on them, then the mean squared error over the rows of
+// fold f at every point into err_row (HOST, nlam).
+static int cv_fold(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int m, int64_t n,
+                   const int32_t* fold, int k, int f, double alpha, double lam_max,
+                   const double* c_lambda, int nlam, double tol, hipStream_t st,
+                   const ssnal_en_opts* opts, double* err_row, ssnal_en_info* inf) {
+  HIPCHK(hipSetDevice(c->device));
+  double* hs = c->h_scal;
+  const size_t sa = (size_t)dtype_size(dt);
+  if (int rc = ensure(c->cv_a, (size_t)(m - 1) * (size_t)n * sa)) return rc;
+  if (int rc = ensure(c->cv_x, (size_t)nlam * (size_t)n * 8)) return rc;
+  if (int rc = ensure(c->cv_m, (size_t)m * 4 + (size_t)(m + nlam + 2) * 8)) return rc;
+  int32_t* rows = (int32_t*)c->cv_m.p;
+  double* bt = (double*)((char*)c->cv_m.p + ((size_t)m * 4 + 7) / 8 * 8);
+  double* errd = bt + m;
+  double* X = (double*)c->cv_x.p;
+  Workspace w;
+  if (int rc = prepare(c, m, n, w)) return rc;
+  HIPCHK(fold_rows(fold, m, k, f, rows, w.scal, st));
+  if (int rc = readback(c, w, st, nullptr)) return rc;
+  if (hs[SC_CV_BAD] != 0.0) return fail(SSNAL_EINVAL, "%g fold labels outside [0, %d)", hs[SC_CV_BAD], k);
+  const int mt = (int)hs[SC_CV_MT];
+  const double mv = hs[SC_CV_MV];
+  if (mt < 1 || mv < 1) return fail(SSNAL_EINVAL, "fold %d leaves no training or no validation rows", f);
+  HIPCHK(gather_rows(A, dt, lda, n, rows, mt, b, c->cv_a.p, bt, st));
+  const int rc = path_impl(c, c->cv_a.p, dt, mt, bt, mt, n, alpha, lam_max, c_lambda, nlam, 0, tol, st,
+                           X, opts, inf);
+  if (rc < 0) return rc;
+  // validation errors: residual of the full design, summed over fold f
+  if (int rc2 = prepare(c, m, n, w)) return rc2;
+  for (int q = 0; q < nlam; ++q) {
+    const double* xq = X + (int64_t)q * n;
+    HIPCHK(support_count(xq, n, w.counts, st));
+    HIPCHK(support_write(xq, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
+    HIPCHK(gather_gemv_partial(A, dt, lda, m, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
+    HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, m, 2, nullptr, b, nullptr, w.t1, w.scal, st));
+    HIPCHK(fold_sq(w.t1, fold, m, f, errd + q, st));
+  }
+  HIPCHK(hipMemcpyAsync(err_row, errd, (size_t)nlam * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int q = 0; q < nlam; ++q) err_row[q] /= mv;
+  return rc;
+}
+
 int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
                 int64_t m, int64_t n, const int32_t* fold, int k, double alpha,
-                const double* c_lambda, int nlam, double tol, hipStream_t stream,
+                const double* c_lambda, int nlam, double tol, int slots, hipStream_t stream,
                 const ssnal_en_opts* opts, double* err_out, ssnal_en_info* infos) {
   g_err[0] = 0;
   if (!ctx || !fold || !err_out || !c_lambda) return fail(SSNAL_EINVAL, "null argument");
@@ -827,63 +879,76 @@ int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
   if (nlam < 1) return fail(SSNAL_EINVAL, "nlam must be >= 1");
   if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1]");
   if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
+  if (slots < 1 || slots > 64) return fail(SSNAL_EINVAL, "slots must lie in [1, 64]");
   for (int q = 0; q < nlam; ++q)
     if (!(c_lambda[q] > 0.0) || !std::isfinite(c_lambda[q]))
       return fail(SSNAL_EINVAL, "c_lambda[%d] must be finite and > 0", q);
   HIPCHK(hipSetDevice(ctx->device));
   const int dt = (int)a_dtype;
   const int mi = (int)m;
-  hipStream_t st = stream;
-  double* hs = ctx->h_scal;
-  // the full data's grid: lam_max = ||A^T b||_inf / alpha
+  // the full data's grid: lam_max = ||A^T b||_inf / alpha.  The read-back
+  // also means the caller's stream has finished all earlier work, so the
+  // workers' streams may read A, b and fold.
   double amax = 0.0;
   {
     Workspace w;
     if (int rc = prepare(ctx, m, n, w)) return rc;
-    HIPCHK(gemv_t(A, dt, lda, mi, n, nullptr, b, w.wd, true, st));
-    HIPCHK(absmax(w.wd, n, w.part, w.scal + SC_AMAX, st));
-    if (int rc = readback(ctx, w, st, nullptr)) return rc;
-    amax = hs[SC_AMAX];
+    HIPCHK(gemv_t(A, dt, lda, mi, n, nullptr, b, w.wd, true, stream));
+    HIPCHK(absmax(w.wd, n, w.part, w.scal + SC_AMAX, stream));
+    if (int rc = readback(ctx, w, stream, nullptr)) return rc;
+    amax = ctx->h_scal[SC_AMAX];
   }
   const double lam_max = amax / alpha;
-  // fold buffers: the training design (at most m - 1 rows), its path, row list, b and errors
-  const size_t sa = (size_t)dtype_size(dt);
-  if (int rc = ensure(ctx->cv_a, (size_t)(m - 1) * (size_t)n * sa)) return rc;
-  if (int rc = ensure(ctx->cv_x, (size_t)nlam * (size_t)n * 8)) return rc;
-  if (int rc = ensure(ctx->cv_m, (size_t)m * 4 + (size_t)(m + nlam + 2) * 8)) return rc;
-  int32_t* rows = (int32_t*)ctx->cv_m.p;
-  double* bt = (double*)((char*)ctx->cv_m.p + ((size_t)m * 4 + 7) / 8 * 8);
-  double* errd = bt + m;
-  double* X = (double*)ctx->cv_x.p;
+  const int nw = std::min(slots, k);
+  if (nw == 1) {
+    int worst = 0;
+    for (int f = 0; f < k; ++f) {
+      const int rc = cv_fold(ctx, A, dt, lda, b, mi, n, fold, k, f, alpha, lam_max, c_lambda, nlam, tol,
+                             stream, opts, err_out + (int64_t)f * nlam,
+                             infos ? infos + (int64_t)f * nlam : nullptr);
+      if (rc < 0) return rc;
+      worst = std::max(worst, rc);
+    }
+    return worst;
+  }
+  // folds run concurrently: worker i has its own context and stream; each
+  // fold's work is independent of the others, so the results do not depend
+  // on the schedule
+  while ((int)ctx->cv_sub.size() < nw) {
+    ssnal_ctx* sub = nullptr;
+    if (int rc = ssnal_ctx_create(ctx->device, &sub)) return rc;
+    hipStream_t s = nullptr;
+    if (hipStreamCreate(&s) != hipSuccess) {
+      ssnal_ctx_destroy(sub);
+      return fail(SSNAL_EHIP, "stream creation failed");
+    }
+    ctx->cv_sub.push_back(sub);
+    ctx->cv_streams.push_back(s);
+  }
+  std::vector<int> rcs(k, 0);
+  std::vector<std::string> msgs(k);
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int i = 0; i < nw; ++i) {
+    th.emplace_back([&, i]() {
+      for (int f = next++; f < k; f = next++) {
+        g_err[0] = 0;
+        rcs[f] = cv_fold(ctx->cv_sub[i], A, dt, lda, b, mi, n, fold, k, f, alpha, lam_max, c_lambda, nlam,
+                         tol, ctx->cv_streams[i], opts, err_out + (int64_t)f * nlam,
+                         infos ? infos + (int64_t)f * nlam : nullptr);
+        msgs[f] = g_err;
+        if (rcs[f] < 0) next = k;  // stop handing out folds
+      }
+    });
+  }
+  for (std::thread& t : th) t.join();
   int worst = 0;
   for (int f = 0; f < k; ++f) {
-    Workspace w;
-    if (int rc = prepare(ctx, m, n, w)) return rc;
-    HIPCHK(fold_rows(fold, mi, k, f, rows, w.scal, st));
-    if (int rc = readback(ctx, w, st, nullptr)) return rc;
-    if (hs[SC_CV_BAD] != 0.0) return fail(SSNAL_EINVAL, "%g fold labels outside [0, %d)", hs[SC_CV_BAD], k);
-    const int mt = (int)hs[SC_CV_MT];
-    const double mv = hs[SC_CV_MV];
-    if (mt < 1 || mv < 1) return fail(SSNAL_EINVAL, "fold %d leaves no training or no validation rows", f);
-    HIPCHK(gather_rows(A, dt, lda, n, rows, mt, b, ctx->cv_a.p, bt, st));
-    ssnal_en_info* inf = infos ? infos + (int64_t)f * nlam : nullptr;
-    const int rc = path_impl(ctx, ctx->cv_a.p, dt, mt, bt, mt, n, alpha, lam_max, c_lambda, nlam, 0,
-                             tol, st, X, opts, inf);
-    if (rc < 0) return rc;
-    worst = std::max(worst, rc);
-    // validation errors: residual of the full design, summed over fold f
-    if (int rc2 = prepare(ctx, m, n, w)) return rc2;
-    for (int q = 0; q < nlam; ++q) {
-      const double* xq = X + (int64_t)q * n;
-      HIPCHK(support_count(xq, n, w.counts, st));
-      HIPCHK(support_write(xq, n, w.counts, w.J, w.uJ, w.scal + SC_R, st));
-      HIPCHK(gather_gemv_partial(A, dt, lda, mi, w.J, w.uJ, w.scal + SC_R, n, w.gpart, st));
-      HIPCHK(gather_finish(w.gpart, w.scal + SC_R, 0, mi, 2, nullptr, b, nullptr, w.t1, w.scal, st));
-      HIPCHK(fold_sq(w.t1, fold, mi, f, errd + q, st));
+    if (rcs[f] < 0) {
+      snprintf(g_err, sizeof(g_err), "%s", msgs[f].c_str());
+      return rcs[f];
     }
-    HIPCHK(hipMemcpyAsync(err_out + (int64_t)f * nlam, errd, (size_t)nlam * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int q = 0; q < nlam; ++q) err_out[(int64_t)f * nlam + q] /= mv;
+    worst = std::max(worst, rcs[f]);
   }
   return worst;
 }

@@ -65,3 +65,23 @@ def test_cv_errors(gpu, ctx):
         gpu.ssnal_en_cv(ctx, A, b, _fold_dev(empty), 2, 0.5, [0.5])
     with pytest.raises(gpu.SsnalError):
         gpu.ssnal_en_cv(ctx, A, b, _fold_dev(np.arange(40) % 2), 1, 0.5, [0.5])
+    with pytest.raises(gpu.SsnalError):
+        gpu.ssnal_en_cv(ctx, A, b, _fold_dev(np.arange(40) % 2), 2, 0.5, [0.5], slots=0)
+
+
+def test_cv_slots_bitwise(gpu, ctx):
+    """Folds on concurrent workers give the errors of the folds in turn, bit for bit."""
+    import datagen
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    _say("cv slots")
+    p = datagen.make_problem(dict(m=200, n=4000, design="toeplitz", k=10, snr=4.0, alpha=0.6, c_lam=1.0,
+                                  tol=1e-6), seed=6, store="f32")
+    A, b = design_to_device(p.AT, "f32"), vec_to_device(p.b)
+    fold = _fold_dev(np.random.default_rng(9).permutation(np.arange(200) % 5))
+    grid = np.geomspace(1.0, 0.05, 12)
+    E1, I1, rc1 = gpu.ssnal_en_cv(ctx, A, b, fold, 5, 0.6, grid, tol=1e-6, slots=1)
+    E3, I3, rc3 = gpu.ssnal_en_cv(ctx, A, b, fold, 5, 0.6, grid, tol=1e-6, slots=3)
+    E8, I8, rc8 = gpu.ssnal_en_cv(ctx, A, b, fold, 5, 0.6, grid, tol=1e-6, slots=8)
+    assert rc1 == rc3 == rc8 == 0
+    assert np.array_equal(E1, E3) and np.array_equal(E1, E8)
+    assert [i["newton_iters"] for row in I1 for i in row] == [i["newton_iters"] for row in I8 for i in row]
