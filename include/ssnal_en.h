@@ -193,8 +193,8 @@ int ssnal_en_path(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t ld
  *              by ctx (1: every fold in turn on `stream`).  Each fold's work is
  *              independent of the others, so the results do not depend on slots.
  * The training rows of a fold are copied into a buffer of its worker ((m-1) x n
- * elements of A's storage type, plus the path: nlam x n doubles); m <= 4096;
- * alpha in (0, 1].  `stream` orders the call after the caller's earlier work
+ * elements of A's storage type, plus the path: nlam x n doubles); alpha in
+ * (0, 1].  `stream` orders the call after the caller's earlier work
  * (the call synchronises it before the workers start).  Returns the most
  * severe status over the solves (an error stops).
  */

@@ -930,9 +930,9 @@ hipError_t scatter(const int32_t* J, const double* v, const double* r_dev, int64
 }
 
 // ------------------------------------------------------------------ k-fold
-// Folds of m <= 4096 rows, one workgroup of 1024 threads: thread t owns the
+// Fold row lists by one workgroup of 1024 threads: thread t owns the
 // contiguous rows [t*c, t*c + c), c = ceil(m / 1024), so a block scan of the
-// per-thread counts orders the compacted rows.
+// per-thread counts orders the compacted rows (any m).
 constexpr int kFoldNT = 1024;
 __global__ __launch_bounds__(kFoldNT) void k_fold_rows(const int32_t* __restrict__ fold, int m, int k,
                                                        int f, int32_t* __restrict__ rows,

@@ -125,7 +125,7 @@ hipError_t eta_pass(const double* x, const double* q, int64_t n, double l1, doub
 // Small helpers
 hipError_t vec_scale_copy(const double* src, double alpha, double* dst, int64_t n, hipStream_t st);
 hipError_t vec_fill(double* dst, double v, int64_t n, hipStream_t st);
-// k-fold (m <= 4096): rows = the rows with fold != f in ascending order; scal
+// k-fold: rows = the rows with fold != f in ascending order; scal
 // slots get their count, the count of fold f, and the labels outside [0, k).
 hipError_t fold_rows(const int32_t* fold, int m, int k, int f, int32_t* rows, double* scal,
                      hipStream_t st);

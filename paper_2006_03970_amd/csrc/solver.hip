@@ -875,7 +875,6 @@ int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
   if (!ctx || !fold || !err_out || !c_lambda) return fail(SSNAL_EINVAL, "null argument");
   if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
   if (k < 2 || k > m) return fail(SSNAL_EINVAL, "need 2 <= k <= m folds");
-  if (m > 4096) return fail(SSNAL_EINVAL, "k-fold cross validation needs m <= 4096");
   if (nlam < 1) return fail(SSNAL_EINVAL, "nlam must be >= 1");
   if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SSNAL_EINVAL, "alpha must lie in (0, 1]");
   if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");

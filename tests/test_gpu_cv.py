@@ -85,3 +85,36 @@ def test_cv_slots_bitwise(gpu, ctx):
     assert rc1 == rc3 == rc8 == 0
     assert np.array_equal(E1, E3) and np.array_equal(E1, E8)
     assert [i["newton_iters"] for row in I1 for i in row] == [i["newton_iters"] for row in I8 for i in row]
+
+
+def test_cv_long_rows_composition(gpu, ctx, orc):
+    """m=4500 > 4096 rows (FP32 storage): each fold's errors equal the path
+    on the fold's training rows copied on the host (full data's grid), with
+    the validation residuals taken by the oracle."""
+    import datagen
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    _say("cv long rows")
+    m, n, k, alpha = 4500, 6000, 3, 0.6
+    p = datagen.make_problem(dict(m=m, n=n, design="gauss", k=20, snr=5.0, alpha=alpha, c_lam=1.0,
+                                  tol=1e-6), seed=12, store="f32")
+    A, b = design_to_device(p.AT, "f32"), vec_to_device(p.b)
+    fold = np.random.default_rng(13).permutation(np.arange(m) % k)
+    grid = np.geomspace(0.6, 0.1, 4)
+    E, infos, rc = gpu.ssnal_en_cv(ctx, A, b, _fold_dev(fold), k, alpha, grid, tol=1e-6, slots=2)
+    assert rc == 0
+    lam_max = np.max(np.abs(orc.gemv_t(p.AT64, p.b))) / alpha
+    ctx2 = gpu.Context(0)
+    for f in range(k):
+        tr = np.flatnonzero(fold != f)
+        At = design_to_device(np.ascontiguousarray(p.AT[:, tr]), "f32")
+        # the path on the training rows scales its own grid by ||A_t^T b_t||_inf; rescale
+        lam_t = np.max(np.abs(orc.gemv_t(p.AT64[:, tr], p.b[tr]))) / alpha
+        X, inf_t, st = gpu.ssnal_en_path(ctx2, At, vec_to_device(p.b[tr]), alpha, grid * lam_max / lam_t,
+                                         tol=1e-6)
+        assert st == 0
+        X = X.cpu().numpy()
+        va = np.flatnonzero(fold == f)
+        for q in range(len(grid)):
+            res = orc.gemv_n(p.AT64, X[q]) - p.b
+            ref = np.mean(res[va] ** 2)
+            assert E[f, q] == pytest.approx(ref, rel=1e-6), (f, q)
