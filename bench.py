@@ -316,7 +316,7 @@ def main():
     ap.add_argument("--no-path", action="store_true", help="skip the path + model selection section")
     ap.add_argument("--no-cg", action="store_true", help="skip the Newton-CG (m=20000) section")
     ap.add_argument("--cg-only", action="store_true", help="run only the Newton-CG section")
-    ap.add_argument("--serving", type=int, default=64, help="requests in the serving stream (0 = off)")
+    ap.add_argument("--serving", type=int, default=512, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-nmax", type=float, default=5e5)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--profile-gemv", type=int, default=0)
