@@ -17,6 +17,11 @@ solves being measured).
 The CPU baseline is the FP64 oracle on the machine's host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Further sections in the same JSON line (each can be skipped): the m=1000,
+n=1e6 single solve in FP32/BF16/FP64 (--no-c3); the 100-point SNP-like path
+with gcv / e-bic at every point and 10-fold cross validation (--no-path); a
+long-column Newton-CG solve, m=20000, n=2e5 (--no-cg, or --cg-only); the
+serving stream (--serving 0 skips it).
 Serving: a stream of requests with the serving workload's distributions (m
 log-uniform in [100, 2000], n log-uniform in [1e4, n_max], Gaussian-Toeplitz
 or SNP-like designs, FP32 or BF16 storage, tol 1e-6) goes through the
@@ -24,8 +29,7 @@ library's serving loop: first closed-loop (all submitted at once) for the
 saturated rate, then open-loop with seeded Poisson arrivals at 0.8x that rate;
 latency is scheduled arrival -> completion.  The serving designs are drawn on
 the GPU (datagen.make_problem_device: same distributions, torch's seeded
-generator).  Default: 64 requests with n_max = 5e5 (the full stream:
---serving 512).
+generator).  Default: the full stream of 512 requests with n_max = 5e5.
 Counter runs (HBM traffic of the A^T v kernel and of a plain copy of the same
 byte count, for the calibration factor):
        python bench.py --profile-gemv K     K launches of the FP32 A^T v pass
