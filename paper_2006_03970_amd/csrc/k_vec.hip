@@ -1,8 +1,9 @@
 // Passes over the n-vectors (x, A^T y, A^T d) and the gathers over the
 // active set J.  These read a few bytes per feature, next to the m bytes per
-// feature of the A^T v pass, so they are sized for few launches rather than
-// for bandwidth: 256 threads, 8 elements per thread, one block per 2048
-// features, and "last block finishes" reductions instead of extra launches.
+// feature of the A^T v pass, so their time is latency: 256 threads and 2
+// elements per thread, one block per 512 features (many short blocks spread
+// over the CUs; measured faster than 8 elements per thread at n = 1e5), and
+// sums across blocks finished by a one-block kernel (no device-wide fences).
 #include <algorithm>
 #include <type_traits>
 
@@ -13,7 +14,7 @@
 namespace ssnal {
 
 constexpr int kNT = 256;
-constexpr int kEPT = 8;
+constexpr int kEPT = 2;
 constexpr int kChunk = kNT * kEPT;
 
 int prox_blocks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
