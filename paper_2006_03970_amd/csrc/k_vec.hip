@@ -522,10 +522,11 @@ hipError_t gather_finish(const double* part, const double* r_dev, int64_t r_host
 // inactive for every trial step contributes nothing and is skipped; one that
 // stays active on its side for every step contributes s^2 times a common sum.
 constexpr int kLsSlots = kMaxTrials + 1;  // 32 trial sums + the common second-order sum
-// One feature per thread (grid-stride past kLsMaxBlocks blocks): only features
+// One feature per thread, grid-stride past kLsMaxBlocks blocks: only features
 // near the threshold run the trial loop, so spreading them over many waves
-// keeps that loop off a few SIMDs.
-constexpr int kLsMaxBlocks = 1024;
+// keeps that loop off a few SIMDs, while the cap bounds the 33-slot partial
+// rows the selection kernel sums (256 measured faster than 1024 at n = 1e5).
+constexpr int kLsMaxBlocks = 256;
 int ls_blocks(int64_t n) {
   const int64_t nb = (n + kNT - 1) / kNT;
   return (int)(nb < kLsMaxBlocks ? nb : kLsMaxBlocks);
