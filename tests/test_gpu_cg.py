@@ -202,3 +202,32 @@ def test_path_long_rows(gpu, ctx, orc):
         lam = cl[k] * lam_max
         eta = orc.eta(p.AT64, p.b, X[k], 0.7 * lam, 0.3 * lam)
         assert eta <= 1.5e-6, (k, eta)
+
+
+def test_solve_max_rows(gpu, ctx, orc):
+    """The largest m a solve accepts (2^20 rows, n = 64, FP32 storage):
+    certified by the oracle's KKT residual; one row more is rejected."""
+    import torch
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    m, n = 1 << 20, 64
+    _say("max rows", m, n)
+    g = np.random.default_rng(21)
+    AT = g.standard_normal((n, m)).astype(np.float32)
+    AT /= np.linalg.norm(AT, axis=1, keepdims=True).astype(np.float32)
+    x_true = np.zeros(n)
+    x_true[[3, 17, 40]] = [2.0, -1.5, 1.0]
+    AT64 = AT.astype(np.float64)
+    b = orc.gemv_n(AT64, x_true) + 0.01 * g.standard_normal(m)
+    lmax = np.max(np.abs(orc.gemv_t(AT64, b)))
+    l1, l2 = 0.2 * lmax, 0.1 * lmax
+    A = design_to_device(AT, "f32")
+    x, info = gpu.ssnal_en_solve(ctx, A, vec_to_device(b), l1, l2, tol=1e-6)
+    assert info["status"] == 0, info
+    xh = x.cpu().numpy()
+    assert orc.eta(AT64, b, xh, l1, l2) <= 1.5e-6
+    assert set(np.flatnonzero(xh)) >= {3, 17, 40}
+    big = torch.zeros((2, m + 1), dtype=torch.float32, device="cuda")
+    with pytest.raises(gpu.SsnalError):
+        gpu.ssnal_en_solve(ctx, big, vec_to_device(np.ones(m + 1)), 0.1, 0.1)
+    del A, big
+    torch.cuda.empty_cache()
