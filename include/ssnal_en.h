@@ -300,19 +300,22 @@ int ssnal_active_prox(ssnal_ctx* ctx, const double* x, const double* w, int64_t 
 
 /* Newton matrix (eq. AJ_system / eq. smw_formula) for the active columns J (r entries):
  * form 0: out = I_m + kappa A_J A_J^T (m x m); form 1: out = I_r / kappa + A_J^T A_J (r x r).
- * out: N x N row-major FP64 (N = m or r), both triangles written. */
+ * out: N x N row-major FP64 (N = m or r), both triangles written; N <= 4096
+ * (SSNAL_EINVAL beyond). */
 int ssnal_newton_matrix(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
                         int64_t m, const int32_t* J, int64_t r, double kappa, int form,
                         double* out, hipStream_t stream);
 
 /* In-place FP64 Cholesky of an SPD N x N row-major matrix: on return the lower
  * triangle holds L (V = L L^T) and the strict upper triangle is zero.
- * Returns SSNAL_ENUMERIC for a non-positive pivot. */
+ * 1 <= N <= 4096.  Returns SSNAL_ENUMERIC for a non-positive pivot. */
 int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream);
 
 /* Newton direction d = -(I + kappa A_J A_J^T)^{-1} g (eq. AJ_system), by the
  * m x m system (form 0), the r x r system of eq. smw_formula (form 1), or the
- * solver's own choice (form -1: r x r when 0 < r < m). g, d: m doubles. */
+ * solver's own choice (form -1: r x r when 0 < r < m). g, d: m doubles.  The
+ * factored system must fit 4096 x 4096 (SSNAL_EINVAL otherwise; larger systems
+ * take ssnal_newton_cg). */
 int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
                            int64_t m, const int32_t* J, int64_t r, double kappa, const double* g,
                            double* d, int form, hipStream_t stream);
