@@ -14,7 +14,7 @@ timed live with HIP events around each of its launches on the solve's stream
 in every fourth timed solve (the event records leave the GPU idle for a few
 microseconds around each timed launch, so timing every solve would slow the
 solves being measured).
-The CPU baseline is the FP64 oracle on the machine's host cores.
+The CPU baseline is the FP64 oracle on the host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Further sections in the same JSON line (each can be skipped): the m=1000,
@@ -327,7 +327,7 @@ def main():
     ap.add_argument("--profile-copy", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
