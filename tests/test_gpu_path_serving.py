@@ -261,3 +261,37 @@ def test_concurrent_solves_bitwise(gpu):
     torch.cuda.synchronize()
     for i, xa in enumerate(alone):
         assert bool((xs[i] == xa).all()), i
+
+
+def test_server_long_rows_cg_in_mix(gpu, ctx):
+    """A request with m = 5000 > 4096 rows (its first Newton steps take
+    conjugate-gradient directions) among small ones on three slots gives the
+    same bits as each solved alone."""
+    import datagen
+    import torch
+    _say("server mix with a Newton-CG request")
+    probs, _ = _problems(gpu, 4, seed0=70)
+    p = datagen.make_problem(dict(m=5000, n=30000, design="gauss", k=20, snr=5.0, alpha=0.5, c_lam=0.05,
+                                  tol=1e-6), seed=71, store="f32")
+    A, b = _upload(p)
+    probs.insert(1, dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol,
+                         x_out=torch.empty(p.n, dtype=torch.float64, device=A.device)))
+    alone = []
+    for q in probs:
+        x, info = gpu.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"])
+        assert info["status"] == 0
+        alone.append(x.clone())
+        q["x_out"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    srv = gpu.Server(0, hbm_budget=8 << 30, max_slots=3)
+    try:
+        tickets = [srv.submit(q["A"], q["b"], q["lambda1"], q["lambda2"], q["tol"], q["x_out"])
+                   for q in probs]
+        infos = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    assert all(i["status"] == 0 for i in infos)
+    assert infos[1]["cg_iters"] > 0
+    for q, xa in zip(probs, alone):
+        assert bool((q["x_out"] == xa).all())
