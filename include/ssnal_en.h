@@ -82,7 +82,7 @@ typedef struct {
                             r < m and r <= 4096 for the Woodbury form), conjugate
                             gradients beyond (default); 1 = conjugate gradients always */
   int32_t cg_maxit;      /* <= 0: 500 conjugate-gradient iterations per Newton step */
-  double cg_eta;         /* <= 0: 0.1; CG stops at ||V d + g|| <= min(cg_eta, kkt1^cg_tau) ||g|| */
+  double cg_eta;         /* <= 0: 0.1; < 1; CG stops at ||V d + g|| <= min(cg_eta, kkt1^cg_tau) ||g|| */
   double cg_tau;         /* <= 0: 0.5 */
 } ssnal_en_opts;
 

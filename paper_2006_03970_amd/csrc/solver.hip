@@ -438,6 +438,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   if (o.max_backtrack > kMaxTrials - 1) o.max_backtrack = kMaxTrials - 1;
   if (!(o.mu < 0.5)) return fail(SSNAL_EINVAL, "mu must lie in (0, 1/2)");
   if (!(o.delta < 1.0)) return fail(SSNAL_EINVAL, "delta must lie in (0, 1)");
+  if (!(o.cg_eta < 1.0)) return fail(SSNAL_EINVAL, "cg_eta must lie in (0, 1)");
   HIPCHK(hipSetDevice(c->device));
   Workspace w;
   if (int rc = prepare(c, m, n, w)) return rc;

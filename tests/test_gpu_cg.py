@@ -125,6 +125,8 @@ def test_solve_forced_cg_fp64_vs_oracle(gpu, ctx, orc, seed):
     xd, infod = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
     assert infod["cg_iters"] == 0
     assert np.max(np.abs(x - xd.cpu().numpy())) <= 1e-7
+    with pytest.raises(gpu.SsnalError):
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(newton_cg=1, cg_eta=1.0))
 
 
 def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc):
