@@ -317,7 +317,7 @@ def ssnal_en_model_select(ctx, A, b, x, lambda2, m=None, want_beta=False, stream
     return out
 
 
-def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, slots=4, m=None, opts=None, stream=None):
+def ssnal_en_cv(ctx, A, b, fold, k, alpha, c_lambda, tol=1e-6, slots=8, m=None, opts=None, stream=None):
     """k-fold cross validation over the full data's grid: (err (k, nlam) mean
     squared validation errors, infos (k, nlam) dicts, status).  fold: device
     int32 tensor of m labels in [0, k); folds run on min(slots, k) concurrent
