@@ -21,7 +21,10 @@ Further sections in the same JSON line (each can be skipped): the m=1000,
 n=1e6 single solve in FP32/BF16/FP64 (--no-c3); the 100-point SNP-like path
 with gcv / e-bic at every point and 10-fold cross validation (--no-path); a
 long-column Newton-CG solve, m=20000, n=2e5 (--no-cg, or --cg-only); the
-serving stream (--serving 0 skips it).
+Newton-matrix SYRK at its largest dense shape, m=4096 from r=8192 columns, in
+TFLOP/s against the MFMA peak (--no-syrk); the serving stream (--serving 0
+skips it).
+       python bench.py --profile-syrk K     K launches of that SYRK per storage type
 Serving: a stream of requests with the serving workload's distributions (m
 log-uniform in [100, 2000], n log-uniform in [1e4, n_max], Gaussian-Toeplitz
 or SNP-like designs, FP32 or BF16 storage, tol 1e-6) goes through the
@@ -231,6 +234,51 @@ def cg_bench(reps=2, r_fixed=16000):
     return out
 
 
+SYRK_M, SYRK_R = 4096, 8192  # the largest dense Newton matrix: m x m from r columns
+MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA, published
+
+
+def syrk_bench(reps=5, launches=0):
+    """The Newton matrix I + kappa A_J A_J^T at its largest dense shape (m =
+    4096 rows, r = 8192 active columns; FP64 storage on FP64 MFMA, FP32
+    storage on FP32 MFMA): TFLOP/s of the m (m + 1) r flops of the lower
+    triangle against the dense MFMA peak.  launches > 0: only that many calls
+    per storage type (a short run for rocprofv3 counters)."""
+    import torch
+
+    from paper_2006_03970_amd import binding
+
+    m, r = SYRK_M, SYRK_R
+    dev = torch.device("cuda:0")
+    ctx = binding.Context(0)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    J = torch.arange(r, dtype=torch.int32, device=dev)
+    out = {}
+    for store, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        A = torch.randn((r, m), generator=gen, device=dev, dtype=dt)
+        A /= torch.linalg.vector_norm(A, dim=1, keepdim=True)
+        if launches:
+            for k in range(launches):
+                binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
+                print(f"[bench] syrk {store} launch {k}", file=sys.stderr, flush=True)
+            continue
+        binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
+        el = (time.perf_counter() - t) / reps
+        tfs = m * (m + 1) * r / el / 1e12
+        out[store] = {"ms": el * 1e3, "tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[store],
+                      "frac": tfs / MFMA_PEAK_TFS[store]}
+        print(f"[bench] syrk {store}: {el * 1e3:.2f} ms, {tfs:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        del A
+    if launches:
+        return None
+    out["shape"] = {"m": m, "r": r, "flops": m * (m + 1) * r}
+    return out
+
+
 def serving_bench(nreq, nmax, slots, seed=7):
     """p50/p99 latency and solves/s of the serving loop over a request stream."""
     import numpy as np
@@ -325,6 +373,9 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--profile-gemv", type=int, default=0)
     ap.add_argument("--profile-copy", type=int, default=0)
+    ap.add_argument("--profile-syrk", type=int, default=0,
+                    help="only K launches of the m=4096, r=8192 Newton-matrix SYRK per storage type")
+    ap.add_argument("--no-syrk", action="store_true", help="skip the Newton-matrix SYRK section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -343,6 +394,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.cg_only:
         print(json.dumps({"newton_cg": cg_bench()}), flush=True)
+        return
+    if args.profile_syrk:
+        syrk_bench(launches=args.profile_syrk)
         return
     cfg = datagen.CONFIGS["c2"]
     t0 = time.time()
@@ -465,6 +519,8 @@ def main():
         out["path"] = path_bench()
     if not args.no_cg:
         out["newton_cg"] = cg_bench()
+    if not args.no_syrk:
+        out["newton_matrix_syrk"] = syrk_bench()
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
 
