@@ -16,9 +16,16 @@
 
 namespace ssnal {
 
-template <int ITERS>
+// Columns in flight per wave for ITERS loads per lane and element size ES
+// (ES = 0: the long-column kernel).  FP32 columns of two loads per lane keep
+// 4 in flight (fewer registers, more waves: measured faster than 8), BF16
+// ones 8.
+constexpr int cols_for(int iters, int es) {
+  return iters <= 1 ? 8 : (iters <= 2 ? (es == 4 ? 4 : 8) : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1)));
+}
+template <int ITERS, int ES = 0>
 struct ColsFor {
-  static constexpr int value = ITERS <= 1 ? 8 : (ITERS <= 2 ? 8 : (ITERS <= 4 ? 4 : (ITERS <= 8 ? 2 : 1)));
+  static constexpr int value = cols_for(ITERS, ES);
 };
 
 template <typename T, typename ACC, int ITERS, bool COLSQ, int VB>
@@ -27,7 +34,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
                                                 double* __restrict__ w, int64_t cpb,
                                                 double* __restrict__ colsq_part) {
   constexpr int VN = VB / (int)sizeof(T);
-  constexpr int COLS = ColsFor<ITERS>::value;
+  constexpr int COLS = ColsFor<ITERS, (int)sizeof(T)>::value;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
 
@@ -238,7 +245,7 @@ hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* 
   constexpr int VN = VB / (int)sizeof(T);
   const int need = (m + kWave * VN - 1) / (kWave * VN);
   int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
-  int cols = iters <= 2 ? 8 : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1));
+  const int cols = cols_for(iters, (int)sizeof(T));
   const int64_t step = 4 * (int64_t)cols;
   const int64_t nsteps = (n + step - 1) / step;
   // one column step (4 waves x cols columns) per block: the many short blocks
@@ -301,7 +308,7 @@ hipError_t launch_long(const T* A, int64_t lda, int m, int64_t n, const int32_t*
   const int need = (m + kWave * VN - 1) / (kWave * VN);
   int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
   if (iters > max_iters<T, ACC, VB>()) iters = max_iters<T, ACC, VB>();
-  const int cols = iters <= 2 ? 8 : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1));
+  const int cols = cols_for(iters, 0);
   const int64_t step = 4 * (int64_t)cols;
   const int64_t nsteps = (n + step - 1) / step;
   int64_t spb = (nsteps + 1023) / 1024;
