@@ -129,15 +129,16 @@ def test_solve_forced_cg_fp64_vs_oracle(gpu, ctx, orc, seed):
         gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(newton_cg=1, cg_eta=1.0))
 
 
-def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc):
-    """The m=500, n=100000 block-Toeplitz workload with FP32 storage and CG
-    directions: KKT residual <= 1e-6 on the stored design and the objective of
-    the factored-direction solve."""
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc, store):
+    """The m=500, n=100000 block-Toeplitz workload with FP32 or BF16 storage
+    and CG directions: KKT residual <= 1e-6 on the stored design and the
+    objective of the factored-direction solve."""
     import datagen
     from paper_2006_03970_amd.device import design_to_device, vec_to_device
-    p = datagen.make_problem("c2", seed=1, store="f32")
-    _say("forced cg c2 f32")
-    A, b = design_to_device(p.AT, "f32"), vec_to_device(p.b)
+    p = datagen.make_problem("c2", seed=1, store=store)
+    _say("forced cg c2", store)
+    A, b = design_to_device(p.AT, store), vec_to_device(p.b)
     x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(newton_cg=1))
     x = x.cpu().numpy()
     assert info["status"] == 0, info
@@ -147,7 +148,7 @@ def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc):
     F = orc.primal_obj(p.AT64, p.b, x, p.lam1, p.lam2)
     Fd = orc.primal_obj(p.AT64, p.b, xd.cpu().numpy(), p.lam1, p.lam2)
     assert abs(F - Fd) <= 1e-6 * abs(Fd)
-    print(f"[report] c2 f32 cg: newton {info['newton_iters']} cg {info['cg_iters']} "
+    print(f"[report] c2 {store} cg: newton {info['newton_iters']} cg {info['cg_iters']} "
           f"ms {info['solve_ms']:.1f} (factored: newton {infod['newton_iters']} ms {infod['solve_ms']:.1f})")
 
 
