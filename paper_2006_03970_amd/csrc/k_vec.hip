@@ -443,10 +443,10 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
   }
 }
 
-// Mode 0 by one workgroup of 1024 threads (m <= kFin1Max): the chunk sums,
+// Mode 0 by one workgroup of 512 threads (m <= kFin1Max): the chunk sums,
 // g, rho and the three sums of k_gather_finish + k_final<3> in one launch,
 // optionally publishing the slots to the host at the end.
-constexpr int kFin1NT = 1024;
+constexpr int kFin1NT = 512;
 constexpr int kFin1Max = 2048;
 __global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __restrict__ part,
                                                             const double* __restrict__ r_dev, int m,
