@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("SSNAL_ORACLE_LIB") or os.path.join(_HERE, "liboracle_
 SRC = os.path.join(_HERE, "oracle_en.c")
 
 # No contraction, no fast-math: IEEE binary64 with one rounding per operation.
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
 
 def build(force: bool = True) -> str:
@@ -60,6 +60,8 @@ def lib():
         if not os.path.exists(LIB_PATH):
             build()
         L = C.CDLL(LIB_PATH)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         L.orc_prox_sp.restype = _d
         L.orc_prox_sp.argtypes = [_d, _d, _d, _d]
         L.orc_prox_pstar.restype = _d
@@ -111,6 +113,16 @@ def _design(AT):
     AT = _f64(AT)
     n, m = AT.shape
     return AT, m, n
+
+
+def set_threads(k: int) -> None:
+    """Host threads for the oracle's independent-sum loops (results do not
+    depend on the count)."""
+    lib().orc_set_threads(int(k))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 # ---- primitives -----------------------------------------------------------

@@ -86,7 +86,16 @@ double orc_pstar(const double* z, int64_t n, double l1, double l2) {
 /* ---------------------------------------------------------------------- */
 /* Dense products (plain dot products, left to right) */
 
+/* Host threads for the loops below whose iterations are independent: each
+ * output entry is one sum, evaluated in the same order whatever the thread
+ * count, so every result is bit-for-bit the same with 1 or k threads (a pin
+ * checks this).  Default 1. */
+static int g_threads = 1;
+void orc_set_threads(int k) { g_threads = k < 1 ? 1 : k; }
+int orc_get_threads(void) { return g_threads; }
+
 void orc_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* v, double* w) {
+#pragma omp parallel for num_threads(g_threads) schedule(static) if (g_threads > 1 && n >= 256)
   for (int64_t j = 0; j < n; ++j) {
     const double* a = COL(A, lda, j);
     double s = 0.0;
@@ -95,13 +104,20 @@ void orc_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double
   }
 }
 
+/* out = A x; out_i accumulates a_ij x_j over j in increasing order.  Rows
+ * are split into independent blocks of 256 for the threads. */
 void orc_gemv_n(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, double* out) {
-  for (int64_t i = 0; i < m; ++i) out[i] = 0.0;
-  for (int64_t j = 0; j < n; ++j) {
-    double xj = x[j];
-    if (xj == 0.0) continue; /* adds +-0 only: skipping it changes no value */
-    const double* a = COL(A, lda, j);
-    for (int64_t i = 0; i < m; ++i) out[i] += a[i] * xj;
+  const int64_t nblk = (m + 255) / 256;
+#pragma omp parallel for num_threads(g_threads) schedule(static) if (g_threads > 1 && nblk > 1)
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int64_t i0 = blk * 256, i1 = i0 + 256 < m ? i0 + 256 : m;
+    for (int64_t i = i0; i < i1; ++i) out[i] = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      double xj = x[j];
+      if (xj == 0.0) continue; /* adds +-0 only: skipping it changes no value */
+      const double* a = COL(A, lda, j);
+      for (int64_t i = i0; i < i1; ++i) out[i] += a[i] * xj;
+    }
   }
 }
 
@@ -243,6 +259,7 @@ void orc_newton_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J
     const double* a = COL(A, lda, J[k]);
     for (int64_t i = 0; i < m; ++i) AJ[i * r + k] = a[i];
   }
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 4) if (g_threads > 1 && m >= 64)
   for (int64_t i = 0; i < m; ++i) {
     for (int64_t l = 0; l <= i; ++l) {
       double s = dot(AJ + i * r, AJ + l * r, r);
@@ -260,6 +277,7 @@ void orc_newton_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J
  * Pinned: the Woodbury identity against the m x m matrix. */
 void orc_smw_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, int64_t r,
                     double kappa, double* W) {
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 4) if (g_threads > 1 && r >= 64)
   for (int64_t p = 0; p < r; ++p) {
     const double* ap = COL(A, lda, J[p]);
     for (int64_t q = 0; q <= p; ++q) {
@@ -272,22 +290,29 @@ void orc_smw_matrix(const double* A, int64_t lda, int64_t m, const int32_t* J, i
 }
 
 /* In-place Cholesky V = L L^T (row-major, L in the lower triangle, the
- * strict upper triangle zeroed).  Textbook Cholesky-Banachiewicz.
- * Returns 0, or -(k+1) if the k-th pivot is not positive. */
+ * strict upper triangle zeroed).  Textbook Cholesky-Crout, one column at a
+ * time:
+ *   l_jj = sqrt(v_jj - sum_{k<j} l_jk^2),
+ *   l_ij = (v_ij - sum_{k<j} l_ik l_jk) / l_jj   (i > j),
+ * each sum taken in increasing k.  The entries below a pivot do not depend on
+ * each other, so the threads share them.  Returns 0, or -(k+1) if the k-th
+ * pivot is not positive. */
 int orc_cholesky(double* V, int64_t m) {
-  for (int64_t i = 0; i < m; ++i) {
-    for (int64_t j = 0; j <= i; ++j) {
-      double s = V[i * m + j];
-      for (int64_t k = 0; k < j; ++k) s -= V[i * m + k] * V[j * m + k];
-      if (i == j) {
-        if (!(s > 0.0)) return -(int)(i + 1);
-        V[i * m + i] = sqrt(s);
-      } else {
-        V[i * m + j] = s / V[j * m + j];
-      }
+  for (int64_t j = 0; j < m; ++j) {
+    double s = V[j * m + j];
+    for (int64_t k = 0; k < j; ++k) s -= V[j * m + k] * V[j * m + k];
+    if (!(s > 0.0)) return -(int)(j + 1);
+    const double p = sqrt(s);
+    V[j * m + j] = p;
+#pragma omp parallel for num_threads(g_threads) schedule(static) if (g_threads > 1 && m - j > 128)
+    for (int64_t i = j + 1; i < m; ++i) {
+      double t = V[i * m + j];
+      for (int64_t k = 0; k < j; ++k) t -= V[i * m + k] * V[j * m + k];
+      V[i * m + j] = t / p;
     }
-    for (int64_t j = i + 1; j < m; ++j) V[i * m + j] = 0.0;
   }
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = i + 1; j < m; ++j) V[i * m + j] = 0.0;
   return 0;
 }
 

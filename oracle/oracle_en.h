@@ -49,6 +49,12 @@ typedef struct {
 /* One row per Newton iteration: outer, inner, r, sigma, step, kkt1 */
 #define ORC_TRACE_COLS 6
 
+/* Host threads for the loops whose outputs are independent sums (A^T v, A x,
+ * the Newton matrices, the entries below each Cholesky pivot).  Results do
+ * not depend on the count.  Default 1. */
+void orc_set_threads(int k);
+int orc_get_threads(void);
+
 /* primitives */
 double orc_prox_sp(double t, double sigma, double l1, double l2);
 double orc_prox_pstar(double v, double sigma, double l1, double l2);

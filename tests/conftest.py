@@ -18,6 +18,9 @@ def orc():
     import oracle
     if not os.path.exists(oracle.LIB_PATH):
         oracle.build()
+    # results do not depend on the thread count (pinned); threads only speed
+    # up the large parity cases
+    oracle.set_threads(min(16, os.cpu_count() or 1))
     return oracle
 
 

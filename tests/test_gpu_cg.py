@@ -7,6 +7,8 @@ and duality gap."""
 import numpy as np
 import pytest
 
+from tests.certify import check_eta
+
 pytestmark = pytest.mark.gpu
 
 
@@ -143,7 +145,7 @@ def test_solve_forced_cg_mixed_full_size(gpu, ctx, orc, store):
     x = x.cpu().numpy()
     assert info["status"] == 0, info
     assert info["cg_iters"] > 0
-    assert orc.eta(p.AT64, p.b, x, p.lam1, p.lam2) <= 1.5 * p.tol
+    check_eta(orc, p.AT64, p.b, x, p.lam1, p.lam2, p.tol, eta_gpu=info["kkt_rel"])
     xd, infod = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
     F = orc.primal_obj(p.AT64, p.b, x, p.lam1, p.lam2)
     Fd = orc.primal_obj(p.AT64, p.b, xd.cpu().numpy(), p.lam1, p.lam2)
@@ -171,8 +173,7 @@ def test_solve_long_rows_auto_cg(gpu, ctx, orc, store):
     assert info["status"] == 0, info
     assert info["cg_iters"] > 0
     x = x.cpu().numpy()
-    eta = orc.eta(p.AT64, p.b, x, p.lam1, p.lam2)
-    assert eta <= 1.5 * p.tol
+    eta = check_eta(orc, p.AT64, p.b, x, p.lam1, p.lam2, p.tol, eta_gpu=info["kkt_rel"])
     F = orc.primal_obj(p.AT64, p.b, x, p.lam1, p.lam2)
     y = orc.gemv_n(p.AT64, x) - p.b
     D = orc.dual_obj(p.AT64, p.b, y, p.lam1, p.lam2)
@@ -203,8 +204,7 @@ def test_path_long_rows(gpu, ctx, orc):
     lam_max = np.max(np.abs(orc.gemv_t(p.AT64, p.b))) / 0.7  # over the stored design, as the path
     for k in range(1, len(cl)):
         lam = cl[k] * lam_max
-        eta = orc.eta(p.AT64, p.b, X[k], 0.7 * lam, 0.3 * lam)
-        assert eta <= 1.5e-6, (k, eta)
+        check_eta(orc, p.AT64, p.b, X[k], 0.7 * lam, 0.3 * lam, 1e-6, eta_gpu=infos[k]["kkt_rel"])
 
 
 def test_solve_max_rows(gpu, ctx, orc):
@@ -227,7 +227,7 @@ def test_solve_max_rows(gpu, ctx, orc):
     x, info = gpu.ssnal_en_solve(ctx, A, vec_to_device(b), l1, l2, tol=1e-6)
     assert info["status"] == 0, info
     xh = x.cpu().numpy()
-    assert orc.eta(AT64, b, xh, l1, l2) <= 1.5e-6
+    check_eta(orc, AT64, b, xh, l1, l2, 1e-6, eta_gpu=info["kkt_rel"])
     assert set(np.flatnonzero(xh)) >= {3, 17, 40}
     big = torch.zeros((2, m + 1), dtype=torch.float32, device="cuda")
     with pytest.raises(gpu.SsnalError):

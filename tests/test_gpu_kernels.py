@@ -102,7 +102,9 @@ def _active(m, n, r, seed):
 
 
 NM_CASES = [(100, 500, 60), (100, 2000, 400), (130, 700, 250), (500, 4000, 900), (500, 4000, 37),
-            (257, 3000, 200), (64, 100, 64)]
+            (257, 3000, 200), (64, 100, 64),
+            # the m x m system at the serving workload's largest m, and past it
+            (1000, 6000, 1500), (2000, 8000, 2600), (2000, 8000, 700)]
 
 
 @pytest.mark.parametrize("m,n,r", NM_CASES)
@@ -128,7 +130,7 @@ def test_newton_matrix(gpu, ctx, orc, m, n, r, store):
 
 
 # ----------------------------------------------------------------- Cholesky
-@pytest.mark.parametrize("N", [1, 5, 64, 100, 128, 129, 200, 500, 1000])
+@pytest.mark.parametrize("N", [1, 5, 64, 100, 128, 129, 200, 500, 1000, 2000, 4095, 4096])
 def test_cholesky(gpu, ctx, orc, N):
     import torch
     _say("cholesky", N)
@@ -157,7 +159,11 @@ DIR_CASES = [(100, 2000, 76, "f64"), (100, 2000, 150, "f64"), (500, 5000, 208, "
              (500, 5000, 208, "f32"), (500, 5000, 700, "bf16"), (40, 300, 0, "f64"),
              # systems past 544 rows (backward substitution streams rows it cannot
              # hold), even and odd orders
-             (1000, 4000, 900, "f64"), (999, 4000, 901, "f64")]
+             (1000, 4000, 900, "f64"), (999, 4000, 901, "f64"),
+             # m = 2000 (the serving workload's largest m) in both forms, and the
+             # Woodbury form at r = 4000 (m = 4500: no m x m system exists)
+             (2000, 8000, 2600, "f64"), (2000, 8000, 1300, "f64"), (2000, 8000, 1300, "f32"),
+             (4500, 9000, 4000, "f64")]
 
 
 @pytest.mark.parametrize("m,n,r,store", DIR_CASES)
@@ -172,7 +178,7 @@ def test_newton_direction(gpu, ctx, orc, m, n, r, store):
     A = _dev(AT, store)
     Jd = torch.from_numpy(J).cuda()
     tol = 1e-10 if store == "f64" else 1e-4
-    forms = [0, -1] + ([1] if 0 < r < m else [])
+    forms = ([0] if m <= 4096 else []) + [-1] + ([1] if 0 < r < m else [])
     for form in forms:
         d = gpu.ssnal_newton_direction(ctx, A, Jd, kappa, _vec(gvec), form=form).cpu().numpy()
         assert np.linalg.norm(d - dr) <= tol * np.linalg.norm(dr), form

@@ -8,6 +8,8 @@ solutions' objectives."""
 import numpy as np
 import pytest
 
+from tests.certify import check_eta
+
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
@@ -47,10 +49,8 @@ def test_c3_fp32_storage(gpu, ctx, orc, c3):
     xh = x.cpu().numpy()
     del A
     torch.cuda.empty_cache()
-    eta = orc.eta(p.AT64, p.b, xh, p.lam1, p.lam2)
+    eta = check_eta(orc, p.AT64, p.b, xh, p.lam1, p.lam2, p.tol, eta_gpu=info["kkt_rel"])
     _say("c3 fp32 eta", eta, "nnz", info["nnz"], "iters", info["outer_iters"], info["newton_iters"])
-    assert eta <= p.tol
-    assert abs(eta - info["kkt_rel"]) <= 1e-3 * p.tol + 1e-2 * eta
     F = orc.primal_obj(p.AT64, p.b, xh, p.lam1, p.lam2)
     y = orc.gemv_n(p.AT64, xh) - p.b  # y = A x - b
     D = orc.dual_obj(p.AT64, p.b, y, p.lam1, p.lam2)
@@ -74,10 +74,9 @@ def test_c3_bf16_storage(gpu, ctx, orc, c3):
     torch.cuda.empty_cache()
     assert info["status"] == 0, info
     xh = x.cpu().numpy()
-    eta = orc.eta(ATb, p.b, xh, p.lam1, p.lam2)
+    eta = check_eta(orc, ATb, p.b, xh, p.lam1, p.lam2, p.tol, eta_gpu=info["kkt_rel"])
     eta32 = orc.eta(p.AT64, p.b, xh, p.lam1, p.lam2)  # against the FP32 design, reported
     _say("c3 bf16 eta", eta, "eta on the fp32 design", eta32, "nnz", info["nnz"])
-    assert eta <= p.tol
 
 
 def test_c3_fp64_storage(gpu, ctx, orc, c3):
@@ -92,10 +91,9 @@ def test_c3_fp64_storage(gpu, ctx, orc, c3):
     torch.cuda.empty_cache()
     assert info["status"] == 0, info
     xh = x.cpu().numpy()
-    eta = orc.eta(p.AT64, p.b, xh, p.lam1, p.lam2)
+    eta = check_eta(orc, p.AT64, p.b, xh, p.lam1, p.lam2, p.tol, eta_gpu=info["kkt_rel"])
     F = orc.primal_obj(p.AT64, p.b, xh, p.lam1, p.lam2)
     _say("c3 fp64 eta", eta, "F", F)
-    assert eta <= p.tol
     if hasattr(c3, "F32"):
         # the FP32-storage and FP64 solutions of the same (FP32-representable)
         # design agree to the accuracy eta <= 1e-6 allows

@@ -21,8 +21,8 @@ MUTATIONS = {
     "grad_psi_sign": ("g[i] = y[i] + b[i] - u[i];", "g[i] = y[i] + b[i] + u[i];"),
     "tie_active": ("if (t > thr) { J[r]", "if (t >= thr) { J[r]"),
     "newton_identity": ("double v = kappa * s + (i == l ? 1.0 : 0.0);", "double v = kappa * s;"),
-    "chol_sign": ("for (int64_t k = 0; k < j; ++k) s -= V[i * m + k] * V[j * m + k];",
-                  "for (int64_t k = 0; k < j; ++k) s += V[i * m + k] * V[j * m + k];"),
+    "chol_sign": ("for (int64_t k = 0; k < j; ++k) t -= V[i * m + k] * V[j * m + k];",
+                  "for (int64_t k = 0; k < j; ++k) t += V[i * m + k] * V[j * m + k];"),
     "ls_second_order": ("ei = 0.5 * s * s * kappa * wd[i] * wd[i];", "ei = 0.5 * s * kappa * wd[i] * wd[i];"),
     "eta_sign": ("double p = orc_prox_sp(x[j] - g[j], 1.0, l1, l2);", "double p = orc_prox_sp(x[j] + g[j], 1.0, l1, l2);"),
     "dual_sign": ("return -hs - ps;", "return -hs + ps;"),
@@ -61,7 +61,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
     mut.write_text(src.replace(old, new))
     (tmp_path / "oracle_en.h").write_text(open(os.path.join(ROOT, "oracle", "oracle_en.h")).read())
     lib = tmp_path / "liboracle_mut.so"
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                            "-I", str(tmp_path), "-o", str(lib), str(mut), "-lm"])
     env = dict(os.environ, SSNAL_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",

@@ -612,3 +612,33 @@ def test_newton_cg_solve_reaches_cd_minimiser(orc):
     _, info_ch = _solve(orc, A, b, l1, l2)
     assert info_ch["cg_iters"] == 0
     assert info["newton_iters"] <= 3 * info_ch["newton_iters"]
+
+
+# ---------------------------------------------------------------- host threads
+
+def test_thread_count_does_not_change_results(orc):
+    """The oracle's threaded loops (A^T v, A x, both Newton matrices, the
+    Cholesky columns) and a whole solve give the same bits with 1 and 4
+    threads; the Cholesky also matches LAPACK past the threading cut-off."""
+    g = np.random.default_rng(4242)
+    m, n = 300, 700
+    AT = g.standard_normal((n, m)) / np.sqrt(m)
+    v = g.standard_normal(m)
+    x = np.where(g.random(n) < 0.1, g.standard_normal(n), 0.0)
+    J = np.sort(g.choice(n, 350, replace=False)).astype(np.int32)
+    b = AT.T @ x + 0.1 * g.standard_normal(m)
+    l1 = 0.3 * np.max(np.abs(AT @ b))
+    saved = orc.get_threads()
+    out = []
+    try:
+        for k in (1, 4):
+            orc.set_threads(k)
+            V = orc.newton_matrix(AT, J, 0.7)
+            xs, info, _ = orc.en_solve(AT, b, l1, 0.2, tol=1e-10)
+            out.append((orc.gemv_t(AT, v), orc.gemv_n(AT, x), V, orc.smw_matrix(AT, J[:200], 0.7),
+                        orc.cholesky(V), xs, info["primal_obj"]))
+    finally:
+        orc.set_threads(saved)
+    for a, c in zip(*out):
+        assert np.array_equal(np.asarray(a), np.asarray(c))
+    assert np.allclose(out[0][4], np.linalg.cholesky(out[0][2]), rtol=1e-12, atol=1e-12)
