@@ -234,6 +234,83 @@ def cg_bench(reps=2, r_fixed=16000):
     return out
 
 
+def c1_bench(single_reps=200, batches=(1, 64, 1024)):
+    """The single-solve workload (m=100, n=2000 Gaussian, FP64, tol 1e-10):
+    back-to-back single solves of one problem on one stream, then batches of
+    B independent problems (B seeds) through ssnal_en_solve_batch on its
+    default 8 concurrent workers.  Latency-bound: the design (1.6 MB) lives in
+    the caches, so solves/s is the figure, not bandwidth."""
+    import torch
+
+    import datagen
+    from paper_2006_03970_amd import binding
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+
+    ctx = binding.Context(0)
+    stream = torch.cuda.current_stream()
+    nmax = max(batches)
+    t0 = time.time()
+    probs = []
+    for s in range(nmax):
+        p = datagen.make_problem("c1", seed=1000 + s)
+        A, b = design_to_device(p.AT, "f64"), vec_to_device(p.b)
+        probs.append(dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol,
+                          x_out=torch.empty(p.n, dtype=torch.float64, device=A.device)))
+    torch.cuda.synchronize()
+    print(f"[bench] c1: {nmax} problems generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    q = probs[0]
+    for _ in range(5):
+        binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                               x_out=q["x_out"], stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(single_reps):
+        _, info = binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                                         x_out=q["x_out"], stream=stream)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / single_reps
+    out = {"workload": "Gaussian elastic net, m=100, n=2000, k=10, snr=5, alpha=0.5, c_lambda=0.5, "
+                       "FP64, tol 1e-10",
+           "single": {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "status": info["status"],
+                      "iterations": [info["outer_iters"], info["newton_iters"]], "eta": info["kkt_rel"]},
+           "batched": {}}
+    binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream)  # creates the workers
+    for B in batches:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos, rc = binding.ssnal_en_solve_batch(ctx, probs[:B], stream=stream)
+        el = time.perf_counter() - t
+        out["batched"][str(B)] = {"solves_per_s": B / el, "ms": el * 1e3, "worst_status": rc,
+                                  "max_eta": max(i["kkt_rel"] for i in infos)}
+        print(f"[bench] c1 batch {B}: {B / el:.0f} solves/s", file=sys.stderr, flush=True)
+    out["batched"]["workers"] = 8
+    del probs
+    torch.cuda.empty_cache()
+    return out
+
+
+FP64_PEAK_TFS = 78.6  # MI355X dense FP64 (vector and matrix), published
+
+
+def chol_roofline(infos, label):
+    """FP64 Cholesky factor + solve of the Newton systems inside the timed
+    solves that carried events: sum of N^3/3 over the factorisations divided
+    by their summed duration, against the FP64 peak."""
+    tim = [i for i in infos if i["chol_calls"] > 0]
+    calls = sum(i["chol_calls"] for i in tim)
+    ms = sum(i["chol_ms"] for i in tim)
+    gflop = sum(i["chol_gflop"] for i in tim)
+    if not calls or ms <= 0:
+        return None
+    tfs = gflop / ms  # GFLOP per ms = TFLOP/s
+    return {"bound": "fp64", "kernel": f"Cholesky factor + forward/backward solve (k_chol_step x ceil(N/64) "
+                                       f"+ k_chol_back) of the Newton systems, {label}",
+            "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": tfs / FP64_PEAK_TFS,
+            "calls_per_solve": calls / len(tim), "us_per_call": ms / calls * 1e3,
+            "mean_N3_over_3_mflop": gflop / calls * 1e3, "share_of_solve": ms / sum(
+                i["solve_ms"] for i in tim)}
+
+
 SYRK_M, SYRK_R = 4096, 8192  # the largest dense Newton matrix: m x m from r columns
 MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA, published
 
@@ -279,14 +356,75 @@ def syrk_bench(reps=5, launches=0):
     return out
 
 
-def serving_bench(nreq, nmax, slots, seed=7):
-    """p50/p99 latency and solves/s of the serving loop over a request stream."""
+def _pinned_pool(sizes, chunk=4 << 30):
+    """Pinned host buffers for tensors of the given byte sizes, carved out of
+    4 GiB pinned chunks (one allocation per chunk; offsets 256-byte aligned).
+    Returns a list of uint8 tensors."""
+    import torch
+    out, cur, off = [], None, 0
+    for sz in sizes:
+        need = (sz + 255) // 256 * 256
+        if cur is None or off + need > cur.numel():
+            cur = torch.empty(max(chunk, need), dtype=torch.uint8, pin_memory=True)
+            off = 0
+        out.append(cur[off:off + sz])
+        off += need
+    return out
+
+
+def _latency_stats(lat, alone):
+    import numpy as np
+    slow = lat / alone
+    return {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_latency_ms": float(lat.mean() * 1e3),
+            "p50_slowdown": float(np.percentile(slow, 50)), "p99_slowdown": float(np.percentile(slow, 99))}
+
+
+def _open_loop(srv, probs, rate, seed, host):
+    """Seeded Poisson arrivals at `rate`; latency = scheduled arrival ->
+    completion (for host-resident requests it includes the upload)."""
+    import numpy as np
+    nreq = len(probs)
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=nreq)
+    arrive = np.cumsum(gaps) - gaps[0]
+    lat = np.zeros(nreq)
+    upload = np.zeros(nreq)
+    bad = []
+    pending = {}
+    start = time.perf_counter()
+    nxt = 0
+    while nxt < nreq or pending:
+        now = time.perf_counter() - start
+        while nxt < nreq and arrive[nxt] <= now:
+            q = probs[nxt]
+            A, b, x = (q["Ah"], q["bh"], q["xh"]) if host else (q["A"], q["b"], q["x"])
+            pending[srv.submit(A, b, q["l1"], q["l2"], 1e-6, x)] = nxt
+            nxt += 1
+        for tk in list(pending):
+            info = srv.poll(tk)
+            if info is not None:
+                k = pending.pop(tk)
+                lat[k] = time.perf_counter() - start - arrive[k]
+                upload[k] = info["upload_ms"]
+                if info["status"] != 0:
+                    bad.append(info["status"])
+        time.sleep(5e-5)
+    return lat, upload, nreq / (time.perf_counter() - start), bad
+
+
+def serving_bench(nreq, nmax, slots, seed=7, host_requests=128, fp64_subset=128):
+    """The serving stream: p50/p99 latency and solves/s of the library's
+    serving loop with the designs resident in HBM; then its first
+    host_requests requests with their designs in pinned host memory (uploaded
+    on admission, latency including the upload), and an FP64 figure on the
+    first fp64_subset requests with their stored values upcast exactly.
+    Returns (report, state kept for the oracle check of the served results)."""
     import numpy as np
     import torch
 
     import datagen
     from paper_2006_03970_amd import binding
-    from paper_2006_03970_amd.device import design_to_device, vec_to_device
 
     reqs = datagen.serving_requests(nreq, seed=seed, n_range=(10_000, int(nmax)))
     t0 = time.time()
@@ -296,18 +434,23 @@ def serving_bench(nreq, nmax, slots, seed=7):
         p = datagen.make_problem_device(q, seed=q["seed"], store=q["store"], device=dev)
         x = torch.empty(p["n"], dtype=torch.float64, device=dev)
         probs.append(dict(A=p["AT"], b=p["b"], l1=p["lam1"], l2=p["lam2"], x=x, m=p["m"], n=p["n"],
-                          store=p["store"]))
+                          store=p["store"], design=q["design"]))
     torch.cuda.synchronize()
-    print(f"[bench] serving: generated and uploaded {nreq} requests in {time.time() - t0:.1f}s",
+    print(f"[bench] serving: generated {nreq} requests on the device in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     srv = binding.Server(0, hbm_budget=64 << 30, max_slots=slots)
+    out = {"requests": nreq, "slots": slots, "n_range": [10_000, int(nmax)], "m_range": [100, 2000],
+           "mean_m": float(np.mean([q["m"] for q in probs])), "mean_n": float(np.mean([q["n"] for q in probs])),
+           "stores": {s: sum(1 for q in probs if q["store"] == s) for s in ("f32", "bf16")},
+           "admission": "smallest estimated work first among the requests whose footprint fits; "
+                        "a request passed over 4 x slots times goes next"}
     try:
-        # alone: one request at a time (also the warm-up)
-        alone = []
-        for q in probs[: min(8, nreq)]:
+        # every request alone (its service time: the slowdown denominators)
+        alone = np.zeros(nreq)
+        for i, q in enumerate(probs):
             t = time.perf_counter()
             info = srv.wait(srv.submit(q["A"], q["b"], q["l1"], q["l2"], 1e-6, q["x"]))
-            alone.append(time.perf_counter() - t)
+            alone[i] = time.perf_counter() - t
             assert info["status"] == 0, info
         # closed loop: everything submitted at once
         t = time.perf_counter()
@@ -315,46 +458,207 @@ def serving_bench(nreq, nmax, slots, seed=7):
         infos = [srv.wait(tk) for tk in tickets]
         sat = nreq / (time.perf_counter() - t)
         bad = [i["status"] for i in infos if i["status"] != 0]
-        # open loop: Poisson arrivals at 0.8x the saturated rate
-        rate = 0.8 * sat
-        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=nreq)
-        arrive = np.cumsum(gaps) - gaps[0]
-        lat = np.zeros(nreq)
-        pending = {}
-        start = time.perf_counter()
-        nxt = 0
-        while nxt < nreq or pending:
-            now = time.perf_counter() - start
-            while nxt < nreq and arrive[nxt] <= now:
-                q = probs[nxt]
-                pending[srv.submit(q["A"], q["b"], q["l1"], q["l2"], 1e-6, q["x"])] = nxt
-                nxt += 1
-            for tk in list(pending):
-                info = srv.poll(tk)
-                if info is not None:
-                    k = pending.pop(tk)
-                    lat[k] = time.perf_counter() - start - arrive[k]
-                    if info["status"] != 0:
-                        bad.append(info["status"])
-            time.sleep(5e-5)
-        span = time.perf_counter() - start
+        eta_max = max(i["kkt_rel"] for i in infos)
+        lat, _, rate_done, bad2 = _open_loop(srv, probs, 0.8 * sat, seed, host=False)
+        out["device_resident"] = {
+            "saturated_solves_per_s": sat, "poisson_rate_per_s": 0.8 * sat, "solves_per_s": rate_done,
+            **_latency_stats(lat, alone), "alone_latency_ms_mean": float(alone.mean() * 1e3),
+            "alone_latency_ms_p50": float(np.percentile(alone, 50) * 1e3),
+            "alone_latency_ms_p99": float(np.percentile(alone, 99) * 1e3),
+            "max_eta_gpu": eta_max, "nonzero_status": bad + bad2}
+        print(f"[bench] serving (HBM-resident): {sat:.0f}/s saturated, p50 "
+              f"{out['device_resident']['p50_latency_ms']:.1f} ms p99 {out['device_resident']['p99_latency_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+        # served results, kept for the oracle check (the stored bytes go to host memory below)
+        xs = [q["x"].cpu() for q in probs]
+        if host_requests > 0:
+            hp = probs[:host_requests]
+            sizes = [q["A"].numel() * q["A"].element_size() for q in hp]
+            bufs = _pinned_pool(sizes)
+            for q, buf in zip(hp, bufs):
+                q["Ah"] = buf.view(q["A"].dtype).view(q["A"].shape)
+                q["Ah"].copy_(q["A"])
+                q["bh"] = q["b"].cpu().pin_memory()
+                q["xh"] = torch.empty(q["n"], dtype=torch.float64).pin_memory()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            tickets = [srv.submit(q["Ah"], q["bh"], q["l1"], q["l2"], 1e-6, q["xh"]) for q in hp]
+            infos = [srv.wait(tk) for tk in tickets]
+            sat_h = len(hp) / (time.perf_counter() - t)
+            bad = [i["status"] for i in infos if i["status"] != 0]
+            lat, up, rate_done, bad2 = _open_loop(srv, hp, 0.8 * sat_h, seed + 1, host=True)
+            same = all(bool(torch.equal(q["xh"], x)) for q, x in zip(hp, xs))
+            gb = sum(sizes) / 1e9
+            out["host_resident"] = {
+                "requests": len(hp),
+                "saturated_solves_per_s": sat_h, "poisson_rate_per_s": 0.8 * sat_h, "solves_per_s": rate_done,
+                **_latency_stats(lat, alone[:len(hp)]),
+                "upload_ms_mean": float(up.mean()), "upload_ms_p99": float(np.percentile(up, 99)),
+                "upload_gbs": gb / (up.sum() / 1e3), "design_gb_total": gb,
+                "x_bitwise_equal_to_hbm_resident": same, "nonzero_status": bad + bad2,
+                "note": "latency from scheduled arrival to completion includes the upload of A, b "
+                        "(pinned host memory) on the slot's stream; slowdown is against the request "
+                        "alone with its design already in HBM"}
+            print(f"[bench] serving (host-resident): {sat_h:.0f}/s saturated, upload "
+                  f"{out['host_resident']['upload_gbs']:.1f} GB/s", file=sys.stderr, flush=True)
+        # FP64 on the first fp64_subset requests (stored values upcast exactly) beside the
+        # mixed solves of the same requests
+        sub = probs[:fp64_subset]
+        for q in sub:
+            q["A64"] = q["A"].to(torch.float64)
+            q["Am"] = q["A"]
+        torch.cuda.synchronize()
+        res = {}
+        for key in ("Am", "A64"):
+            al = []
+            for q in sub:
+                t = time.perf_counter()
+                info = srv.wait(srv.submit(q[key], q["b"], q["l1"], q["l2"], 1e-6, q["x"]))
+                al.append(time.perf_counter() - t)
+                assert info["status"] == 0, info
+            t = time.perf_counter()
+            tk = [srv.submit(q[key], q["b"], q["l1"], q["l2"], 1e-6, q["x"]) for q in sub]
+            inf = [srv.wait(k) for k in tk]
+            res[key] = {"saturated_solves_per_s": len(sub) / (time.perf_counter() - t),
+                        "alone_latency_ms_mean": float(np.mean(al) * 1e3),
+                        "max_eta_gpu": max(i["kkt_rel"] for i in inf)}
+        out["fp64_vs_mixed_subset"] = {"requests": len(sub), "mixed": res["Am"], "fp64": res["A64"],
+                                       "mixed_over_fp64": res["Am"]["saturated_solves_per_s"] /
+                                       res["A64"]["saturated_solves_per_s"]}
+        for q in sub:
+            q.pop("A64")
+            q.pop("Am")
+        torch.cuda.empty_cache()
     finally:
         srv.close()
-    ms = np.array([q["m"] for q in probs])
-    ns = np.array([q["n"] for q in probs])
-    return {
-        "requests": nreq, "slots": slots, "n_range": [10_000, int(nmax)], "m_range": [100, 2000],
-        "mean_m": float(ms.mean()), "mean_n": float(ns.mean()),
-        "stores": {s: sum(1 for q in probs if q["store"] == s) for s in ("f32", "bf16")},
-        "saturated_solves_per_s": sat,
-        "poisson_rate_per_s": rate,
-        "solves_per_s": nreq / span,
-        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-        "mean_latency_ms": float(lat.mean() * 1e3),
-        "alone_latency_ms_mean": float(np.mean(alone) * 1e3),
-        "nonzero_status": bad,
-    }
+    state = {"probs": probs, "xs": xs}
+    return out, state
+
+
+def served_vs_oracle(state, sample, seed=11):
+    """Oracle check of served results (part of the CPU-baseline leg): for a
+    seeded sample of the served requests that includes m > 1000, n > 3e5 and
+    both storage types, the FP64 oracle evaluates on the stored design (the
+    exact bytes the GPU read, dequantised) the KKT residual eta of the served
+    x, its objective F and the dual objective D at A x - b; F - D bounds the
+    objective error (weak duality, lambda2 > 0)."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    probs, xs = state["probs"], state["xs"]
+    g = np.random.default_rng(seed)
+    idx = list(g.choice(len(probs), size=min(sample, len(probs)), replace=False))
+    need = [lambda q: q["m"] > 1000, lambda q: q["n"] > 300_000, lambda q: q["store"] == "f32",
+            lambda q: q["store"] == "bf16", lambda q: q["m"] > 1000 and q["n"] > 300_000]
+    for cond in need:
+        if not any(cond(probs[i]) for i in idx):
+            cand = [i for i in range(len(probs)) if cond(probs[i]) and i not in idx]
+            if cand:
+                idx.append(cand[0])
+    rows = []
+    t0 = time.perf_counter()
+    for i in idx:
+        q = probs[i]
+        AT64 = q["A"].cpu().to(torch.float64).numpy()
+        b = q["b"].cpu().numpy()
+        x = xs[i].numpy()
+        eta = oracle.eta(AT64, b, x, q["l1"], q["l2"])
+        F = oracle.primal_obj(AT64, b, x, q["l1"], q["l2"])
+        D = oracle.dual_obj(AT64, b, oracle.gemv_n(AT64, x) - b, q["l1"], q["l2"])
+        rows.append(dict(i=int(i), m=q["m"], n=q["n"], store=q["store"], eta=eta, rel_gap=(F - D) / abs(D)))
+        del AT64
+    return {"sample": len(rows), "seconds": time.perf_counter() - t0,
+            "max_eta_oracle": max(r["eta"] for r in rows),
+            "max_rel_objective_error_bound": max(r["rel_gap"] for r in rows),
+            "all_eta_le_tol": all(r["eta"] <= 1e-6 * (1 + 1e-9) for r in rows),
+            "largest": max(rows, key=lambda r: r["m"] * r["n"]),
+            "covers": {"m_gt_1000": any(r["m"] > 1000 for r in rows),
+                       "n_gt_3e5": any(r["n"] > 300_000 for r in rows),
+                       "f32": any(r["store"] == "f32" for r in rows),
+                       "bf16": any(r["store"] == "bf16" for r in rows)}}
+
+
+def _host_threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(n, int(omp))) if omp and omp.isdigit() else n
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_leg(p64, AT32, bits_bf, xs_gpu, serving_state, serving_sample):
+    """The FP64 oracle on the host (the CPU baseline), then the oracle's report
+    on the GPU's results: per C2 solve, the relative objective error against a
+    tight oracle solve (tol 1e-10) on the stored and on the original design,
+    the support difference, eta on the stored design and eta on the original;
+    and the served-request check."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+    out = {}
+    runs = {}
+    for threads, budget, cap in ((1, 10.0, 12), (_host_threads(), 10.0, 64)):
+        oracle.set_threads(threads)
+        nsolve = 0
+        t = time.perf_counter()
+        while True:
+            oracle.en_solve(p64.AT, p64.b, p64.lam1, p64.lam2, tol=p64.tol)
+            nsolve += 1
+            if time.perf_counter() - t > budget or nsolve >= cap:
+                break
+        runs[threads] = (nsolve, time.perf_counter() - t)
+        print(f"[bench] oracle on {threads} thread(s): {nsolve / runs[threads][1]:.2f} solves/s",
+              file=sys.stderr, flush=True)
+    nt = _host_threads()
+    n1, e1 = runs[1]
+    nn, en = runs[nt]
+    out["cpu_baseline"] = {
+        "value": nn / en, "unit": "solves/s", "cores": nt, "kind": "oracle",
+        "sample": f"{nn} complete FP64 oracle solves of the same problem (tol 1e-6) on {nt} host threads "
+                  f"(OpenMP over the A^T y, A x and Newton-matrix loops; every sum in its serial order)",
+        "single_thread": {"value": n1 / e1, "cores": 1, "sample": f"{n1} solves on one thread"},
+        "cpu_model": _cpu_model()}
+    # per-solve parity of the C2 solves
+    orig = p64.AT
+    stored = {"mixed_f32": AT32.astype(np.float64), "fp64": orig,
+              "mixed_bf16": datagen.bf16_bits_to_f64(bits_bf)}
+    x_orig, i_orig, _ = oracle.en_solve(orig, p64.b, p64.lam1, p64.lam2, tol=1e-10)
+    rep = {}
+    for key, x in xs_gpu.items():
+        A_s = stored[key]
+        if A_s is orig:
+            x_s, i_s = x_orig, i_orig
+        else:
+            x_s, i_s, _ = oracle.en_solve(A_s, p64.b, p64.lam1, p64.lam2, tol=1e-10)
+        F_s = oracle.primal_obj(A_s, p64.b, x, p64.lam1, p64.lam2)
+        F_o = oracle.primal_obj(orig, p64.b, x, p64.lam1, p64.lam2)
+        diff = (x != 0) ^ (x_s != 0)
+        rep[key] = {"eta_stored": oracle.eta(A_s, p64.b, x, p64.lam1, p64.lam2),
+                    "eta_orig": oracle.eta(orig, p64.b, x, p64.lam1, p64.lam2),
+                    "rel_obj_err_stored": abs(F_s - i_s["primal_obj"]) / abs(i_s["primal_obj"]),
+                    "rel_obj_err_orig": abs(F_o - i_orig["primal_obj"]) / abs(i_orig["primal_obj"]),
+                    "support_diff": int(diff.sum()),
+                    "support_diff_above_1e-8": int(np.sum(diff & ((np.abs(x) > 1e-8) | (np.abs(x_s) > 1e-8)))),
+                    "nnz": int(np.count_nonzero(x)), "nnz_oracle": int(np.count_nonzero(x_s))}
+    out["parity_vs_oracle"] = rep
+    if serving_state is not None:
+        out["served_vs_oracle"] = served_vs_oracle(serving_state, serving_sample)
+    oracle.set_threads(1)
+    return out
 
 
 def main():
@@ -368,7 +672,12 @@ def main():
     ap.add_argument("--no-path", action="store_true", help="skip the path + model selection section")
     ap.add_argument("--no-cg", action="store_true", help="skip the Newton-CG (m=20000) section")
     ap.add_argument("--cg-only", action="store_true", help="run only the Newton-CG section")
+    ap.add_argument("--no-c1", action="store_true", help="skip the m=100, n=2000 single/batched section")
     ap.add_argument("--serving", type=int, default=512, help="requests in the serving stream (0 = off)")
+    ap.add_argument("--serving-host", type=int, default=128,
+                    help="requests of the stream (its first ones) also served from pinned host memory (0 = off)")
+    ap.add_argument("--serving-oracle-sample", type=int, default=64,
+                    help="served requests checked by the oracle in the CPU-baseline leg")
     ap.add_argument("--serving-nmax", type=float, default=5e5)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--profile-gemv", type=int, default=0)
@@ -423,7 +732,8 @@ def main():
                 print(f"[bench] copy launch {k}", file=sys.stderr, flush=True)
         return
     A64 = design_to_device(p64.AT, "f64")
-    Abf = design_to_device(datagen.f32_to_bf16_bits(AT32), "bf16")
+    bits_bf = datagen.f32_to_bf16_bits(AT32)
+    Abf = design_to_device(bits_bf, "bf16")
 
     TIME_EVERY = 4  # solves of the timed region whose A^T d launches carry HIP events
 
@@ -453,7 +763,7 @@ def main():
 
     el32, inf32, x32 = timed(A32, "mixed f32")
     el64, inf64, x64 = timed(A64, "fp64")
-    elbf, infbf, _ = timed(Abf, "mixed bf16")
+    elbf, infbf, xbf = timed(Abf, "mixed bf16")
 
     def atd_stats(infos, s_a):
         """Average duration of the Newton A^T d launches (HIP events, in the
@@ -513,6 +823,14 @@ def main():
         },
     }
 
+    out["roofline_chol"] = chol_roofline(inf32, "FP32-stored design (FP64 factor)")
+    out["roofline_chol_fp64"] = chol_roofline(inf64, "FP64 design")
+    xs_gpu = {"mixed_f32": x32.cpu().numpy(), "fp64": x64.cpu().numpy(), "mixed_bf16": xbf.cpu().numpy()}
+    del A64, Abf
+    torch.cuda.empty_cache()
+
+    if not args.no_c1:
+        out["small_single_solve"] = c1_bench()
     if not args.no_c3:
         out["large_single_solve"] = large_bench()
     if not args.no_path:
@@ -521,26 +839,13 @@ def main():
         out["newton_cg"] = cg_bench()
     if not args.no_syrk:
         out["newton_matrix_syrk"] = syrk_bench()
+    serving_state = None
     if args.serving > 0:
-        out["serving"] = serving_bench(args.serving, args.serving_nmax, args.serving_slots)
+        out["serving"], serving_state = serving_bench(args.serving, args.serving_nmax, args.serving_slots,
+                                                      host_requests=args.serving_host)
 
     if not args.no_cpu_baseline:
-        import oracle
-        if not os.path.exists(oracle.LIB_PATH):
-            oracle.build()
-        nsolve = 0
-        t = time.perf_counter()
-        while True:
-            oracle.en_solve(p64.AT, p64.b, p64.lam1, p64.lam2, tol=p64.tol)
-            nsolve += 1
-            if time.perf_counter() - t > 10.0 or nsolve >= 12:
-                break
-        el = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": nsolve / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsolve} complete FP64 oracle solves of the same problem (tol 1e-6), "
-                      "single thread",
-        }
+        out.update(cpu_baseline_leg(p64, AT32, bits_bf, xs_gpu, serving_state, args.serving_oracle_sample))
     print(json.dumps(out), flush=True)
 
 

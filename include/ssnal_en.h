@@ -84,6 +84,9 @@ typedef struct {
   int32_t cg_maxit;      /* <= 0: 500 conjugate-gradient iterations per Newton step */
   double cg_eta;         /* <= 0: 0.1; < 1; CG stops at ||V d + g|| <= min(cg_eta, kkt1^cg_tau) ||g|| */
   double cg_tau;         /* <= 0: 0.5 */
+  int32_t workers;       /* ssnal_en_solve_batch: <= 0: 8 concurrent workers (own context and
+                            stream each, kept by the context); 1 = every problem in turn on
+                            the caller's stream */
 } ssnal_en_opts;
 
 typedef struct {
@@ -107,6 +110,15 @@ typedef struct {
   int32_t atd_launches;  /* with opts.timing: launches of the Newton pass w_d = A^T d ... */
   double atd_ms;         /* ... and their summed durations (HIP events on the solve's stream) */
   int32_t cg_iters;      /* conjugate-gradient iterations over all Newton steps */
+  double sigma0;         /* the initial penalty the solve used (a warm-started path point
+                            that continues from this one passes min(sigma_final, cap)) */
+  double queue_ms;       /* serving: submission -> admission to a slot (host clock) */
+  double upload_ms;      /* serving, host-resident request: the upload of A, b and x0
+                            (HIP events on the slot's stream); 0 otherwise */
+  int32_t chol_calls;    /* with opts.timing: Cholesky factor + solve calls of the Newton
+                            directions ... */
+  double chol_ms;        /* ... their summed durations (HIP events on the solve's stream) ... */
+  double chol_gflop;     /* ... and their summed N^3/3 flops, in GFLOP */
 } ssnal_en_info;
 
 /* Fill *opts with the defaults listed above. */
@@ -203,6 +215,10 @@ int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
                 const double* c_lambda, int nlam, double tol, int slots, hipStream_t stream,
                 const ssnal_en_opts* opts, double* err_out, ssnal_en_info* infos);
 
+/* where the arrays of a problem live */
+#define SSNAL_ON_DEVICE 0
+#define SSNAL_ON_HOST 1
+
 /* One problem of a batch or of the serving loop (fields as in ssnal_en_solve). */
 typedef struct {
   const void* A;
@@ -213,6 +229,17 @@ typedef struct {
   const double* x0;  /* nullable */
   double tol;
   double* x_out;
+  double sigma0;       /* > 0: this problem's initial penalty, overriding opts->sigma0 (a
+                          warm-started path point passes the sigma its predecessor ended
+                          with, as ssnal_en_path does); <= 0: opts / default */
+  int32_t location;    /* SSNAL_ON_DEVICE: A, b, x0, x_out are device pointers.
+                          SSNAL_ON_HOST (serving only): they are host memory (pinned for
+                          asynchronous uploads); the server uploads A, b and x0 into
+                          device buffers of the slot on admission and copies x back */
+  hipEvent_t ready;    /* nullable, device-resident problems: the solve's stream waits for
+                          this event before reading A, b and x0 (record it on the stream
+                          that wrote them); without it the caller must have completed
+                          those writes before submitting */
 } ssnal_en_problem;
 
 /*
@@ -247,23 +274,39 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
                           const double* b, int64_t m, int64_t n, double lambda2, const double* x,
                           hipStream_t stream, double* beta_out, ssnal_en_select* out);
 
-/* Independent solves, one after the other on `stream` with the context's
- * workspace (k-fold or grid-search style).  infos: HOST, nullable, count
- * entries.  Returns the most severe status; an error stops the batch. */
+/* Independent solves (k-fold or grid-search style) of device-resident
+ * problems, on opts->workers concurrent workers (default 8; each a context and
+ * stream of its own, created on first use and kept by ctx) that start after
+ * the caller's earlier work on `stream` and each problem's `ready` event; with
+ * opts->workers = 1, one after the other on `stream` with ctx's workspace.
+ * Every solve's result is the same bits under any worker count.  Returns
+ * after every solve has completed.  infos: HOST, nullable, count entries.
+ * Returns the most severe status; an error stops handing out problems. */
 int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int count,
                          const ssnal_en_opts* opts, hipStream_t stream, ssnal_en_info* infos);
 
 /*
- * Serving loop: a slot table of up to max_slots concurrent solves on one
- * device.  Each slot owns a context and a HIP stream (default priority) and
- * is driven by its own host thread, so the latency-bound phases of different
- * requests overlap on the GPU.  A request is admitted when its workspace
- * footprint (the context allocation for its (m, n); A, b and x stay with the
- * caller) fits in hbm_budget bytes next to the slots in use; otherwise it
- * waits, first come first served.  A request's reductions have a fixed tiling
- * that depends only on its (m, n), so its result is bitwise the same alone
- * or in the mix.  Pointers in a submitted problem must stay valid until its
- * ticket completes.
+ * Serving loop (continuous batching of independent solves): a slot table of
+ * up to max_slots concurrent solves on one device.  Each slot owns a context
+ * and a HIP stream (default priority) and is driven by its own host thread,
+ * so the latency-bound phases of different requests overlap on the GPU.
+ *
+ * Admission by HBM footprint: a request is admitted to an idle slot when its
+ * footprint, ssnal_srv_footprint (the context workspace for its (m, n), plus
+ * for a host-resident request the device copies of A, b and x), fits in
+ * hbm_budget bytes next to what the other slots hold.  Among the queued
+ * requests that fit, the one with the smallest estimated work (its passes
+ * over A and its Newton factorisations) goes first, so small requests do not
+ * wait behind multi-gigabyte ones; a request that has been passed over
+ * 4*max_slots times is admitted next, before any other (no starvation).  When
+ * nothing runs and the oldest request does not fit, idle slots release their
+ * buffers.  A host-resident request is uploaded on its slot's stream on
+ * admission (info->upload_ms) and its x copied back before completion.
+ *
+ * A request's reductions have a fixed tiling that depends only on its (m, n),
+ * so its result is bitwise the same alone or in the mix.  Pointers in a
+ * submitted problem (and its ready event) must stay valid until its ticket
+ * completes.
  */
 typedef struct ssnal_srv ssnal_srv;
 int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_en_opts* opts,
@@ -277,8 +320,12 @@ int ssnal_srv_poll(ssnal_srv* srv, uint64_t ticket, ssnal_en_info* info);
 int ssnal_srv_wait(ssnal_srv* srv, uint64_t ticket, ssnal_en_info* info);
 /* Finishes every admitted and queued request, then frees the slots. */
 void ssnal_srv_destroy(ssnal_srv* srv);
-/* Workspace bytes a context holds for an (m, n) problem (the admission footprint). */
+/* Workspace bytes a context holds for an (m, n) problem. */
 size_t ssnal_workspace_bytes(int64_t m, int64_t n);
+/* Device bytes a served problem occupies while it runs (the admission
+ * footprint): ssnal_workspace_bytes(m, n), plus m*n*sizeof(elem) + (m + n)*8
+ * for a host-resident problem.  0 for an invalid problem. */
+size_t ssnal_srv_footprint(const ssnal_en_problem* problem);
 
 /* ---------------------------------------------------------------------
  * Building blocks of the solve, exported for verification and benchmarking.

@@ -31,7 +31,7 @@ class Opts(C.Structure):
                 ("max_inner", C.c_int32), ("max_backtrack", C.c_int32), ("no_refine", C.c_int32),
                 ("no_smw", C.c_int32), ("timing", C.c_int32), ("trace_cap", C.c_int32),
                 ("trace", C.POINTER(C.c_double)), ("newton_cg", C.c_int32), ("cg_maxit", C.c_int32),
-                ("cg_eta", C.c_double), ("cg_tau", C.c_double)]
+                ("cg_eta", C.c_double), ("cg_tau", C.c_double), ("workers", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -41,7 +41,9 @@ class Info(C.Structure):
                 ("dual_obj", C.c_double), ("rel_gap", C.c_double), ("sigma_final", C.c_double),
                 ("gemv_calls", C.c_int32), ("syncs", C.c_int32), ("gemv_ms", C.c_double),
                 ("solve_ms", C.c_double), ("atd_launches", C.c_int32), ("atd_ms", C.c_double),
-                ("cg_iters", C.c_int32)]
+                ("cg_iters", C.c_int32), ("sigma0", C.c_double), ("queue_ms", C.c_double),
+                ("upload_ms", C.c_double), ("chol_calls", C.c_int32), ("chol_ms", C.c_double),
+                ("chol_gflop", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -50,7 +52,11 @@ class Info(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("A", C.c_void_p), ("a_dtype", C.c_int), ("lda", C.c_int64), ("m", C.c_int64),
                 ("n", C.c_int64), ("b", C.c_void_p), ("lambda1", C.c_double), ("lambda2", C.c_double),
-                ("x0", C.c_void_p), ("tol", C.c_double), ("x_out", C.c_void_p)]
+                ("x0", C.c_void_p), ("tol", C.c_double), ("x_out", C.c_void_p),
+                ("sigma0", C.c_double), ("location", C.c_int32), ("ready", C.c_void_p)]
+
+
+SSNAL_ON_DEVICE, SSNAL_ON_HOST = 0, 1
 
 
 _lib = None
@@ -101,6 +107,8 @@ def lib():
         L.ssnal_srv_destroy.argtypes = [_vp]
         L.ssnal_workspace_bytes.argtypes = [_i64, _i64]
         L.ssnal_workspace_bytes.restype = C.c_size_t
+        L.ssnal_srv_footprint.argtypes = [C.POINTER(Problem)]
+        L.ssnal_srv_footprint.restype = C.c_size_t
         for name in ("ssnal_en_path", "ssnal_en_solve_batch", "ssnal_srv_create", "ssnal_srv_submit",
                      "ssnal_srv_poll", "ssnal_srv_wait"):
             getattr(L, name).restype = _i
@@ -363,20 +371,39 @@ def ssnal_en_path(ctx, A, b, alpha, c_lambda, tol=1e-6, X_out=None, m=None, max_
     return X_out, [infos[k].as_dict() for k in range(nlam)], rc
 
 
-def _problem(A, b, lambda1, lambda2, tol, x_out, x0=None, m=None):
+def _problem(A, b, lambda1, lambda2, tol, x_out, x0=None, m=None, sigma0=0.0, ready=None):
+    """ssnal_en_problem of tensors that all live on the device, or all in host
+    memory (a served host-resident request)."""
     pA, dt, lda, m, n = _design(A, m)
+    on_host = A.device.type == "cpu"
+    for t in (b, x_out, x0):
+        assert t is None or (t.device.type == "cpu") == on_host, "A, b, x0, x_out: all host or all device"
     return Problem(pA, dt, lda, m, n, _ptr(b), float(lambda1), float(lambda2), _ptr(x0), float(tol),
-                   _ptr(x_out))
+                   _ptr(x_out), float(sigma0), SSNAL_ON_HOST if on_host else SSNAL_ON_DEVICE,
+                   None if ready is None else _vp(ready.cuda_event))
 
 
-def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None):
-    """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0].
-    Returns (list of info dicts, worst status)."""
+def srv_footprint(A, m=None):
+    """Device bytes a served request with this design occupies (admission footprint)."""
+    import torch
+    pA, dt, lda, m, n = _design(A, m)
+    on_host = A.device.type == "cpu"
+    p = Problem(pA, dt, lda, m, n, None, 0.0, 0.0, None, 1.0, None, 0.0,
+                SSNAL_ON_HOST if on_host else SSNAL_ON_DEVICE, None)
+    return int(lib().ssnal_srv_footprint(C.byref(p)))
+
+
+def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None, workers=0):
+    """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0,
+    sigma0].  workers: concurrent workers (0 = the library's default of 8, 1 =
+    in turn on `stream`).  Returns (list of info dicts, worst status)."""
     cnt = len(problems)
     arr = (Problem * cnt)(*[_problem(p["A"], p["b"], p["lambda1"], p["lambda2"], p["tol"], p["x_out"],
-                                     p.get("x0")) for p in problems])
+                                     p.get("x0"), sigma0=p.get("sigma0", 0.0)) for p in problems])
     infos = (Info * cnt)()
     o = opts if opts is not None else make_opts()
+    if workers:
+        o.workers = int(workers)
     rc = lib().ssnal_en_solve_batch(ctx.ptr, arr, cnt, C.byref(o), _stream(stream), infos)
     _check(rc, allow_warn=True)
     return [infos[i].as_dict() for i in range(cnt)], rc
@@ -392,11 +419,20 @@ class Server:
         self.ptr = p
         self._keep = {}
 
-    def submit(self, A, b, lambda1, lambda2, tol, x_out, x0=None) -> int:
+    def submit(self, A, b, lambda1, lambda2, tol, x_out, x0=None, sigma0=0.0, m=None) -> int:
+        """Queue a request.  Device tensors: an event recorded on the current
+        stream orders the solve after the work that wrote them.  Host tensors
+        (pinned for asynchronous uploads): the server uploads A, b and x0 on
+        admission and writes x_out back."""
+        import torch
         t = C.c_uint64(0)
-        prob = _problem(A, b, lambda1, lambda2, tol, x_out, x0)
+        ready = None
+        if A.device.type != "cpu":
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream(A.device))
+        prob = _problem(A, b, lambda1, lambda2, tol, x_out, x0, m=m, sigma0=sigma0, ready=ready)
         _check(lib().ssnal_srv_submit(self.ptr, C.byref(prob), C.byref(t)))
-        self._keep[t.value] = (A, b, x_out, x0)  # tensors stay alive until collected
+        self._keep[t.value] = (A, b, x_out, x0, ready)  # alive until collected
         return t.value
 
     def poll(self, ticket):

@@ -283,7 +283,7 @@ __device__ __forceinline__ void invert_block(const double* __restrict__ Ls, doub
   for (int q = 0; q < kNB * kNB / kStepNT; ++q) {
     const int e = tid + kStepNT * q;
     const int r = e / kNB, c = e % kNB;
-    Ws[e] = (r < nk) & (c < nk) ? WI[r][c] : 0.0;
+    Ws[e] = ((r < nk) & (c < nk)) ? WI[r][c] : 0.0;
   }
 }
 
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kStepNT) void k_chol_step(double* __restrict__ V, i
       {
         const int bad = L.bad;
         if (bad >= 0) {  // a uniform exit: every thread read the same flag
-          if (tid == 0 && p == 0) *info = s0 + j0 + bad + 1;
+          if (tid == 0 && p == 0) atomicCAS(info, 0, s0 + j0 + bad + 1);  // the first bad pivot wins
           return;
         }
       }

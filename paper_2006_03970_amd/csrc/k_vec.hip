@@ -184,32 +184,34 @@ hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t*
 // adds the partials in chunk order, so the sum is reproducible.  r may live
 // on the device (it comes from the compaction pass): the grid is sized for
 // the largest possible r and blocks past the last chunk return at once.
+// Most chunks an r-column gather over m rows takes: 1024; columns longer than
+// 4096 rows already multiply the blocks by their row panels and take fewer
+// (>= 64), which keeps the partial sums (nc m-vectors) small next to A_J.
+__host__ __device__ __forceinline__ int64_t chunk_cap(int m) {
+  if (m <= 4096) return 1024;
+  const int64_t c = (int64_t)1024 * 4096 / m;
+  return c < 64 ? 64 : c;
+}
+
 __host__ __device__ __forceinline__ void chunk_plan(int64_t r, int m, int& nc, int64_t& ck) {
   if (r <= 0) {
     nc = 0;
     ck = 0;
     return;
   }
-  // at most 1024 chunks; columns longer than 4096 rows already multiply the
-  // blocks by their row panels and take fewer (>= 64), which keeps the
-  // partial sums (nc m-vectors) small next to A_J
-  int64_t maxc = 1024;
-  if (m > 4096) {
-    maxc = (int64_t)1024 * 4096 / m;
-    if (maxc < 64) maxc = 64;
-  }
-  int64_t c = (r + maxc - 1) / maxc;
+  int64_t c = (r + chunk_cap(m) - 1) / chunk_cap(m);
   c = (c + 15) / 16 * 16;  // whole groups of 16 columns
   nc = (int)((r + c - 1) / c);
   ck = c;
 }
 
-// Upper bound of the chunk count for any r <= r_bound and any m: nc(r, m) <=
-// ceil(r/16) and <= 1024 (nc itself is not monotone in r).
-int gather_chunks(int64_t r_bound) {
+// Upper bound of the chunk count for any r <= r_bound over m rows: nc(r, m)
+// <= ceil(r/16) and <= chunk_cap(m) (nc itself is not monotone in r).
+int gather_chunks(int64_t r_bound, int m) {
   if (r_bound <= 0) return 0;
   const int64_t c = (r_bound + 15) / 16;
-  return (int)(c < 1024 ? c : 1024);
+  const int64_t cap = chunk_cap(m);
+  return (int)(c < cap ? c : cap);
 }
 
 // Block (b, p) sums columns [b*ck, (b+1)*ck) of A_J weighted by c, for the
@@ -332,7 +334,7 @@ template <typename T>
 static hipError_t launch_gather(const T* A, int64_t lda, int m, const int32_t* J, const double* c,
                                 const double* r_dev, int64_t r_bound, double* part, hipStream_t st,
                                 const double* skip) {
-  const int nb = gather_chunks(r_bound);
+  const int nb = gather_chunks(r_bound, m);
   if (nb == 0) return hipSuccess;
   constexpr int VN = 16 / (int)sizeof(T);
   const int nv = (m + kNT * VN - 1) / (kNT * VN);  // row groups of kNT * VN

@@ -56,11 +56,11 @@ hipError_t support_write(const double* x, int64_t n, const int* counts, int32_t*
 
 // A_J c as per-chunk partial m-vectors: part[chunk*m + i].  r is read from
 // r_dev when non-null (the grid is sized for r_bound >= r), else r = r_bound.
-// gather_chunks(r_bound) bounds the chunk count of every r <= r_bound; the
-// partial buffer holds that many m-vectors.  gather_nchunks(r, m) is the
+// gather_chunks(r_bound, m) bounds the chunk count of every r <= r_bound over
+// m rows; the partial buffer holds that many m-vectors.  gather_nchunks(r, m) is the
 // chunk count of exactly r columns of m rows.  skip (nullable): nothing is
 // done while *skip != 0.
-int gather_chunks(int64_t r_bound);
+int gather_chunks(int64_t r_bound, int m);
 int gather_nchunks(int64_t r, int m);
 hipError_t gather_gemv_partial(const void* A, int dtype, int64_t lda, int m, const int32_t* J,
                                const double* c, const double* r_dev, int64_t r_bound, double* part,
@@ -87,7 +87,7 @@ hipError_t cg_init(const double* g, double* d, double* res, double* p, int m, do
 // One iteration (a no-op once done is set): s = A_J^T p, q = p + kappa A_J s,
 // alpha = rr/(p^T q), d += alpha p, res -= alpha q, beta = rr_new/rr,
 // p = res + beta p; done once rr_new <= stop.  par = iteration parity.
-// gpart: gather_chunks(r) m-vectors; blk: ceil(m/256) + cg_blocks(m) doubles.
+// gpart: gather_chunks(r, m) m-vectors; blk: ceil(m/256) + cg_blocks(m) doubles.
 int cg_blocks(int m);
 hipError_t cg_iteration(const void* A, int dtype, int64_t lda, int m, const int32_t* J, int64_t r,
                         double kappa, bool acc64, double* d, double* res, double* p, double* q,

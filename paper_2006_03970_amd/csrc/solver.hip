@@ -67,6 +67,7 @@ struct ssnal_ctx {
   double* d_scal = nullptr;  // the same memory as the device addresses it
   unsigned long long pub_seq = 0;
   std::vector<hipEvent_t> ev;
+  hipEvent_t ev_order = nullptr;  // orders worker streams after the caller's stream
   bool chol_ready = false;
   double last_sigma0 = 0.0;  // sigma0 of the last solve (after defaults)
 };
@@ -129,7 +130,7 @@ WsPlan plan_ws(int64_t m, int64_t n) {
   p.bytes[3] = (size_t)n * 4;  // J
   p.bytes[4] = (size_t)nb * 4;  // counts
   p.bytes[5] = (std::max({ls_part_doubles(n), (size_t)(2048 + nb) + 4 * (size_t)nb, m_part}) + 64) * 8;  // part
-  p.bytes[6] = (size_t)(gather_chunks(n) + 1) * m * 8;  // gpart
+  p.bytes[6] = (size_t)(gather_chunks(n, (int)m) + 1) * m * 8;  // gpart
   p.bytes[7] = (size_t)md * md * 8;  // V
   p.bytes[8] = (size_t)(2048 + T * (T + 1) / 2 + 1) * 64 * 64 * sizeof(double);  // syrk split-K
   p.bytes[9] = (size_t)MV_COUNT * m * 8;  // m-vectors
@@ -233,6 +234,13 @@ int readback(ssnal_ctx* c, const Workspace& w, hipStream_t st, int* syncs) {
   return wait_pub(c, st, p.seq, syncs);
 }
 
+// Error of a non-zero Cholesky status word: row + 1 of a non-positive pivot,
+// or -1 when a wait inside a factorisation step ran out (an internal error).
+int chol_fail(int info) {
+  if (info < 0) return fail(SSNAL_EHIP, "Cholesky: an internal wait of a factorisation step timed out");
+  return fail(SSNAL_ENUMERIC, "Cholesky: non-positive pivot at row %d", info - 1);
+}
+
 int check_args(const void* A, int dt, int64_t lda, const double* b, int64_t m, int64_t n) {
   if (!A || !b) return fail(SSNAL_EINVAL, "A and b must be non-null device pointers");
   if (dt < 0 || dt > 2) return fail(SSNAL_EINVAL, "a_dtype %d is not SSNAL_F64/F32/BF16", dt);
@@ -248,7 +256,8 @@ struct Timer {
   hipStream_t st;
   bool on;
   int used = 0;
-  std::vector<char> tags;  // 1 = the Newton A^T d pass, 0 = any other A^T v pass
+  std::vector<char> tags;  // 1 = the Newton A^T d pass, 2 = a Cholesky factor + solve, 0 = any other A^T v pass
+  double chol_flops = 0.0;  // N^3/3 summed over the timed factorisations
   hipEvent_t e0 = nullptr, e1 = nullptr;  // the pair for the next timed launch
   // Hand out the next event pair (nulls when timing is off); the launch
   // stamps them around the kernel.
@@ -268,14 +277,20 @@ struct Timer {
     ++used;
     return 0;
   }
-  // Summed durations of every timed pass, and of the tag-1 passes alone.
-  int total_ms(double* out, double* out1 = nullptr, int* n1 = nullptr) {
-    double t = 0.0, t1 = 0.0;
-    int c1 = 0;
+  // Summed durations of the timed A^T v passes (tags 0 and 1), of the tag-1
+  // passes alone, and of the tag-2 factorisations.
+  int total_ms(double* out, double* out1, int* n1, double* out2, int* n2) {
+    double t = 0.0, t1 = 0.0, t2 = 0.0;
+    int c1 = 0, c2 = 0;
     for (int k = 0; k < used; ++k) {
       float ms = 0.0f;
       HIPCHK(hipEventSynchronize(c->ev[2 * k + 1]));  // readbacks do not wait for events
       HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+      if (tags[k] == 2) {
+        t2 += ms;
+        ++c2;
+        continue;
+      }
       t += ms;
       if (tags[k] == 1) {
         t1 += ms;
@@ -283,8 +298,10 @@ struct Timer {
       }
     }
     *out = t;
-    if (out1) *out1 = t1;
-    if (n1) *n1 = c1;
+    *out1 = t1;
+    *n1 = c1;
+    *out2 = t2;
+    *n2 = c2;
     return 0;
   }
 };
@@ -294,7 +311,21 @@ struct Timer {
 // eq. smw_formula when 0 < r < m and smw is allowed.
 int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J, int64_t r,
                      double kappa, const double* g, double* d, int form, const Workspace& w,
-                     hipStream_t st) {
+                     hipStream_t st, Timer* tm = nullptr) {
+  // factor + solve of an N x N system, timed as tag 2 when timing is on
+  auto factor_solve = [&](int N, const double* rhs, double alpha, double* out) -> int {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm && tm->on) {
+      if (int rc = tm->next(2)) return rc;
+      e0 = tm->e0;
+      e1 = tm->e1;
+      tm->chol_flops += (double)N * N * N / 3.0;
+      HIPCHK(hipEventRecord(e0, st));
+    }
+    HIPCHK(chol_factor_solve(w.V, N, rhs, alpha, w.t3, out, (double*)w.syrk, w.info, st));
+    if (e1) HIPCHK(hipEventRecord(e1, st));
+    return 0;
+  };
   if (r == 0) {
     HIPCHK(vec_scale_copy(g, -1.0, d, m, st));
     return 0;
@@ -304,8 +335,7 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
     HIPCHK(syrk(A, dt, lda, m, J, r, 0, 1.0, kappa, w.V, w.syrk, st));
     // the SYRK partials are dead once V is formed: their buffer holds the
     // diagonal blocks of L
-    HIPCHK(chol_factor_solve(w.V, m, g, -1.0, w.t3, d, (double*)w.syrk, w.info, st));
-    return 0;
+    return factor_solve(m, g, -1.0, d);
   }
   // (I + kappa A_J A_J^T)^{-1} = I - A_J (I/kappa + A_J^T A_J)^{-1} A_J^T
   // d = -g + A_J q,  (I/kappa + A_J^T A_J) q = A_J^T g
@@ -314,7 +344,7 @@ int newton_direction(const void* A, int dt, int64_t lda, int m, const int32_t* J
   double* q = w.t2;
   HIPCHK(gemv_t(A, dt, lda, m, r, J, g, v, true, st));
   HIPCHK(syrk(A, dt, lda, m, J, r, 1, 1.0 / kappa, 1.0, w.V, w.syrk, st));
-  HIPCHK(chol_factor_solve(w.V, N, v, 1.0, w.t3, q, (double*)w.syrk, w.info, st));
+  if (int rc = factor_solve(N, v, 1.0, q)) return rc;
   HIPCHK(gather_gemv_partial(A, dt, lda, m, J, q, nullptr, r, w.gpart, st));
   HIPCHK(gather_finish(w.gpart, nullptr, r, m, 1, nullptr, nullptr, const_cast<double*>(g), d, w.scal,
                        st));
@@ -404,9 +434,12 @@ void certificate_values(const double* hs, double l1, double l2, double* eta, dou
   }
 }
 
+// preset (nullable): a workspace the caller laid out (the no-allocation entry
+// point); otherwise the context's workspace, grown as needed.
 int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int64_t m64,
                int64_t n, double l1, double l2, const double* x0, double tol, hipStream_t st,
-               double* x, const ssnal_en_opts* user_opts, ssnal_en_info* info) {
+               double* x, const ssnal_en_opts* user_opts, ssnal_en_info* info,
+               const Workspace* preset = nullptr) {
   const auto t_start = std::chrono::steady_clock::now();
   if (int rc = check_args(A, dt, lda, b, m64, n)) return rc;
   if (!x) return fail(SSNAL_EINVAL, "x_out must be a non-null device pointer");
@@ -441,7 +474,11 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   if (!(o.cg_eta < 1.0)) return fail(SSNAL_EINVAL, "cg_eta must lie in (0, 1)");
   HIPCHK(hipSetDevice(c->device));
   Workspace w;
-  if (int rc = prepare(c, m, n, w)) return rc;
+  if (preset) {
+    w = *preset;
+  } else if (int rc = prepare(c, m, n, w)) {
+    return rc;
+  }
   const bool mixed = dt != kF64;
   Timer tm{c, st, o.timing != 0};
   int gemv_calls = 0, syncs = 0;
@@ -523,7 +560,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
       {
         int cinfo = 0;
         std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
-        if (cinfo != 0) return fail(SSNAL_ENUMERIC, "Cholesky: non-positive pivot at row %d", cinfo - 1);
+        if (cinfo != 0) return chol_fail(cinfo);
       }
       if (pending_row >= 0) {
         if (o.trace && pending_row < o.trace_cap) o.trace[pending_row * 6 + 4] = hs[SC_S];
@@ -563,7 +600,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
         rc = newton_cg(c, A, dt, lda, m, w.J, r, kappa, w.g, w.d, eps, o.cg_maxit, w, st, &syncs, &it);
         cg_iters += it;
       } else {
-        rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, dense_r ? 1 : 0, w, st);
+        rc = newton_direction(A, dt, lda, m, w.J, r, kappa, w.g, w.d, dense_r ? 1 : 0, w, st, &tm);
       }
       if (rc) return rc;
       // w_d = A^T d, the HBM pass
@@ -632,12 +669,16 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     info->gemv_calls = gemv_calls;
     info->syncs = syncs;
     info->cg_iters = cg_iters;
-    double gms = 0.0, dms = 0.0;
-    int dn = 0;
-    if (int rc = tm.total_ms(&gms, &dms, &dn)) return rc;
+    info->sigma0 = c->last_sigma0;
+    double gms = 0.0, dms = 0.0, cms = 0.0;
+    int dn = 0, cn = 0;
+    if (int rc = tm.total_ms(&gms, &dms, &dn, &cms, &cn)) return rc;
     info->gemv_ms = gms;
     info->atd_ms = dms;
     info->atd_launches = dn;
+    info->chol_ms = cms;
+    info->chol_calls = cn;
+    info->chol_gflop = tm.chol_flops * 1e-9;
     info->solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }
@@ -711,6 +752,7 @@ void ssnal_ctx_destroy(ssnal_ctx* c) {
     if (b->p) (void)hipFree(b->p);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_order) (void)hipEventDestroy(c->ev_order);
   for (ssnal_ctx* s : c->cv_sub) ssnal_ctx_destroy(s);
   for (hipStream_t s : c->cv_streams) (void)hipStreamDestroy(s);
   delete c;
@@ -822,6 +864,34 @@ static int path_impl(ssnal_ctx* ctx, const void* A, int dt, int64_t lda, const d
   return worst;
 }
 
+// Worker contexts of ctx (k-fold folds, batch problems), each with its own
+// stream of default priority; created on first use and kept by ctx.
+static int ensure_workers(ssnal_ctx* ctx, int nw) {
+  while ((int)ctx->cv_sub.size() < nw) {
+    ssnal_ctx* sub = nullptr;
+    if (int rc = ssnal_ctx_create(ctx->device, &sub)) return rc;
+    hipStream_t s = nullptr;
+    if (hipStreamCreate(&s) != hipSuccess) {
+      ssnal_ctx_destroy(sub);
+      return fail(SSNAL_EHIP, "stream creation failed");
+    }
+    ctx->cv_sub.push_back(sub);
+    ctx->cv_streams.push_back(s);
+  }
+  return 0;
+}
+
+// Options of one problem of a batch or of the serving loop: the shared
+// options with the problem's own sigma0 when it sets one.
+static const ssnal_en_opts* problem_opts(const ssnal_en_problem& p, const ssnal_en_opts* shared,
+                                         ssnal_en_opts& local) {
+  if (!(p.sigma0 > 0.0)) return shared;
+  if (shared) local = *shared;
+  else ssnal_en_opts_init(&local);
+  local.sigma0 = p.sigma0;
+  return &local;
+}
+
 // Fold f of k-fold cross validation on context c and stream st: the
 // training rows (fold != f, in order) copied into c's buffer, the path over
 // the full data's grid on them, then the mean squared error over the rows of
@@ -914,17 +984,7 @@ int ssnal_en_cv(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
   // folds run concurrently: worker i has its own context and stream; each
   // fold's work is independent of the others, so the results do not depend
   // on the schedule
-  while ((int)ctx->cv_sub.size() < nw) {
-    ssnal_ctx* sub = nullptr;
-    if (int rc = ssnal_ctx_create(ctx->device, &sub)) return rc;
-    hipStream_t s = nullptr;
-    if (hipStreamCreate(&s) != hipSuccess) {
-      ssnal_ctx_destroy(sub);
-      return fail(SSNAL_EHIP, "stream creation failed");
-    }
-    ctx->cv_sub.push_back(sub);
-    ctx->cv_streams.push_back(s);
-  }
+  if (int rc = ensure_workers(ctx, nw)) return rc;
   std::vector<int> rcs(k, 0);
   std::vector<std::string> msgs(k);
   std::atomic<int> next{0};
@@ -958,15 +1018,68 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
   g_err[0] = 0;
   if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
   if (count < 0 || (count > 0 && !problems)) return fail(SSNAL_EINVAL, "invalid problem list");
+  for (int i = 0; i < count; ++i)
+    if (problems[i].location != SSNAL_ON_DEVICE)
+      return fail(SSNAL_EINVAL, "problem %d: a batch takes device-resident problems only", i);
+  if (count == 0) return 0;
+  HIPCHK(hipSetDevice(ctx->device));
+  const int want = opts && opts->workers > 0 ? opts->workers : 8;
+  if (want > 64) return fail(SSNAL_EINVAL, "opts->workers must lie in [1, 64]");
+  const int nw = std::min(want, count);
+  if (nw == 1) {
+    int worst = 0;
+    for (int i = 0; i < count; ++i) {
+      const ssnal_en_problem& p = problems[i];
+      if (p.ready) HIPCHK(hipStreamWaitEvent(stream, p.ready, 0));
+      ssnal_en_opts local;
+      ssnal_en_info info_i;
+      const int rc = solve_impl(ctx, p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1, p.lambda2,
+                                p.x0, p.tol, stream, p.x_out, problem_opts(p, opts, local), &info_i);
+      if (rc < 0) return rc;
+      if (infos) infos[i] = info_i;
+      worst = std::max(worst, rc);
+    }
+    return worst;
+  }
+  if (int rc = ensure_workers(ctx, nw)) return rc;
+  // the workers' streams start after the caller's earlier work on `stream`
+  if (!ctx->ev_order) HIPCHK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
+  hipEvent_t start = ctx->ev_order;
+  HIPCHK(hipEventRecord(start, stream));
+  for (int i = 0; i < nw; ++i) HIPCHK(hipStreamWaitEvent(ctx->cv_streams[i], start, 0));
+  std::vector<int> rcs(count, 0);
+  std::vector<std::string> msgs(count);
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w) {
+    th.emplace_back([&, w]() {
+      for (int i = next++; i < count; i = next++) {
+        g_err[0] = 0;
+        const ssnal_en_problem& p = problems[i];
+        hipStream_t st = ctx->cv_streams[w];
+        if (p.ready && hipStreamWaitEvent(st, p.ready, 0) != hipSuccess) {
+          rcs[i] = fail(SSNAL_EHIP, "problem %d: waiting for its ready event failed", i);
+        } else {
+          ssnal_en_opts local;
+          ssnal_en_info info_i;
+          rcs[i] = solve_impl(ctx->cv_sub[w], p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1,
+                              p.lambda2, p.x0, p.tol, st, p.x_out, problem_opts(p, opts, local),
+                              &info_i);
+          if (infos && rcs[i] >= 0) infos[i] = info_i;
+        }
+        msgs[i] = g_err;
+        if (rcs[i] < 0) next = count;  // stop handing out problems
+      }
+    });
+  }
+  for (std::thread& t : th) t.join();
   int worst = 0;
   for (int i = 0; i < count; ++i) {
-    const ssnal_en_problem& p = problems[i];
-    ssnal_en_info info_i;
-    const int rc = solve_impl(ctx, p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1, p.lambda2,
-                              p.x0, p.tol, stream, p.x_out, opts, &info_i);
-    if (rc < 0) return rc;
-    if (infos) infos[i] = info_i;
-    worst = std::max(worst, rc);
+    if (rcs[i] < 0) {
+      snprintf(g_err, sizeof(g_err), "problem %d: %s", i, msgs[i].c_str());
+      return rcs[i];
+    }
+    worst = std::max(worst, rcs[i]);
   }
   return worst;
 }
@@ -982,16 +1095,47 @@ size_t ssnal_workspace_bytes(int64_t m, int64_t n) {
 }  // extern "C"
 
 // ====================================================================== serving loop
-// Slot i is a host thread with its own context and stream.  Admission is
-// first come, first served: the request at the head of the queue goes to the
-// first idle slot whose context, grown for it, keeps the bytes held by all
-// contexts within the budget.  When nothing is running and the head still
-// does not fit, idle contexts release their workspace (no work is in flight,
-// so freeing is safe) and the head is admitted.
+// Slot i is a host thread with its own context, stream and (for host-resident
+// requests) device buffers for the uploaded A, b and x.  Admission: among the
+// queued requests whose footprint fits the budget next to what the other
+// slots hold, the one with the least estimated work goes to an idle slot; the
+// oldest request goes first once it has been passed over kBypassPerSlot *
+// slots times.  When nothing is running and the oldest request still does
+// not fit, idle slots release their buffers (no work is in flight, so freeing
+// is safe) and it is admitted.
+namespace {
+
+constexpr int kBypassPerSlot = 4;
+
+using Clock = std::chrono::steady_clock;
+
+// Staging bytes a host-resident problem needs on the device: A packed with
+// lda = m, then b and x.
+size_t stage_a_bytes(const ssnal_en_problem& p) {
+  return p.location == SSNAL_ON_HOST ? (size_t)p.m * (size_t)p.n * (size_t)dtype_size((int)p.a_dtype) : 0;
+}
+size_t stage_v_bytes(const ssnal_en_problem& p) {
+  return p.location == SSNAL_ON_HOST ? (size_t)(p.m + p.n) * 8 : 0;
+}
+
+// Estimated device time of a solve in milliseconds, for ordering only: about
+// 15 passes over A at 6 TB/s, 10 factorisations of ceil(N/64) block steps of
+// 20 us each (N = min(m, 4096)), and 1 ms of fixed costs.
+double est_ms(const ssnal_en_problem& p) {
+  const double pass = (double)p.m * (double)p.n * dtype_size((int)p.a_dtype) / 6e9;
+  const double steps = (double)((std::min<int64_t>(p.m, 4096) + 63) / 64);
+  return 15.0 * pass + 10.0 * steps * 0.02 + 1.0;
+}
+
+}  // namespace
+
 struct ssnal_srv {
   struct Req {
     uint64_t ticket;
     ssnal_en_problem p;
+    Clock::time_point t_submit;
+    double cost;
+    int bypassed;
   };
   struct Done {
     int status;
@@ -1000,6 +1144,7 @@ struct ssnal_srv {
   };
   int device = 0;
   size_t budget = 0;
+  int max_bypass = 0;
   ssnal_en_opts opts;
   bool has_opts = false;
   std::mutex mu;
@@ -1008,7 +1153,8 @@ struct ssnal_srv {
   std::unordered_map<uint64_t, Done> done;
   std::unordered_map<uint64_t, int> live;  // queued or running tickets
   std::vector<ssnal_ctx*> ctx;
-  std::vector<size_t> held;  // bytes held by each slot's context
+  std::vector<DevBuf> stage_a, stage_v;  // per slot: uploaded A; b then x
+  std::vector<size_t> held;  // bytes held by each slot (context + staging)
   std::vector<char> busy;
   std::vector<std::thread> workers;
   int running = 0;
@@ -1025,13 +1171,103 @@ size_t ctx_held(ssnal_ctx* c) {
   for (int i = 0; i < 10; ++i) t += ws_bufs(c, i)->bytes;
   return t;
 }
+size_t slot_held(ssnal_srv* s, int slot) {
+  return ctx_held(s->ctx[slot]) + s->stage_a[slot].bytes + s->stage_v[slot].bytes;
+}
+// Bytes slot would hold while serving p (every buffer only grows).
+size_t slot_held_after(ssnal_srv* s, int slot, const ssnal_en_problem& p) {
+  return held_after(s->ctx[slot], plan_ws(p.m, p.n)) + std::max(s->stage_a[slot].bytes, stage_a_bytes(p)) +
+         std::max(s->stage_v[slot].bytes, stage_v_bytes(p));
+}
+void slot_trim(ssnal_srv* s, int slot) {
+  ctx_trim(s->ctx[slot]);
+  for (DevBuf* b : {&s->stage_a[slot], &s->stage_v[slot]}) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+  s->held[slot] = slot_held(s, slot);
+}
+
+// Index in s->queue of the request slot should take now, or -1 (caller holds
+// the lock).  Passed-over requests older than the one taken count a bypass.
+int srv_pick(ssnal_srv* s, int slot) {
+  size_t others = 0;
+  for (size_t j = 0; j < s->held.size(); ++j)
+    if ((int)j != slot) others += s->held[j];
+  auto fits = [&](const ssnal_en_problem& p) { return others + slot_held_after(s, slot, p) <= s->budget; };
+  const int nq = (int)s->queue.size();
+  if (nq == 0) return -1;
+  if (s->queue.front().bypassed >= s->max_bypass) {
+    // the oldest request has waited long enough: it goes next, as soon as it fits
+    if (fits(s->queue.front().p)) return 0;
+    if (s->running == 0) {
+      for (size_t j = 0; j < s->ctx.size(); ++j) slot_trim(s, (int)j);
+      return 0;
+    }
+    return -1;
+  }
+  int best = -1;
+  for (int i = 0; i < nq; ++i) {
+    const ssnal_srv::Req& q = s->queue[i];
+    if (!fits(q.p)) continue;
+    if (best < 0 || q.cost < s->queue[best].cost) best = i;
+  }
+  if (best < 0) {
+    if (s->running != 0) return -1;
+    for (size_t j = 0; j < s->ctx.size(); ++j) slot_trim(s, (int)j);
+    best = 0;
+  }
+  for (int i = 0; i < best; ++i) ++s->queue[i].bypassed;
+  return best;
+}
+
+// Run one admitted request on slot's context and stream.
+int srv_run(ssnal_srv* s, int slot, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+            const ssnal_en_problem& p, ssnal_en_info* info) {
+  ssnal_ctx* c = s->ctx[slot];
+  ssnal_en_opts local;
+  const ssnal_en_opts* o = problem_opts(p, s->has_opts ? &s->opts : nullptr, local);
+  if (p.location != SSNAL_ON_HOST) {
+    if (p.ready) HIPCHK(hipStreamWaitEvent(st, p.ready, 0));
+    return solve_impl(c, p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1, p.lambda2, p.x0, p.tol, st,
+                      p.x_out, o, info);
+  }
+  // host-resident: upload A (packed, lda = m), b and x0 into the slot's buffers
+  if (int rc = ensure(s->stage_a[slot], stage_a_bytes(p))) return rc;
+  if (int rc = ensure(s->stage_v[slot], stage_v_bytes(p))) return rc;
+  const size_t es = (size_t)dtype_size((int)p.a_dtype);
+  void* dA = s->stage_a[slot].p;
+  double* db = (double*)s->stage_v[slot].p;
+  double* dx = db + p.m;
+  HIPCHK(hipEventRecord(ev0, st));
+  if (p.lda == p.m)
+    HIPCHK(hipMemcpyAsync(dA, p.A, (size_t)p.m * (size_t)p.n * es, hipMemcpyHostToDevice, st));
+  else
+    HIPCHK(hipMemcpy2DAsync(dA, (size_t)p.m * es, p.A, (size_t)p.lda * es, (size_t)p.m * es, (size_t)p.n,
+                            hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(db, p.b, (size_t)p.m * 8, hipMemcpyHostToDevice, st));
+  if (p.x0) HIPCHK(hipMemcpyAsync(dx, p.x0, (size_t)p.n * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(ev1, st));
+  const int rc = solve_impl(c, dA, (int)p.a_dtype, p.m, db, p.m, p.n, p.lambda1, p.lambda2,
+                            p.x0 ? dx : nullptr, p.tol, st, dx, o, info);
+  if (rc < 0) return rc;
+  HIPCHK(hipMemcpyAsync(p.x_out, dx, (size_t)p.n * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+  if (info) info->upload_ms = ms;
+  return rc;
+}
 
 void srv_worker(ssnal_srv* s, int slot) {
   hipStream_t st = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   {
     std::unique_lock<std::mutex> lk(s->mu);
     if (hipSetDevice(s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
       s->init_rc = SSNAL_EHIP;
       snprintf(s->init_err, sizeof(s->init_err), "slot %d: stream creation failed", slot);
       st = nullptr;
@@ -1042,55 +1278,36 @@ void srv_worker(ssnal_srv* s, int slot) {
     ssnal_srv::Req req;
     {
       std::unique_lock<std::mutex> lk(s->mu);
+      int pick = -1;
       for (;;) {
-        if (s->queue.empty()) {
-          if (s->stop) {
-            lk.unlock();
-            if (st) (void)hipStreamDestroy(st);
-            return;
-          }
-          s->cv_work.wait(lk);
-          continue;
+        if (s->queue.empty() && s->stop) {
+          lk.unlock();
+          if (ev0) (void)hipEventDestroy(ev0);
+          if (ev1) (void)hipEventDestroy(ev1);
+          if (st) (void)hipStreamDestroy(st);
+          return;
         }
-        const ssnal_en_problem& hp = s->queue.front().p;
-        const WsPlan plan = plan_ws(hp.m, hp.n);
-        size_t others = 0;
-        for (size_t j = 0; j < s->held.size(); ++j)
-          if ((int)j != slot) others += s->held[j];
-        const size_t mine = held_after(s->ctx[slot], plan);
-        if (others + mine <= s->budget) break;
-        if (s->running == 0) {
-          // nothing in flight: release every idle workspace, then admit the head
-          for (size_t j = 0; j < s->ctx.size(); ++j) {
-            ctx_trim(s->ctx[j]);
-            s->held[j] = ctx_held(s->ctx[j]);
-          }
-          break;
-        }
+        if ((pick = srv_pick(s, slot)) >= 0) break;
         s->cv_work.wait(lk);
       }
-      req = s->queue.front();
-      s->queue.pop_front();
-      s->held[slot] = held_after(s->ctx[slot], plan_ws(req.p.m, req.p.n));
+      req = s->queue[pick];
+      s->queue.erase(s->queue.begin() + pick);
+      s->held[slot] = slot_held_after(s, slot, req.p);
       s->busy[slot] = 1;
       ++s->running;
-      s->cv_work.notify_all();  // the next head may fit another idle slot
+      s->cv_work.notify_all();  // another queued request may fit another idle slot
     }
     ssnal_srv::Done d;
     std::memset(&d.info, 0, sizeof(d.info));
-    if (st) {
-      const ssnal_en_problem& p = req.p;
-      d.status = solve_impl(s->ctx[slot], p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1,
-                            p.lambda2, p.x0, p.tol, st, p.x_out, s->has_opts ? &s->opts : nullptr,
-                            &d.info);
-    } else {
-      d.status = SSNAL_EHIP;
-    }
+    const double queue_ms = std::chrono::duration<double, std::milli>(Clock::now() - req.t_submit).count();
+    g_err[0] = 0;
+    d.status = st ? srv_run(s, slot, st, ev0, ev1, req.p, &d.info) : SSNAL_EHIP;
     if (d.status < 0) d.info.status = d.status;
+    d.info.queue_ms = queue_ms;
     snprintf(d.err, sizeof(d.err), "%s", g_err);
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->held[slot] = ctx_held(s->ctx[slot]);
+      s->held[slot] = slot_held(s, slot);
       s->busy[slot] = 0;
       --s->running;
       s->live.erase(req.ticket);
@@ -1101,9 +1318,26 @@ void srv_worker(ssnal_srv* s, int slot) {
   }
 }
 
+int check_problem(const ssnal_en_problem* p) {
+  if (int rc = check_args(p->A, (int)p->a_dtype, p->lda, p->b, p->m, p->n)) return rc;
+  if (!p->x_out) return fail(SSNAL_EINVAL, "x_out must be non-null");
+  if (!(p->lambda1 >= 0.0) || !(p->lambda2 >= 0.0) || !(p->tol > 0.0))
+    return fail(SSNAL_EINVAL, "need lambda1 >= 0, lambda2 >= 0, tol > 0");
+  if (p->location != SSNAL_ON_DEVICE && p->location != SSNAL_ON_HOST)
+    return fail(SSNAL_EINVAL, "location %d is not SSNAL_ON_DEVICE or SSNAL_ON_HOST", (int)p->location);
+  if (p->location == SSNAL_ON_HOST && p->ready)
+    return fail(SSNAL_EINVAL, "a host-resident problem takes no ready event");
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t ssnal_srv_footprint(const ssnal_en_problem* p) {
+  if (!p || p->m < 1 || p->n < 1) return 0;
+  return ssnal_workspace_bytes(p->m, p->n) + stage_a_bytes(*p) + stage_v_bytes(*p);
+}
 
 int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_en_opts* opts,
                      ssnal_srv** out) {
@@ -1116,6 +1350,7 @@ int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_e
   if (!s) return fail(SSNAL_ENOMEM, "host allocation failed");
   s->device = device;
   s->budget = hbm_budget;
+  s->max_bypass = kBypassPerSlot * max_slots;
   if (opts) {
     s->opts = *opts;
     s->opts.trace = nullptr;
@@ -1130,6 +1365,8 @@ int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_e
       return rc;
     }
     s->ctx.push_back(c);
+    s->stage_a.emplace_back();
+    s->stage_v.emplace_back();
     s->held.push_back(ctx_held(c));
     s->busy.push_back(0);
   }
@@ -1141,18 +1378,15 @@ int ssnal_srv_create(int device, size_t hbm_budget, int max_slots, const ssnal_e
 int ssnal_srv_submit(ssnal_srv* s, const ssnal_en_problem* p, uint64_t* ticket) {
   g_err[0] = 0;
   if (!s || !p || !ticket) return fail(SSNAL_EINVAL, "null argument");
-  if (int rc = check_args(p->A, (int)p->a_dtype, p->lda, p->b, p->m, p->n)) return rc;
-  if (!p->x_out) return fail(SSNAL_EINVAL, "x_out must be non-null");
-  if (!(p->lambda1 >= 0.0) || !(p->lambda2 >= 0.0) || !(p->tol > 0.0))
-    return fail(SSNAL_EINVAL, "need lambda1 >= 0, lambda2 >= 0, tol > 0");
-  const size_t need = ssnal_workspace_bytes(p->m, p->n);
+  if (int rc = check_problem(p)) return rc;
+  const size_t need = ssnal_srv_footprint(p);
   if (need > s->budget)
-    return fail(SSNAL_ENOMEM, "request needs %zu workspace bytes, budget is %zu", need, s->budget);
+    return fail(SSNAL_ENOMEM, "request needs %zu device bytes, budget is %zu", need, s->budget);
   std::unique_lock<std::mutex> lk(s->mu);
   if (s->init_rc) return fail(s->init_rc, "%s", s->init_err);
   if (s->stop) return fail(SSNAL_EINVAL, "server is shutting down");
   const uint64_t t = s->next_ticket++;
-  s->queue.push_back({t, *p});
+  s->queue.push_back({t, *p, Clock::now(), est_ms(*p), 0});
   s->live[t] = 1;
   *ticket = t;
   s->cv_work.notify_all();
@@ -1197,7 +1431,12 @@ void ssnal_srv_destroy(ssnal_srv* s) {
     s->cv_work.notify_all();
   }
   for (std::thread& t : s->workers) t.join();
-  for (ssnal_ctx* c : s->ctx) ssnal_ctx_destroy(c);
+  (void)hipSetDevice(s->device);
+  for (size_t j = 0; j < s->ctx.size(); ++j) {
+    for (DevBuf* b : {&s->stage_a[j], &s->stage_v[j]})
+      if (b->p) (void)hipFree(b->p);
+    ssnal_ctx_destroy(s->ctx[j]);
+  }
   delete s;
 }
 
@@ -1266,7 +1505,7 @@ int ssnal_cholesky(ssnal_ctx* ctx, double* V, int64_t N, hipStream_t stream) {
   if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
   int hinfo = 0;
   std::memcpy(&hinfo, &ctx->h_scal[SC_CHOL], sizeof(int));
-  if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
+  if (hinfo != 0) return chol_fail(hinfo);
   return 0;
 }
 
@@ -1290,7 +1529,7 @@ int ssnal_newton_direction(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, i
   if (int rc = readback(ctx, ws, stream, nullptr)) return rc;
   int hinfo = 0;
   std::memcpy(&hinfo, &ctx->h_scal[SC_CHOL], sizeof(int));
-  if (hinfo != 0) return fail(SSNAL_ENUMERIC, "non-positive pivot at row %d", hinfo - 1);
+  if (hinfo != 0) return chol_fail(hinfo);
   return 0;
 }
 
@@ -1372,6 +1611,7 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
   {
     int cinfo = 0;
     std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
+    if (cinfo < 0) return chol_fail(cinfo);
     if (cinfo != 0) return fail(SSNAL_ENUMERIC, "lambda2 I + Gram: non-positive pivot at row %d", cinfo - 1);
   }
   out->nu = (double)N - lambda2 * hs[SC_MS_FROB];
@@ -1394,6 +1634,7 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
   {
     int cinfo = 0;
     std::memcpy(&cinfo, &hs[SC_CHOL], sizeof(int));
+    if (cinfo < 0) return chol_fail(cinfo);
     if (cinfo != 0) {
       out->status = 2;
       out->rss = out->gcv = out->ebic = nan;

@@ -144,13 +144,23 @@ def test_cholesky(gpu, ctx, orc, N):
     assert np.max(np.abs(L - Lr)) <= 1e-12 * np.max(np.abs(Lr)) * max(1.0, np.sqrt(N))
 
 
-def test_cholesky_not_pd(gpu, ctx):
+@pytest.mark.parametrize("N,row", [(10, 0), (200, 150), (200, 180), (1000, 999), (300, 64)])
+def test_cholesky_not_pd(gpu, ctx, N, row):
+    """A non-positive pivot in the first or a later block step, in either
+    half of a block, is reported with its row (the first one met)."""
     import torch
-    _say("cholesky not PD")
-    V = torch.from_numpy(-np.eye(10)).cuda()
+    _say("cholesky not PD", N, row)
+    g = np.random.default_rng(N + row)
+    M = g.standard_normal((N, N)) * 0.01
+    V = np.eye(N) + M @ M.T
+    V[row, :] = 0.0
+    V[:, row] = 0.0
+    V[row, row] = -1.0
+    V[min(row + 3, N - 1), min(row + 3, N - 1)] = -1.0  # a later bad pivot does not replace it
     with pytest.raises(gpu.SsnalError) as e:
-        gpu.ssnal_cholesky(ctx, V)
+        gpu.ssnal_cholesky(ctx, torch.from_numpy(V).cuda())
     assert e.value.code == -5
+    assert f"row {row}" in str(e.value), str(e.value)
 
 
 # ----------------------------------------------------------------- Newton direction
