@@ -166,6 +166,25 @@ int ssnal_en_solve(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t l
                    const ssnal_en_opts* opts, ssnal_en_info* info);
 
 /*
+ * ssnal_en_solve without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics and results as
+ * ssnal_en_solve; the device workspace lives in one static device array of
+ * 48 MiB per device (held from the library's load until the process ends)
+ * instead of the context's buffers, so the call makes no hipMalloc, hipFree
+ * or other allocation.  The context still supplies its scalar slots and
+ * pinned read-back memory (allocated when it was created).
+ * Limits: m <= 512 and n <= 131072 (sizes beyond: SSNAL_EINVAL), opts->timing
+ * and opts->newton_cg must be 0 (SSNAL_EINVAL).  Every call on a device shares
+ * that device's array: calls that overlap on one device (several host threads
+ * or streams) race and must be serialised by the caller.
+ */
+int ssnal_en_solve_noalloc(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda,
+                           const double* b, int64_t m, int64_t n, double lambda1, double lambda2,
+                           const double* x0, double tol, hipStream_t stream, double* x_out,
+                           const ssnal_en_opts* opts, ssnal_en_info* info);
+
+/*
  * Regularisation path with warm starts (Sec. 3.3: each solve starts from the
  * solution at the previous, larger lambda).
  *   alpha in (0, 1]       : mixing weight (1: the Lasso); point k solves lambda1 = alpha*lam_k,

@@ -80,6 +80,7 @@ def lib():
         L.ssnal_ctx_destroy.argtypes = [_vp]
         L.ssnal_en_solve.argtypes = [_vp, _vp, _i, _i64, _vp, _i64, _i64, _d, _d, _vp, _d, _vp, _vp,
                                      C.POINTER(Opts), C.POINTER(Info)]
+        L.ssnal_en_solve_noalloc.argtypes = L.ssnal_en_solve.argtypes
         L.ssnal_gemv_t.argtypes = [_vp, _vp, _i, _i64, _i64, _i64, _vp, _vp, _i, _vp]
         L.ssnal_active_prox.argtypes = [_vp, _vp, _vp, _i64, _d, _d, _d, _vp, _vp,
                                         C.POINTER(_i64), _vp]
@@ -112,7 +113,7 @@ def lib():
         for name in ("ssnal_en_path", "ssnal_en_solve_batch", "ssnal_srv_create", "ssnal_srv_submit",
                      "ssnal_srv_poll", "ssnal_srv_wait"):
             getattr(L, name).restype = _i
-        for name in ("ssnal_ctx_create", "ssnal_en_solve", "ssnal_gemv_t", "ssnal_active_prox",
+        for name in ("ssnal_ctx_create", "ssnal_en_solve", "ssnal_en_solve_noalloc", "ssnal_gemv_t", "ssnal_active_prox",
                      "ssnal_newton_matrix", "ssnal_cholesky", "ssnal_newton_direction",
                      "ssnal_newton_cg", "ssnal_ls_delta", "ssnal_kkt"):
             getattr(L, name).restype = _i
@@ -226,6 +227,21 @@ def ssnal_en_solve(ctx, A, b, lambda1, lambda2, x0=None, tol=1e-6, x_out=None, m
         nz = int(np.count_nonzero(tr[:, 3]))
         return x_out, d, tr[:nz].copy()
     return x_out, d
+
+
+def ssnal_en_solve_noalloc(ctx, A, b, lambda1, lambda2, x_out, x0=None, tol=1e-6, m=None, opts=None,
+                           stream=None):
+    """ssnal_en_solve with the workspace in the library's static device array
+    (no allocation in the call; m <= 512, n <= 131072).  x_out is required.
+    Returns the info dict."""
+    pA, dt, lda, m, n = _design(A, m)
+    o = opts if opts is not None else make_opts()
+    info = Info()
+    rc = lib().ssnal_en_solve_noalloc(ctx.ptr, pA, dt, lda, _ptr(b), m, n, float(lambda1), float(lambda2),
+                                      _ptr(x0), float(tol), _stream(stream), _ptr(x_out), C.byref(o),
+                                      C.byref(info))
+    _check(rc, allow_warn=True)
+    return info.as_dict()
 
 
 def ssnal_gemv_t(ctx, A, v, w=None, acc64=False, m=None, stream=None):

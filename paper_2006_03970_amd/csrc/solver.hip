@@ -1094,6 +1094,118 @@ size_t ssnal_workspace_bytes(int64_t m, int64_t n) {
 
 }  // extern "C"
 
+// ====================================================================== no-allocation solve
+// ssnal_en_solve_noalloc lays the solve's device workspace out in one
+// file-scope device array instead of the context's grow-only buffers, for
+// callers that cannot allocate.  Each device holds its own copy of the array
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (taken once per device).
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+constexpr int64_t kScratchMaxM = 512;
+constexpr int64_t kScratchMaxN = 131072;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current), looked up on first use.
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(SSNAL_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SSNAL_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return 0;
+}
+
+// Bytes of the split-K Newton-matrix partials (and, after them, the
+// Cholesky's diagonal blocks and their inverses) of any dense system of an
+// m-row solve: split-K keeps ntiles * nsplit <= 1024 + ntiles - 1 tiles of
+// 64 x 64 doubles, ntiles <= T (T + 1) / 2, T = ceil(min(m, 4096) / 64).
+size_t scratch_syrk_bytes(int64_t m) {
+  const int64_t T = (std::min<int64_t>(m, kDenseMax) + 63) / 64;
+  const int64_t tiles = std::max<int64_t>(1024 + T * (T + 1) / 2, 2 * T);
+  return (size_t)tiles * 64 * 64 * sizeof(double);
+}
+
+// Lay an (m, n) workspace out in [base, base + bytes): the buffers of plan_ws
+// in its order (the Newton-matrix partials at their exact bound), 256-byte
+// aligned; the scalar slots stay the context's.  Returns the bytes used, or 0
+// if they do not fit.
+size_t layout_scratch(ssnal_ctx* c, unsigned char* base, size_t bytes, int64_t m, int64_t n, Workspace& w) {
+  WsPlan p = plan_ws(m, n);
+  p.bytes[8] = scratch_syrk_bytes(m);
+  size_t off[10], used = 0;
+  for (int i = 0; i < 10; ++i) {
+    off[i] = used;
+    used += (p.bytes[i] + 255) / 256 * 256;
+  }
+  if (used > bytes) return 0;
+  w.wy = (double*)(base + off[0]);
+  w.wd = (double*)(base + off[1]);
+  w.uJ = (double*)(base + off[2]);
+  w.J = (int32_t*)(base + off[3]);
+  w.counts = (int*)(base + off[4]);
+  w.part = (double*)(base + off[5]);
+  w.gpart = (double*)(base + off[6]);
+  w.V = (double*)(base + off[7]);
+  w.syrk = base + off[8];
+  double* mv = (double*)(base + off[9]);
+  w.y = mv + MV_Y * m;
+  w.g = mv + MV_G * m;
+  w.d = mv + MV_D * m;
+  w.rho = mv + MV_RHO * m;
+  w.t1 = mv + MV_T1 * m;
+  w.t2 = mv + MV_T2 * m;
+  w.t3 = mv + MV_T3 * m;
+  w.scal = (double*)c->scal.p;
+  w.info = (int*)(w.scal + SC_CHOL);
+  return used;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssnal_en_solve_noalloc(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, int64_t lda, const double* b,
+                           int64_t m, int64_t n, double lambda1, double lambda2, const double* x0, double tol,
+                           hipStream_t stream, double* x_out, const ssnal_en_opts* opts, ssnal_en_info* info) {
+  g_err[0] = 0;
+  if (!ctx) return fail(SSNAL_EINVAL, "ctx is null");
+  if (int rc = check_args(A, (int)a_dtype, lda, b, m, n)) return rc;
+  if (m > kScratchMaxM || n > kScratchMaxN)
+    return fail(SSNAL_EINVAL, "m=%lld, n=%lld: the no-allocation solve takes m <= %lld and n <= %lld",
+                (long long)m, (long long)n, (long long)kScratchMaxM, (long long)kScratchMaxN);
+  if (opts && opts->timing)
+    return fail(SSNAL_EINVAL, "opts->timing creates events: not available without allocation");
+  if (opts && opts->newton_cg)
+    return fail(SSNAL_EINVAL, "opts->newton_cg: the no-allocation solve factors the Newton systems");
+  HIPCHK(hipSetDevice(ctx->device));
+  void* base = nullptr;
+  if (int rc = scratch_address(ctx->device, &base)) return rc;
+  Workspace w;
+  if (!layout_scratch(ctx, (unsigned char*)base, kScratchBytes, m, n, w))
+    return fail(SSNAL_EINVAL, "m=%lld, n=%lld needs more than the %zu scratch bytes", (long long)m,
+                (long long)n, kScratchBytes);
+  return solve_impl(ctx, A, (int)a_dtype, lda, b, m, n, lambda1, lambda2, x0, tol, stream, x_out, opts,
+                    info, &w);
+}
+
+}  // extern "C"
+
 // ====================================================================== serving loop
 // Slot i is a host thread with its own context, stream and (for host-resident
 // requests) device buffers for the uploaded A, b and x.  Admission: among the
