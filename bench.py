@@ -17,22 +17,37 @@ solves being measured).
 The CPU baseline is the FP64 oracle on the host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-Further sections in the same JSON line (each can be skipped): the m=1000,
-n=1e6 single solve in FP32/BF16/FP64 (--no-c3); the 100-point SNP-like path
-with gcv / e-bic at every point and 10-fold cross validation (--no-path); a
+Beside `value` the line carries: FP64 and BF16 solves/s on the same problem;
+`roofline_chol`, the FP64 Cholesky factor + solve of the Newton systems
+inside the timed solves (sum of N^3/3 over their duration from HIP events)
+against the FP64 peak; and further sections (each can be skipped): the
+m=100, n=2000 single solve, alone and batched B in {1, 64, 1024} over the
+batch entry's 8 workers (--no-c1); the m=1000, n=1e6 single solve in
+FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
+gcv / e-bic at every point and 10-fold cross validation (--no-path); a
 long-column Newton-CG solve, m=20000, n=2e5 (--no-cg, or --cg-only); the
-Newton-matrix SYRK at its largest dense shape, m=4096 from r=8192 columns, in
-TFLOP/s against the MFMA peak (--no-syrk); the serving stream (--serving 0
+Newton-matrix SYRK at its largest dense shape, m=4096 from r=8192 columns,
+in TFLOP/s against the MFMA peak (--no-syrk); the serving stream (--serving 0
 skips it).
        python bench.py --profile-syrk K     K launches of that SYRK per storage type
 Serving: a stream of requests with the serving workload's distributions (m
 log-uniform in [100, 2000], n log-uniform in [1e4, n_max], Gaussian-Toeplitz
 or SNP-like designs, FP32 or BF16 storage, tol 1e-6) goes through the
-library's serving loop: first closed-loop (all submitted at once) for the
-saturated rate, then open-loop with seeded Poisson arrivals at 0.8x that rate;
-latency is scheduled arrival -> completion.  The serving designs are drawn on
-the GPU (datagen.make_problem_device: same distributions, torch's seeded
-generator).  Default: the full stream of 512 requests with n_max = 5e5.
+library's serving loop with the designs in HBM: every request alone (its
+service time), then closed-loop (all submitted at once) for the saturated
+rate, then open-loop with seeded Poisson arrivals at 0.8x that rate; latency
+is scheduled arrival -> completion, slowdown is latency over the request's
+time alone.  The first --serving-host requests are then served again from
+pinned host memory (uploaded on admission; latency includes the upload), and
+the first 128 in FP64 beside their mixed solves.  The serving designs are
+drawn on the GPU (datagen.make_problem_device: same distributions, torch's
+seeded generator).  Default: the full stream of 512 requests with n_max =
+5e5.
+The CPU-baseline leg times the FP64 oracle on one and on all host threads
+and reports, with the oracle: every C2 solve's error (objective against a
+tight oracle solve on the stored and the original design, support
+difference, eta on both) and a seeded sample of served requests (eta on the
+stored design and the duality-gap bound of the objective error).
 Counter runs (HBM traffic of the A^T v kernel and of a plain copy of the same
 byte count, for the calibration factor):
        python bench.py --profile-gemv K     K launches of the FP32 A^T v pass
@@ -312,14 +327,15 @@ def chol_roofline(infos, label):
 
 
 SYRK_M, SYRK_R = 4096, 8192  # the largest dense Newton matrix: m x m from r columns
-MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA, published
+MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # MI355X dense MFMA, published
 
 
 def syrk_bench(reps=5, launches=0):
     """The Newton matrix I + kappa A_J A_J^T at its largest dense shape (m =
     4096 rows, r = 8192 active columns; FP64 storage on FP64 MFMA, FP32
-    storage on FP32 MFMA): TFLOP/s of the m (m + 1) r flops of the lower
-    triangle against the dense MFMA peak.  launches > 0: only that many calls
+    storage on FP32 MFMA, BF16 storage on BF16 MFMA): TFLOP/s of the
+    m (m + 1) r flops of the lower triangle against the dense MFMA peak of
+    the storage type.  launches > 0: only that many calls
     per storage type (a short run for rocprofv3 counters)."""
     import torch
 
@@ -331,9 +347,9 @@ def syrk_bench(reps=5, launches=0):
     gen = torch.Generator(device=dev).manual_seed(11)
     J = torch.arange(r, dtype=torch.int32, device=dev)
     out = {}
-    for store, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        A = torch.randn((r, m), generator=gen, device=dev, dtype=dt)
-        A /= torch.linalg.vector_norm(A, dim=1, keepdim=True)
+    for store, dt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+        A = torch.randn((r, m), generator=gen, device=dev, dtype=torch.float32)
+        A = (A / torch.linalg.vector_norm(A, dim=1, keepdim=True)).to(dt)
         if launches:
             for k in range(launches):
                 binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
@@ -672,6 +688,7 @@ def main():
     ap.add_argument("--no-path", action="store_true", help="skip the path + model selection section")
     ap.add_argument("--no-cg", action="store_true", help="skip the Newton-CG (m=20000) section")
     ap.add_argument("--cg-only", action="store_true", help="run only the Newton-CG section")
+    ap.add_argument("--c3-only", action="store_true", help="run only the m=1000, n=1e6 section")
     ap.add_argument("--no-c1", action="store_true", help="skip the m=100, n=2000 single/batched section")
     ap.add_argument("--serving", type=int, default=512, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-host", type=int, default=128,
@@ -703,6 +720,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.cg_only:
         print(json.dumps({"newton_cg": cg_bench()}), flush=True)
+        return
+    if args.c3_only:
+        print(json.dumps({"large_single_solve": large_bench()}), flush=True)
         return
     if args.profile_syrk:
         syrk_bench(launches=args.profile_syrk)
