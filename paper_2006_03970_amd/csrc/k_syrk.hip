@@ -9,9 +9,12 @@
 // by a second kernel, which also applies scale/shift and mirrors the result,
 // so V is exactly symmetric and reproducible.
 //
-// FP64 storage runs v_mfma_f64_16x16x4 (FP64 accumulation).  FP32 and BF16
-// storage run v_mfma_f32_16x16x4 with FP32 accumulation inside a split (BF16
-// values are exact in FP32, as are their products).
+// FP64 storage runs v_mfma_f64_16x16x4 (FP64 accumulation), FP32 storage
+// v_mfma_f32_16x16x4 and BF16 storage v_mfma_f32_16x16x32_bf16, both with FP32
+// accumulation inside a split (BF16 values and their products are exact in
+// FP32).
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -167,6 +170,121 @@ __global__ __launch_bounds__(256) void k_syrk_partial(const T* __restrict__ A, i
       }
 }
 
+// BF16 storage on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation): the products of two BF16 values are exact in FP32, as in the
+// FP32 path, but one instruction covers 32 k-values.  A stage holds 64 rows x
+// kKS k-values of each operand in LDS as BF16 with the k-values of a row
+// contiguous (zs[row][k]); a lane's MFMA operand is 8 consecutive k-values of
+// one row, one 16-byte LDS read.  Thread t fetches row t/4, k-values
+// 8 (t % 4) .. + 7: form 1 reads them from one column of A (16 bytes when
+// the column starts allow it), form 0 from eight gathered columns (row a of
+// each, adjacent lanes reading adjacent rows).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBPitch = kKS + 8;  // BF16 elements per LDS row (80 bytes: 16-byte aligned, banks spread)
+
+template <int FORM>
+__device__ __forceinline__ void fetch_bf16(const uint16_t* __restrict__ A, int64_t lda, int N, int64_t K,
+                                           const int32_t* __restrict__ J, int row0, int64_t k0, bool v16,
+                                           uint4& out) {
+  const int t = threadIdx.x;
+  const int a = row0 + t / 4;
+  const int64_t kb = k0 + (t % 4) * 8;
+  const bool aok = a < N;
+  uint16_t v[8];
+  if (FORM == 1) {
+    const uint16_t* col = A + (int64_t)J[aok ? a : N - 1] * lda;
+    if (v16 && kb + 8 <= K) {
+      const uint4 x = *reinterpret_cast<const uint4*>(col + kb);
+      out = aok ? x : uint4{0, 0, 0, 0};
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t k = kb + q;
+      const uint16_t x = col[k < K ? k : K - 1];
+      v[q] = (aok & (k < K)) ? x : (uint16_t)0;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t k = kb + q;
+      const bool kok = k < K;
+      const uint16_t x = A[(int64_t)J[kok ? k : K - 1] * lda + (aok ? a : N - 1)];
+      v[q] = (aok & kok) ? x : (uint16_t)0;
+    }
+  }
+  out.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+  out.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+  out.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+  out.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void k_syrk_partial_bf16(const uint16_t* __restrict__ A, int64_t lda,
+                                                           int N, int64_t K, const int32_t* __restrict__ J,
+                                                           int ntiles, int64_t kchunk, bool v16,
+                                                           double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint16_t zi[kTile][kBPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t zj[kTile][kBPitch];
+  const int tile = blockIdx.x % ntiles;
+  const int split = blockIdx.x / ntiles;
+  int ti, tj;
+  tile_of(tile, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t kb = (int64_t)split * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int wi = wid >> 1, wj = wid & 1;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = flt4{0, 0, 0, 0};
+
+  const int t = threadIdx.x;
+  uint4 ri, rj;
+  fetch_bf16<FORM>(A, lda, N, ke, J, ti * kTile, kb, v16, ri);
+  if (!diag) fetch_bf16<FORM>(A, lda, N, ke, J, tj * kTile, kb, v16, rj);
+  for (int64_t k0 = kb; k0 < ke; k0 += kKS) {
+    __syncthreads();
+    *reinterpret_cast<uint4*>(&zi[t / 4][(t % 4) * 8]) = ri;
+    if (!diag) *reinterpret_cast<uint4*>(&zj[t / 4][(t % 4) * 8]) = rj;
+    __syncthreads();
+    if (k0 + kKS < ke) {
+      fetch_bf16<FORM>(A, lda, N, ke, J, ti * kTile, k0 + kKS, v16, ri);
+      if (!diag) fetch_bf16<FORM>(A, lda, N, ke, J, tj * kTile, k0 + kKS, v16, rj);
+    }
+    uint16_t(*zb)[kBPitch] = diag ? zi : zj;
+    const int kq = 8 * (lane / 16);
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+      a[p] = *reinterpret_cast<const bf16x8*>(&zi[wi * 32 + p * 16 + (lane & 15)][kq]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      b[q] = *reinterpret_cast<const bf16x8*>(&zb[wj * 32 + q * 16 + (lane & 15)][kq]);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p], b[q], acc[p][q], 0, 0, 0);
+  }
+  // accumulator v of a 16 x 16 block holds row 4*(lane/16)+v, column lane%16
+  double* out = part + ((int64_t)split * ntiles + tile) * (kTile * kTile);
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wi * 32 + p * 16 + 4 * (lane / 16) + v;
+        const int c = wj * 32 + q * 16 + (lane & 15);
+        out[r * kTile + c] = (double)acc[p][q][v];
+      }
+}
+
 // One thread per tile element (16 workgroups per tile); the split partials
 // are summed in split order, eight loads in flight.
 __global__ __launch_bounds__(256) void k_syrk_finish(const double* __restrict__ part, int N,
@@ -235,7 +353,17 @@ static hipError_t launch_syrk(const T* A, int64_t lda, int m, const int32_t* J, 
   SyrkPlan p = plan(form, m, r);
   if (p.N <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(p.ntiles * p.nsplit);
-  if (form == 0)
+  if (std::is_same<T, uint16_t>::value) {
+    // 16-byte fetches of a column need 16-byte aligned column starts
+    const bool v16 = ((uintptr_t)A % 16 == 0) && (lda % 8 == 0);
+    const uint16_t* Ab = reinterpret_cast<const uint16_t*>(A);
+    if (form == 0)
+      hipLaunchKernelGGL((k_syrk_partial_bf16<0>), dim3(nb), dim3(256), 0, st, Ab, lda, p.N, p.K, J,
+                         p.ntiles, p.kchunk, v16, work);
+    else
+      hipLaunchKernelGGL((k_syrk_partial_bf16<1>), dim3(nb), dim3(256), 0, st, Ab, lda, p.N, p.K, J,
+                         p.ntiles, p.kchunk, v16, work);
+  } else if (form == 0)
     hipLaunchKernelGGL((k_syrk_partial<T, 0>), dim3(nb), dim3(256), 0, st, A, lda, p.N, p.K, J,
                        p.ntiles, p.kchunk, work);
   else
