@@ -285,21 +285,310 @@ __global__ __launch_bounds__(256) void k_syrk_partial_bf16(const uint16_t* __res
       }
 }
 
-// One thread per tile element (16 workgroups per tile); the split partials
+// ---- 128 x 128 output tiles for the large systems (K of thousands of
+// columns and more: the early Newton steps of an m = 1000, n = 10^6 solve
+// contract over r = 5 * 10^5 active columns).  Four waves, each a 64 x 64
+// quarter as 4 x 4 blocks of 16 x 16 accumulators, so every operand read
+// from LDS feeds four MFMAs; a stage is 128 bytes of k per row (16 FP64, 32
+// FP32 or 64 BF16 values) for both operand panels, double-buffered in LDS
+// (one barrier a stage) with the next stage's 16-byte global loads in flight
+// during the current stage's MFMAs; registers are held to 256 a lane so
+// that two workgroups share a CU (64 KB of LDS each).  LDS holds each operand row's k-values
+// contiguously in 16-byte chunks, chunk c of row a at a * 128 + 16 (c ^
+// ((a >> 1) & 7)) bytes, so the 16 rows of one MFMA operand read hit
+// distinct banks.  Lane group g = lane / 16 reads chunk 4q + g of its row:
+// for FP32 and FP64 the elements of that chunk feed consecutive MFMA steps
+// (step e of read q contracts k = 4q*EPB + g*EPB + e over the four groups),
+// for BF16 the chunk is one 16x16x32 operand; both operands use the same
+// assignment, so every k of the stage is contracted exactly once.
+//   form 1 (k contiguous in A): thread t loads chunks t + 256 q of a panel,
+//     row (t + 256 q) / 8, chunk t % 8, straight into LDS;
+//   form 0 (rows contiguous in A): a thread loads EPB-row chunks of
+//     several gathered columns and transposes them in registers into
+//     row chunks (adjacent lanes read adjacent rows of one column).
+constexpr int kBT = 128;                 // output tile
+constexpr int kRowB = 128;               // bytes of k per operand row and stage
+constexpr int kPanelB = kBT * kRowB;     // 16 KB
+
+template <typename T> struct BigT;
+template <> struct BigT<double> { using V4 = dbl4; static constexpr int EPB = 2; };
+template <> struct BigT<float> { using V4 = flt4; static constexpr int EPB = 4; };
+template <> struct BigT<uint16_t> { using V4 = flt4; static constexpr int EPB = 8; };
+
+__device__ __forceinline__ int swz(int row, int chunk) { return row * kRowB + ((chunk ^ ((row >> 1) & 7)) << 4); }
+
+// zero the elements of a 16-byte chunk from element nv on (nv in 0..EPB)
+template <typename T>
+__device__ __forceinline__ uint4 keep_first(uint4 v, int nv) {
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  constexpr int EPB = 16 / (int)sizeof(T);
+#pragma unroll
+  for (int e = 0; e < EPB; ++e) {
+    const bool z = e >= nv;
+    if (sizeof(T) == 8) {
+      w[2 * e] = z ? 0u : w[2 * e];
+      w[2 * e + 1] = z ? 0u : w[2 * e + 1];
+    } else if (sizeof(T) == 4) {
+      w[e] = z ? 0u : w[e];
+    } else {
+      const uint32_t m = (e & 1) ? 0xffff0000u : 0x0000ffffu;
+      w[e >> 1] = z ? (w[e >> 1] & ~m) : w[e >> 1];
+    }
+  }
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// Global loads of one operand panel's stage (4 x 16 bytes per thread).
+template <typename T, int FORM>
+__device__ __forceinline__ void big_fetch(const T* __restrict__ A, int64_t lda, int N, int64_t K,
+                                          const int32_t* __restrict__ J, int row0, int64_t k0,
+                                          uint4 (&v)[4]) {
+  constexpr int EPB = BigT<T>::EPB;
+  const int t = threadIdx.x;
+  if (FORM == 1) {
+    // chunk c = t + 256 q: row c / 8, elements k0 + EPB (c % 8) ..
+    const int64_t kc = k0 + (int64_t)EPB * (t & 7);
+    const int64_t klast = (K - 1) / EPB * EPB;  // last chunk start inside the column
+    const int nv = (int)(K - kc < EPB ? (K - kc > 0 ? K - kc : 0) : EPB);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = row0 + (t >> 3) + 32 * q;
+      const bool aok = a < N;
+      const T* col = A + (int64_t)J[aok ? a : N - 1] * lda;
+      const uint4 x = *reinterpret_cast<const uint4*>(col + (kc < klast ? kc : klast));
+      v[q] = keep_first<T>(x, aok ? nv : 0);
+    }
+  } else if (EPB == 4) {
+    // 32 row groups of 4 x 8 groups of 4 columns: rows 4 (t % 32) .., columns 4 (t / 32) + q
+    const int a = row0 + 4 * (t & 31);
+    const int nv = N - a < 4 ? (N - a > 0 ? N - a : 0) : 4;
+    const int ac = nv > 0 ? a : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = k0 + 4 * (t >> 5) + q;
+      const bool kok = k < K;
+      const uint4 x = *reinterpret_cast<const uint4*>(A + (int64_t)J[kok ? k : K - 1] * lda + ac);
+      v[q] = keep_first<T>(x, kok ? nv : 0);
+    }
+  } else if (EPB == 2) {
+    // two blocks of 2 rows x 2 columns: rows 2 (b % 64) .., columns 2 (b / 64) + j, b = t + 256 h
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = t + 256 * h;
+      const int a = row0 + 2 * (b & 63);
+      const int nv = N - a < 2 ? (N - a > 0 ? N - a : 0) : 2;
+      const int ac = nv > 0 ? a : 0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t k = k0 + 2 * (b >> 6) + j;
+        const bool kok = k < K;
+        const uint4 x = *reinterpret_cast<const uint4*>(A + (int64_t)J[kok ? k : K - 1] * lda + ac);
+        v[2 * h + j] = keep_first<T>(x, kok ? nv : 0);
+      }
+    }
+  } else {
+    // BF16: rows 8 (t % 16) .., columns 4 (t / 16) + q
+    const int a = row0 + 8 * (t & 15);
+    const int nv = N - a < 8 ? (N - a > 0 ? N - a : 0) : 8;
+    const int ac = nv > 0 ? a : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = k0 + 4 * (t >> 4) + q;
+      const bool kok = k < K;
+      const uint4 x = *reinterpret_cast<const uint4*>(A + (int64_t)J[kok ? k : K - 1] * lda + ac);
+      v[q] = keep_first<T>(x, kok ? nv : 0);
+    }
+  }
+}
+
+// The staged chunks into an LDS panel (layout above).
+template <typename T, int FORM>
+__device__ __forceinline__ void big_store(const uint4 (&v)[4], unsigned char* __restrict__ P) {
+  constexpr int EPB = BigT<T>::EPB;
+  const int t = threadIdx.x;
+  if (FORM == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(P + swz((t >> 3) + 32 * q, t & 7)) = v[q];
+  } else if (EPB == 4) {
+    // v[q] = rows a..a+3 of column q; row i gets {v[0].i, v[1].i, v[2].i, v[3].i}
+    const int r = 4 * (t & 31), c = t >> 5;
+    const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w}, {v[1].x, v[1].y, v[1].z, v[1].w},
+                              {v[2].x, v[2].y, v[2].z, v[2].w}, {v[3].x, v[3].y, v[3].z, v[3].w}};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<uint4*>(P + swz(r + i, c)) = uint4{w[0][i], w[1][i], w[2][i], w[3][i]};
+  } else if (EPB == 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = t + 256 * h;
+      const int r = 2 * (b & 63), c = b >> 6;
+      const uint4 x0 = v[2 * h], x1 = v[2 * h + 1];  // columns 2c, 2c+1; rows r, r+1 in .xy / .zw
+      *reinterpret_cast<uint4*>(P + swz(r, c)) = uint4{x0.x, x0.y, x1.x, x1.y};
+      *reinterpret_cast<uint4*>(P + swz(r + 1, c)) = uint4{x0.z, x0.w, x1.z, x1.w};
+    }
+  } else {
+    // BF16: v[q] = rows r..r+7 of column 4 (t / 16) + q; row i gets 4 values, 8 bytes,
+    // half (t / 16) % 2 of chunk (t / 16) / 2
+    const int r = 8 * (t & 15), kq = t >> 4;
+    const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w}, {v[1].x, v[1].y, v[1].z, v[1].w},
+                              {v[2].x, v[2].y, v[2].z, v[2].w}, {v[3].x, v[3].y, v[3].z, v[3].w}};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int sh = 16 * (i & 1);
+      const uint32_t e0 = (w[0][i >> 1] >> sh) & 0xffffu, e1 = (w[1][i >> 1] >> sh) & 0xffffu;
+      const uint32_t e2 = (w[2][i >> 1] >> sh) & 0xffffu, e3 = (w[3][i >> 1] >> sh) & 0xffffu;
+      *reinterpret_cast<uint2*>(P + swz(r + i, kq >> 1) + 8 * (kq & 1)) = uint2{e0 | (e1 << 16), e2 | (e3 << 16)};
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void big_mfma(const uint4* a, const uint4* b, typename BigT<T>::V4 (&acc)[4][4]);
+
+template <>
+__device__ __forceinline__ void big_mfma<float>(const uint4* a, const uint4* b, flt4 (&acc)[4][4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float x[4], y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t ua[4] = {a[i].x, a[i].y, a[i].z, a[i].w};
+      const uint32_t ub[4] = {b[i].x, b[i].y, b[i].z, b[i].w};
+      x[i] = __uint_as_float(ua[e]);
+      y[i] = __uint_as_float(ub[e]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i], y[j], acc[i][j], 0, 0, 0);
+  }
+}
+template <>
+__device__ __forceinline__ void big_mfma<double>(const uint4* a, const uint4* b, dbl4 (&acc)[4][4]) {
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    double x[4], y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t la = e ? a[i].z : a[i].x, ha = e ? a[i].w : a[i].y;
+      const uint32_t lb = e ? b[i].z : b[i].x, hb = e ? b[i].w : b[i].y;
+      x[i] = __hiloint2double((int)ha, (int)la);
+      y[i] = __hiloint2double((int)hb, (int)lb);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], y[j], acc[i][j], 0, 0, 0);
+  }
+}
+template <>
+__device__ __forceinline__ void big_mfma<uint16_t>(const uint4* a, const uint4* b, flt4 (&acc)[4][4]) {
+  bf16x8 x[4], y[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    x[i] = __builtin_bit_cast(bf16x8, a[i]);
+    y[i] = __builtin_bit_cast(bf16x8, b[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[i], y[j], acc[i][j], 0, 0, 0);
+}
+
+template <typename T, int FORM>
+__global__ __launch_bounds__(256, 2) void k_syrk_big(const T* __restrict__ A, int64_t lda, int N, int64_t K,
+                                                  const int32_t* __restrict__ J, int ntiles,
+                                                  int64_t kchunk, double* __restrict__ part) {
+  using V4 = typename BigT<T>::V4;
+  constexpr int KS = kRowB / (int)sizeof(T);  // k-values per stage
+  __shared__ __attribute__((aligned(16))) unsigned char lds[4 * kPanelB];  // [buffer][operand]
+  const int tile = blockIdx.x % ntiles;
+  const int split = blockIdx.x / ntiles;
+  int ti, tj;
+  tile_of(tile, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t kb = (int64_t)split * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int wi = wid >> 1, wj = wid & 1;
+  // a diagonal tile's lower-left quarter is never read: its wave only stages
+  const bool work = !(diag && wi > wj);
+  V4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+  uint4 ri[4], rj[4];
+  big_fetch<T, FORM>(A, lda, N, ke, J, ti * kBT, kb, ri);
+  if (!diag) big_fetch<T, FORM>(A, lda, N, ke, J, tj * kBT, kb, rj);
+  big_store<T, FORM>(ri, lds);
+  if (!diag) big_store<T, FORM>(rj, lds + kPanelB);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += KS) {
+    const bool more = k0 + KS < ke;
+    if (more) {
+      big_fetch<T, FORM>(A, lda, N, ke, J, ti * kBT, k0 + KS, ri);
+      if (!diag) big_fetch<T, FORM>(A, lda, N, ke, J, tj * kBT, k0 + KS, rj);
+    }
+    const unsigned char* Pi = lds + (2 * buf) * kPanelB;
+    const unsigned char* Pj = diag ? Pi : Pi + kPanelB;
+    if (work) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ch = 4 * q + (lane >> 4);
+        uint4 a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[i] = *reinterpret_cast<const uint4*>(Pi + swz(wi * 64 + 16 * i + (lane & 15), ch));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[j] = *reinterpret_cast<const uint4*>(Pj + swz(wj * 64 + 16 * j + (lane & 15), ch));
+        big_mfma<T>(a, b, acc);
+      }
+    }
+    if (more) {
+      unsigned char* Qi = lds + (2 * (buf ^ 1)) * kPanelB;
+      big_store<T, FORM>(ri, Qi);
+      if (!diag) big_store<T, FORM>(rj, Qi + kPanelB);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // accumulator v of a 16 x 16 block: row 4*(lane/16)+v (FP32 acc) or lane/16 + 4v (FP64), column lane%16
+  double* out = part + ((int64_t)split * ntiles + tile) * (kBT * kBT);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = std::is_same<T, double>::value ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+        const int r = wi * 64 + 16 * i + rr;
+        const int c = wj * 64 + 16 * j + (lane & 15);
+        out[r * kBT + c] = work ? (double)acc[i][j][v] : 0.0;
+      }
+}
+
+// One thread per tile element (TL*TL/256 workgroups per tile); the split partials
 // are summed in split order, eight loads in flight.
+template <int TL>
 __global__ __launch_bounds__(256) void k_syrk_finish(const double* __restrict__ part, int N,
                                                      int ntiles, int nsplit, double shift,
                                                      double scale, double* __restrict__ out) {
-  const int tile = blockIdx.x / 16;
-  const int e = (blockIdx.x % 16) * 256 + threadIdx.x;
+  constexpr int kPer = TL * TL / 256;  // workgroups per tile
+  const int tile = blockIdx.x / kPer;
+  const int e = (blockIdx.x % kPer) * 256 + threadIdx.x;
   int ti, tj;
   tile_of(tile, ti, tj);
-  const int li = e / kTile, lj = e % kTile;
-  const int i = ti * kTile + li, j = tj * kTile + lj;
+  const int li = e / TL, lj = e % TL;
+  const int i = ti * TL + li, j = tj * TL + lj;
   if (i >= N || j >= N) return;
   if (ti == tj && li > lj) return;  // diagonal tile: upper half, mirrored below
-  const double* src = part + (int64_t)tile * (kTile * kTile) + e;
-  const int64_t stride = (int64_t)ntiles * (kTile * kTile);
+  const double* src = part + (int64_t)tile * (TL * TL) + e;
+  const int64_t stride = (int64_t)ntiles * (TL * TL);
   double s = 0.0;
   int sp = 0;
   for (; sp + 8 <= nsplit; sp += 8) {
@@ -340,16 +629,74 @@ SyrkPlan plan(int form, int m, int64_t r) {
   if (p.nsplit < 1) p.nsplit = 1;
   return p;
 }
+
+// The 128-tile kernel: one round of at most 512 workgroups (two per CU; a
+// second, part-filled round would double the time) from the split of K, at
+// least 256 k-values a split, and no more partial tiles than fit the workspace:
+// (1024 + T64 (T64 + 1) / 2) tiles of 64 x 64 up to N = 512 (the bound of
+// the no-allocation entry point, whose m is at most 512), twice the 1024
+// beyond; nsplit = 0 when not even one split fits.
+SyrkPlan plan_big(int form, int m, int64_t r) {
+  SyrkPlan p;
+  p.N = form == 0 ? m : (int)r;
+  p.K = form == 0 ? r : m;
+  p.T = (p.N + kBT - 1) / kBT;
+  p.ntiles = p.T * (p.T + 1) / 2;
+  const int64_t t64 = (p.N + kTile - 1) / kTile;
+  const int64_t cap = ((p.N > 512 ? 2048 : 1024) + t64 * (t64 + 1) / 2) / 4 / p.ntiles;
+  int64_t s = p.ntiles <= 512 ? 512 / p.ntiles : 1;
+  const int64_t maxs = (p.K + 255) / 256;
+  if (s > maxs) s = maxs;
+  if (s > cap) s = cap;
+  if (s < 1) {
+    p.nsplit = 0;
+    p.kchunk = 0;
+    return p;
+  }
+  int64_t kc = (p.K + s - 1) / s;
+  kc = (kc + 63) / 64 * 64;
+  p.kchunk = kc;
+  p.nsplit = (int)((p.K + kc - 1) / kc);
+  return p;
+}
+
+// The large systems (N >= 256 outputs over K >= 4096 terms) go to the
+// 128-tile kernel when its 16-byte loads are aligned: A on 16 bytes and a
+// column pitch of whole 16-byte chunks.
+bool use_big(int form, int m, int64_t r, const void* A, int64_t lda, int esize) {
+  const int64_t N = form == 0 ? m : r, K = form == 0 ? r : m;
+  if (N < 256 || K < 4096) return false;
+  if ((uintptr_t)A % 16 != 0 || (lda * esize) % 16 != 0) return false;
+  return plan_big(form, m, r).nsplit >= 1;
+}
 }  // namespace
 
 size_t syrk_workspace_bytes(int form, int m, int64_t r) {
   SyrkPlan p = plan(form, m, r);
-  return (size_t)p.nsplit * p.ntiles * kTile * kTile * sizeof(double);
+  size_t b = (size_t)p.nsplit * p.ntiles * kTile * kTile * sizeof(double);
+  SyrkPlan q = plan_big(form, m, r);
+  const size_t c = (size_t)q.nsplit * q.ntiles * kBT * kBT * sizeof(double);
+  return c > b ? c : b;
 }
 
 template <typename T>
 static hipError_t launch_syrk(const T* A, int64_t lda, int m, const int32_t* J, int64_t r, int form,
                               double shift, double scale, double* out, double* work, hipStream_t st) {
+  if (use_big(form, m, r, A, lda, (int)sizeof(T))) {
+    SyrkPlan q = plan_big(form, m, r);
+    const unsigned nb = (unsigned)(q.ntiles * q.nsplit);
+    if (form == 0)
+      hipLaunchKernelGGL((k_syrk_big<T, 0>), dim3(nb), dim3(256), 0, st, A, lda, q.N, q.K, J, q.ntiles,
+                         q.kchunk, work);
+    else
+      hipLaunchKernelGGL((k_syrk_big<T, 1>), dim3(nb), dim3(256), 0, st, A, lda, q.N, q.K, J, q.ntiles,
+                         q.kchunk, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_syrk_finish<kBT>, dim3(q.ntiles * (kBT * kBT / 256)), dim3(256), 0, st, work, q.N,
+                       q.ntiles, q.nsplit, shift, scale, out);
+    return hipGetLastError();
+  }
   SyrkPlan p = plan(form, m, r);
   if (p.N <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(p.ntiles * p.nsplit);
@@ -371,7 +718,7 @@ static hipError_t launch_syrk(const T* A, int64_t lda, int m, const int32_t* J, 
                        p.ntiles, p.kchunk, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_syrk_finish, dim3(p.ntiles * 16), dim3(256), 0, st, work, p.N, p.ntiles,
+  hipLaunchKernelGGL(k_syrk_finish<kTile>, dim3(p.ntiles * 16), dim3(256), 0, st, work, p.N, p.ntiles,
                      p.nsplit, shift, scale, out);
   return hipGetLastError();
 }

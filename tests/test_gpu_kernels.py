@@ -104,7 +104,10 @@ def _active(m, n, r, seed):
 NM_CASES = [(100, 500, 60), (100, 2000, 400), (130, 700, 250), (500, 4000, 900), (500, 4000, 37),
             (257, 3000, 200), (64, 100, 64),
             # the m x m system at the serving workload's largest m, and past it
-            (1000, 6000, 1500), (2000, 8000, 2600), (2000, 8000, 700)]
+            (1000, 6000, 1500), (2000, 8000, 2600), (2000, 8000, 700),
+            # 128-tile kernel (N >= 256 outputs over K >= 4096 terms): ragged N
+            # and K, with the column pitch a whole number of 16-byte chunks
+            (296, 9000, 5000), (520, 12000, 4100)]
 
 
 @pytest.mark.parametrize("m,n,r", NM_CASES)
@@ -127,6 +130,30 @@ def test_newton_matrix(gpu, ctx, orc, m, n, r, store):
         Wr = orc.smw_matrix(AT64, J, kappa)
         assert np.array_equal(W, W.T)
         assert np.max(np.abs(W - Wr)) <= tol * max(1.0, np.max(np.abs(Wr)))
+
+
+# r x r system of the Woodbury form over long columns (K = m >= 4096): the
+# 128-tile kernel where the column pitch is a whole number of 16-byte chunks
+# (m = 4104 for every storage; m = 4100 is one for FP32 and FP64 but not for
+# BF16, which takes the 64-tile kernel), and a padded pitch
+SMW_LONG_CASES = [(4104, 5000, 300, None), (4100, 5000, 257, None), (4100, 3000, 390, 4112)]
+
+
+@pytest.mark.parametrize("m,n,r,lda", SMW_LONG_CASES)
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+def test_smw_matrix_long_columns(gpu, ctx, orc, m, n, r, lda, store):
+    import torch
+    _say("smw_matrix long", m, n, r, lda, store)
+    AT, AT64 = _design(m, n, 11 + m + r, store)
+    J = _active(m, n, r, m + 3 * r)
+    kappa = 1.7
+    A = _dev(AT, store, lda=lda)
+    Jd = torch.from_numpy(J).cuda()
+    tol = 1e-12 if store == "f64" else 3e-6
+    W = gpu.ssnal_newton_matrix(ctx, A, Jd, kappa, 1, m=m).cpu().numpy()
+    Wr = orc.smw_matrix(AT64, J, kappa)
+    assert np.array_equal(W, W.T)
+    assert np.max(np.abs(W - Wr)) <= tol * max(1.0, np.max(np.abs(Wr)))
 
 
 # ----------------------------------------------------------------- Cholesky
