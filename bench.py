@@ -20,7 +20,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Beside `value` the line carries: FP64 and BF16 solves/s on the same problem;
 `roofline_chol`, the FP64 Cholesky factor + solve of the Newton systems
 inside the timed solves (sum of N^3/3 over their duration from HIP events)
-against the FP64 peak; and further sections (each can be skipped): the
+against the FP64 peak; `concurrent`, 64 copies of the same solve through
+the batch entry on 4 and 8 workers (aggregate solves/s of independent
+solves sharing the GPU, FP32 and FP64 storage); and further sections (each
+can be skipped): the
 m=100, n=2000 single solve, alone and batched B in {1, 64, 1024} over the
 batch entry's 8 workers (--no-c1); the m=1000, n=1e6 single solve in
 FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
@@ -301,6 +304,35 @@ def c1_bench(single_reps=200, batches=(1, 64, 1024)):
     out["batched"]["workers"] = 8
     del probs
     torch.cuda.empty_cache()
+    return out
+
+
+def c2_concurrent(ctx, designs, b, p, stream, copies=64, workers=(4, 8)):
+    """The same block-Toeplitz solve, `copies` times, through
+    ssnal_en_solve_batch on W concurrent workers (own streams): the
+    aggregate solves/s when independent solves share the GPU.  One solve is
+    latency-bound (its Cholesky steps run on a few CUs), so the single-solve
+    rate above is the headline and this is the throughput beside it."""
+    import torch
+
+    from paper_2006_03970_amd import binding
+
+    out = {"copies": copies}
+    for label, A in designs.items():
+        probs = [dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol,
+                      x_out=torch.empty(p.n, dtype=torch.float64, device=A.device)) for _ in range(copies)]
+        res = {}
+        for w in workers:
+            binding.ssnal_en_solve_batch(ctx, probs[:2 * w], stream=stream, workers=w)  # warm the workers
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            infos, rc = binding.ssnal_en_solve_batch(ctx, probs, stream=stream, workers=w)
+            el = time.perf_counter() - t
+            res[str(w)] = {"solves_per_s": copies / el, "worst_status": rc,
+                           "max_eta": max(i["kkt_rel"] for i in infos)}
+            print(f"[bench] c2 concurrent {label} x{w}: {copies / el:.0f} solves/s", file=sys.stderr, flush=True)
+        out[label] = res
+        del probs
     return out
 
 
@@ -845,6 +877,7 @@ def main():
 
     out["roofline_chol"] = chol_roofline(inf32, "FP32-stored design (FP64 factor)")
     out["roofline_chol_fp64"] = chol_roofline(inf64, "FP64 design")
+    out["concurrent"] = c2_concurrent(ctx, {"mixed_f32": A32, "fp64": A64}, b, p64, stream)
     xs_gpu = {"mixed_f32": x32.cpu().numpy(), "fp64": x64.cpu().numpy(), "mixed_bf16": xbf.cpu().numpy()}
     del A64, Abf
     torch.cuda.empty_cache()
