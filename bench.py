@@ -30,7 +30,8 @@ FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
 gcv / e-bic at every point and 10-fold cross validation (--no-path); a
 long-column Newton-CG solve, m=20000, n=2e5 (--no-cg, or --cg-only); the
 Newton-matrix SYRK at its largest dense shape, m=4096 from r=8192 columns,
-in TFLOP/s against the MFMA peak (--no-syrk); the serving stream (--serving 0
+and at the first Newton step of the m=1000, n=1e6 solve, m=1000 from
+r=520000 columns, in TFLOP/s against the MFMA peak (--no-syrk); the serving stream (--serving 0
 skips it).
        python bench.py --profile-syrk K     K launches of that SYRK per storage type
 Serving: a stream of requests with the serving workload's distributions (m
@@ -363,45 +364,52 @@ MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # MI355X dense MFMA
 
 
 def syrk_bench(reps=5, launches=0):
-    """The Newton matrix I + kappa A_J A_J^T at its largest dense shape (m =
-    4096 rows, r = 8192 active columns; FP64 storage on FP64 MFMA, FP32
-    storage on FP32 MFMA, BF16 storage on BF16 MFMA): TFLOP/s of the
-    m (m + 1) r flops of the lower triangle against the dense MFMA peak of
-    the storage type.  launches > 0: only that many calls
-    per storage type (a short run for rocprofv3 counters)."""
+    """The Newton matrix I + kappa A_J A_J^T at two shapes: the largest dense
+    one (m = 4096 rows, r = 8192 active columns) and the first Newton step of
+    the m = 1000, n = 1e6 solve (m = 1000 from r = 520000 columns, the
+    active set of its first iteration); FP64 storage on FP64 MFMA, FP32 on
+    FP32 MFMA, BF16 on BF16 MFMA.  TFLOP/s of the m (m + 1) r flops of the
+    triangle against the dense MFMA peak of the storage type.  launches > 0:
+    only that many calls per shape and storage type (a short run for
+    rocprofv3 counters)."""
     import torch
 
     from paper_2006_03970_amd import binding
 
-    m, r = SYRK_M, SYRK_R
     dev = torch.device("cuda:0")
     ctx = binding.Context(0)
     gen = torch.Generator(device=dev).manual_seed(11)
-    J = torch.arange(r, dtype=torch.int32, device=dev)
     out = {}
-    for store, dt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
-        A = torch.randn((r, m), generator=gen, device=dev, dtype=torch.float32)
-        A = (A / torch.linalg.vector_norm(A, dim=1, keepdim=True)).to(dt)
-        if launches:
-            for k in range(launches):
-                binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
-                print(f"[bench] syrk {store} launch {k}", file=sys.stderr, flush=True)
-            continue
-        binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
+    for key, (m, r) in (("dense_max", (SYRK_M, SYRK_R)), ("first_newton_step_m1000", (1000, 520000))):
+        J = torch.arange(r, dtype=torch.int32, device=dev)
+        res = {}
+        for store, dt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+            A = torch.randn((r, m), generator=gen, device=dev, dtype=torch.float32)
+            A = (A / torch.linalg.vector_norm(A, dim=1, keepdim=True)).to(dt)
+            if launches:
+                for k in range(launches):
+                    binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
+                    print(f"[bench] syrk {key} {store} launch {k}", file=sys.stderr, flush=True)
+                del A
+                continue
             binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
-        el = (time.perf_counter() - t) / reps
-        tfs = m * (m + 1) * r / el / 1e12
-        out[store] = {"ms": el * 1e3, "tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[store],
-                      "frac": tfs / MFMA_PEAK_TFS[store]}
-        print(f"[bench] syrk {store}: {el * 1e3:.2f} ms, {tfs:.1f} TFLOP/s", file=sys.stderr, flush=True)
-        del A
-    if launches:
-        return None
-    out["shape"] = {"m": m, "r": r, "flops": m * (m + 1) * r}
-    return out
+            torch.cuda.synchronize()
+            n_rep = reps if m * m * r < 2e11 else 3
+            t = time.perf_counter()
+            for _ in range(n_rep):
+                binding.ssnal_newton_matrix(ctx, A, J, 0.5, 0)
+            el = (time.perf_counter() - t) / n_rep
+            tfs = m * (m + 1) * r / el / 1e12
+            res[store] = {"ms": el * 1e3, "tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[store],
+                          "frac": tfs / MFMA_PEAK_TFS[store]}
+            print(f"[bench] syrk {key} {store}: {el * 1e3:.2f} ms, {tfs:.1f} TFLOP/s", file=sys.stderr,
+                  flush=True)
+            del A
+        res["shape"] = {"m": m, "r": r, "flops": m * (m + 1) * r}
+        out[key] = res
+        del J
+        torch.cuda.empty_cache()
+    return None if launches else out
 
 
 def _pinned_pool(sizes, chunk=4 << 30):
