@@ -22,8 +22,8 @@ Beside `value` the line carries: FP64 and BF16 solves/s on the same problem;
 inside the timed solves (sum of N^3/3 over their duration from HIP events)
 against the FP64 peak; `concurrent`, 64 copies of the same solve through
 the batch entry on 4 and 8 workers (aggregate solves/s of independent
-solves sharing the GPU, FP32 and FP64 storage); and further sections (each
-can be skipped): the
+solves sharing the GPU, FP32 and FP64 storage; --no-concurrent); and
+further sections (each can be skipped): the
 m=100, n=2000 single solve, alone and batched B in {1, 64, 1024} over the
 batch entry's 8 workers (--no-c1); the m=1000, n=1e6 single solve in
 FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
@@ -742,6 +742,8 @@ def main():
     ap.add_argument("--profile-syrk", type=int, default=0,
                     help="only K launches of the m=4096, r=8192 Newton-matrix SYRK per storage type")
     ap.add_argument("--no-syrk", action="store_true", help="skip the Newton-matrix SYRK section")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the concurrent copies of the block-Toeplitz solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -885,7 +887,8 @@ def main():
 
     out["roofline_chol"] = chol_roofline(inf32, "FP32-stored design (FP64 factor)")
     out["roofline_chol_fp64"] = chol_roofline(inf64, "FP64 design")
-    out["concurrent"] = c2_concurrent(ctx, {"mixed_f32": A32, "fp64": A64}, b, p64, stream)
+    if not args.no_concurrent:
+        out["concurrent"] = c2_concurrent(ctx, {"mixed_f32": A32, "fp64": A64}, b, p64, stream)
     xs_gpu = {"mixed_f32": x32.cpu().numpy(), "fp64": x64.cpu().numpy(), "mixed_bf16": xbf.cpu().numpy()}
     del A64, Abf
     torch.cuda.empty_cache()
