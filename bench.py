@@ -291,9 +291,28 @@ def c1_bench(single_reps=200, batches=(1, 64, 1024)):
     out = {"workload": "Gaussian elastic net, m=100, n=2000, k=10, snr=5, alpha=0.5, c_lambda=0.5, "
                        "FP64, tol 1e-10",
            "single": {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "status": info["status"],
-                      "iterations": [info["outer_iters"], info["newton_iters"]], "eta": info["kkt_rel"]},
+                      "iterations": [info["outer_iters"], info["newton_iters"]], "eta": info["kkt_rel"],
+                      "one_workgroup": info["one_workgroup"]},
            "batched": {}}
-    binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream)  # creates the workers
+    print(f"[bench] c1 single: {1.0 / el:.0f} solves/s (one workgroup: {info['one_workgroup']})",
+          file=sys.stderr, flush=True)
+    # the multi-kernel path on the same problem (opts.no_small = 1), for comparison
+    multi = binding.make_opts(no_small=1)
+    for _ in range(3):
+        binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                               x_out=q["x_out"], stream=stream, opts=multi)
+    torch.cuda.synchronize()
+    reps = max(single_reps // 4, 10)
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, info = binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                                         x_out=q["x_out"], stream=stream, opts=multi)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / reps
+    out["single_multi_kernel"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "status": info["status"],
+                                  "iterations": [info["outer_iters"], info["newton_iters"]]}
+    binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream)
+    binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream, opts=binding.make_opts(no_small=1))  # workers
     for B in batches:
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -302,7 +321,17 @@ def c1_bench(single_reps=200, batches=(1, 64, 1024)):
         out["batched"][str(B)] = {"solves_per_s": B / el, "ms": el * 1e3, "worst_status": rc,
                                   "max_eta": max(i["kkt_rel"] for i in infos)}
         print(f"[bench] c1 batch {B}: {B / el:.0f} solves/s", file=sys.stderr, flush=True)
-    out["batched"]["workers"] = 8
+    out["batched"]["launch"] = "one launch, one workgroup per problem"
+    out["batched_multi_kernel"] = {}
+    for B in batches:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos, rc = binding.ssnal_en_solve_batch(ctx, probs[:B], stream=stream,
+                                                 opts=binding.make_opts(no_small=1))
+        el = time.perf_counter() - t
+        out["batched_multi_kernel"][str(B)] = {"solves_per_s": B / el, "ms": el * 1e3, "worst_status": rc}
+        print(f"[bench] c1 batch {B} multi-kernel: {B / el:.0f} solves/s", file=sys.stderr, flush=True)
+    out["batched_multi_kernel"]["workers"] = 8
     del probs
     torch.cuda.empty_cache()
     return out

@@ -87,6 +87,12 @@ typedef struct {
   int32_t workers;       /* ssnal_en_solve_batch: <= 0: 8 concurrent workers (own context and
                             stream each, kept by the context); 1 = every problem in turn on
                             the caller's stream */
+  int32_t no_small;      /* 0 = a problem with A in FP64, m <= 120 and m n <= 2^19 runs its
+                            whole solve (Algorithm 1: both loops, the stopping tests, the
+                            certificates) in one workgroup, one launch and one host wait,
+                            unless trace, timing or newton_cg is asked for; a batch runs its
+                            such problems (m n <= 2^21) as one launch, one workgroup each
+                            (default); 1 = never */
 } ssnal_en_opts;
 
 typedef struct {
@@ -119,6 +125,7 @@ typedef struct {
                             directions ... */
   double chol_ms;        /* ... their summed durations (HIP events on the solve's stream) ... */
   double chol_gflop;     /* ... and their summed N^3/3 flops, in GFLOP */
+  int32_t one_workgroup; /* 1 when the solve ran in one workgroup (see opts.no_small) */
 } ssnal_en_info;
 
 /* Fill *opts with the defaults listed above. */

@@ -31,7 +31,8 @@ class Opts(C.Structure):
                 ("max_inner", C.c_int32), ("max_backtrack", C.c_int32), ("no_refine", C.c_int32),
                 ("no_smw", C.c_int32), ("timing", C.c_int32), ("trace_cap", C.c_int32),
                 ("trace", C.POINTER(C.c_double)), ("newton_cg", C.c_int32), ("cg_maxit", C.c_int32),
-                ("cg_eta", C.c_double), ("cg_tau", C.c_double), ("workers", C.c_int32)]
+                ("cg_eta", C.c_double), ("cg_tau", C.c_double), ("workers", C.c_int32),
+                ("no_small", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -43,7 +44,7 @@ class Info(C.Structure):
                 ("solve_ms", C.c_double), ("atd_launches", C.c_int32), ("atd_ms", C.c_double),
                 ("cg_iters", C.c_int32), ("sigma0", C.c_double), ("queue_ms", C.c_double),
                 ("upload_ms", C.c_double), ("chol_calls", C.c_int32), ("chol_ms", C.c_double),
-                ("chol_gflop", C.c_double)]
+                ("chol_gflop", C.c_double), ("one_workgroup", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

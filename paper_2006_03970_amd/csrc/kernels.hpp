@@ -159,6 +159,48 @@ hipError_t sum_parts(const double* part, int nb, double* out, const double* y, i
 // *out = max_i |v_i| (part: 1024 doubles of scratch).
 hipError_t absmax(const double* v, int64_t n, double* part, double* out, hipStream_t st);
 
+// ---- one-workgroup solves of small problems (k_small.hip) ----------------
+// FP64 storage, m <= kSmallMaxM; the whole solve (outer and inner loops,
+// stopping tests, certificates) in one workgroup, one workgroup per problem.
+constexpr int kSmallMaxM = 120;
+struct SmallOpts {
+  double sigma_factor, sigma_max, mu;
+  int max_outer, max_inner, K, no_smw;
+  double s[kMaxTrials];  // trial steps delta^k, k < K
+};
+struct SmallOut {
+  int status;  // 0 converged, 1 not converged, 2 line-search stall, -1 sigma0 not a positive
+               // number, -2 non-finite, -5 non-positive pivot
+  int outer, newton, passes;
+  int chol_row;  // status -5: row + 1 of the pivot
+  int64_t r;
+  double eta, kkt1, kkt3, F, D, sigma, sigma0;
+};
+struct SmallArgs {
+  const double* A;
+  int64_t lda;
+  int m;
+  int64_t n;
+  const double* b;
+  const double* x0;  // null: cold start
+  double* x;
+  double l1, l2, tol, sigma0;  // sigma0 <= 0: 2.5 / mean |a_j|^2
+  double* wy;  // n doubles each
+  double* wd;
+  double* uJ;
+  int32_t* J;  // n entries
+  SmallOut* out;
+};
+// Raise the dynamic LDS limit of the one-workgroup solve (once per device).
+hipError_t small_init();
+size_t small_lds_bytes(int mmax);
+// count problems whose descriptors probs[] the device reads (device or mapped
+// pinned memory), or one problem passed by value in *one (probs ignored);
+// mmax = max m over them.  With pub.flag set (single problem), the result
+// record is published with that sequence number once written.
+hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, int mmax, const SmallOpts& o,
+                       Pub pub, hipStream_t st);
+
 // ---- Cholesky and triangular solves (k_chol.hip) --------------------------
 // Raise the dynamic LDS limits of the Cholesky kernels (once per device).
 hipError_t chol_init();

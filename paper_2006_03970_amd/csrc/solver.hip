@@ -61,6 +61,9 @@ struct ssnal_ctx {
   int device = 0;
   DevBuf wy, wd, uJ, J, counts, part, gpart, V, syrk, mvec, scal;
   DevBuf cv_a, cv_x, cv_m;  // k-fold: a fold's training design, its path, rows / b / errors
+  DevBuf sm_ws;             // batch: the n-vectors of the problems solved in one workgroup each
+  SmallArgs* h_small = nullptr;  // batch: coherent pinned descriptors, then the result records
+  int small_cap = 0;             // problems h_small holds
   std::vector<ssnal_ctx*> cv_sub;      // k-fold worker contexts (created on first use)
   std::vector<hipStream_t> cv_streams;  // their streams (default priority)
   double* h_scal = nullptr;  // coherent pinned: SC_SIZE doubles, then the publish flag
@@ -434,20 +437,41 @@ void certificate_values(const double* hs, double l1, double l2, double* eta, dou
   }
 }
 
-// preset (nullable): a workspace the caller laid out (the no-allocation entry
-// point); otherwise the context's workspace, grown as needed.
-int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int64_t m64,
-               int64_t n, double l1, double l2, const double* x0, double tol, hipStream_t st,
-               double* x, const ssnal_en_opts* user_opts, ssnal_en_info* info,
-               const Workspace* preset = nullptr) {
-  const auto t_start = std::chrono::steady_clock::now();
-  if (int rc = check_args(A, dt, lda, b, m64, n)) return rc;
-  if (!x) return fail(SSNAL_EINVAL, "x_out must be a non-null device pointer");
-  if (!(l1 >= 0.0) || !std::isfinite(l1)) return fail(SSNAL_EINVAL, "lambda1 must be finite and >= 0");
-  if (!(l2 >= 0.0) || !std::isfinite(l2)) return fail(SSNAL_EINVAL, "lambda2 must be finite and >= 0");
-  if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
-  const int m = (int)m64;
-  ssnal_en_opts o;
+// ---- one-workgroup solves of small problems (k_small.hip)
+// At m <= 120 and small m n the multi-kernel path is bound by its launches
+// and its host read-back per Newton step; one workgroup runs the whole solve
+// there, streaming A at one CU's rate.  A single solve takes that path up to
+// kSmallMaxMN = m n (where the per-step passes of one CU over A catch up with
+// the launch overhead they replace); a batch, whose problems fill the CUs side
+// by side, up to kSmallBatchMaxMN.
+constexpr int64_t kSmallMaxMN = (int64_t)1 << 19;
+constexpr int64_t kSmallBatchMaxMN = (int64_t)1 << 21;
+
+bool small_ok(int dt, int64_t m, int64_t n, const ssnal_en_opts& o, int64_t max_mn) {
+  return !o.no_small && dt == kF64 && m <= kSmallMaxM && m * n <= max_mn && !o.newton_cg && !o.timing &&
+         !(o.trace && o.trace_cap > 0);
+}
+
+SmallOpts small_opts(const ssnal_en_opts& o) {
+  SmallOpts so{};
+  so.sigma_factor = o.sigma_factor;
+  so.sigma_max = o.sigma_max;
+  so.mu = o.mu;
+  so.max_outer = o.max_outer;
+  so.max_inner = o.max_inner;
+  so.K = o.max_backtrack + 1;
+  so.no_smw = o.no_smw;
+  double t = 1.0;
+  for (int k = 0; k < kMaxTrials; ++k) {
+    so.s[k] = k < so.K ? t : 0.0;
+    t *= o.delta;
+  }
+  return so;
+}
+
+// Options of one solve: the defaults, overridden by the caller's positive
+// fields, validated.
+int parse_opts(const ssnal_en_opts* user_opts, ssnal_en_opts& o) {
   ssnal_en_opts_init(&o);
   if (user_opts) {
     if (user_opts->sigma0 > 0) o.sigma0 = user_opts->sigma0;
@@ -467,11 +491,98 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     o.timing = user_opts->timing;
     o.trace = user_opts->trace;
     o.trace_cap = user_opts->trace_cap;
+    o.workers = user_opts->workers;
+    o.no_small = user_opts->no_small;
   }
   if (o.max_backtrack > kMaxTrials - 1) o.max_backtrack = kMaxTrials - 1;
   if (!(o.mu < 0.5)) return fail(SSNAL_EINVAL, "mu must lie in (0, 1/2)");
   if (!(o.delta < 1.0)) return fail(SSNAL_EINVAL, "delta must lie in (0, 1)");
   if (!(o.cg_eta < 1.0)) return fail(SSNAL_EINVAL, "cg_eta must lie in (0, 1)");
+  if (user_opts && user_opts->sigma0 > 0 && !std::isfinite(user_opts->sigma0))
+    return fail(SSNAL_EINVAL, "sigma0 = %g is not a positive number", user_opts->sigma0);
+  return 0;
+}
+
+int check_scalars(const double* x, double l1, double l2, double tol) {
+  if (!x) return fail(SSNAL_EINVAL, "x_out must be a non-null device pointer");
+  if (!(l1 >= 0.0) || !std::isfinite(l1)) return fail(SSNAL_EINVAL, "lambda1 must be finite and >= 0");
+  if (!(l2 >= 0.0) || !std::isfinite(l2)) return fail(SSNAL_EINVAL, "lambda2 must be finite and >= 0");
+  if (!(tol > 0.0)) return fail(SSNAL_EINVAL, "tol must be > 0");
+  return 0;
+}
+
+SmallArgs small_args(const void* A, int64_t lda, const double* b, int64_t m, int64_t n, double l1, double l2,
+                     const double* x0, double tol, double* x, const ssnal_en_opts* user_opts, double* wy,
+                     double* wd, double* uJ, int32_t* J, SmallOut* out) {
+  SmallArgs a{};
+  a.A = static_cast<const double*>(A);
+  a.lda = lda;
+  a.m = (int)m;
+  a.n = n;
+  a.b = b;
+  a.x0 = x0;
+  a.x = x;
+  a.l1 = l1;
+  a.l2 = l2;
+  a.tol = tol;
+  a.sigma0 = user_opts && user_opts->sigma0 > 0 ? user_opts->sigma0 : 0.0;
+  a.wy = wy;
+  a.wd = wd;
+  a.uJ = uJ;
+  a.J = J;
+  a.out = out;
+  return a;
+}
+
+// The outcome of a one-workgroup solve as the multi-kernel path reports it:
+// errors as their codes, info filled, the status returned.
+int small_result(ssnal_ctx* c, const SmallOut& so, double tol, double solve_ms, ssnal_en_info* info) {
+  if (so.status == -2)
+    return fail(SSNAL_ENONFINITE, "non-finite values in b, x0, A or the iterates");
+  if (so.status == -1) return fail(SSNAL_EINVAL, "sigma0 = %g is not a positive number", so.sigma0);
+  if (so.status == -5) return chol_fail(so.chol_row);
+  c->last_sigma0 = so.sigma0;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = so.status;
+    info->outer_iters = so.outer;
+    info->newton_iters = so.newton;
+    info->r_final = (int32_t)so.r;
+    info->nnz = so.r;
+    info->kkt_rel = so.eta;
+    info->kkt1 = so.kkt1;
+    info->kkt3 = so.kkt3;
+    info->primal_obj = so.F;
+    info->dual_obj = so.D;
+    info->rel_gap = (so.F - so.D) / (1.0 + std::fabs(so.F));
+    info->sigma_final = so.sigma;
+    info->gemv_calls = so.passes;
+    info->syncs = 1;
+    info->sigma0 = so.sigma0;
+    info->solve_ms = solve_ms;
+    info->one_workgroup = 1;
+  }
+  if (so.status != SSNAL_OK) {
+    snprintf(g_err, sizeof(g_err), "%s after %d outer iterations (eta=%.3e, tol=%.3e)",
+             so.status == SSNAL_NOT_CONVERGED ? "not converged" : "line search stalled", so.outer, so.eta,
+             tol);
+  }
+  return so.status;
+}
+static_assert(sizeof(SmallOut) <= SC_SIZE * sizeof(double), "the result record fits the scalar slots");
+
+// preset (nullable): a workspace the caller laid out (the no-allocation entry
+// point); otherwise the context's workspace, grown as needed.
+int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b, int64_t m64,
+               int64_t n, double l1, double l2, const double* x0, double tol, hipStream_t st,
+               double* x, const ssnal_en_opts* user_opts, ssnal_en_info* info,
+               const Workspace* preset = nullptr) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (int rc = check_args(A, dt, lda, b, m64, n)) return rc;
+  if (int rc = check_scalars(x, l1, l2, tol)) return rc;
+  const int m = (int)m64;
+  ssnal_en_opts o;
+  if (int rc = parse_opts(user_opts, o)) return rc;
   HIPCHK(hipSetDevice(c->device));
   Workspace w;
   if (preset) {
@@ -479,10 +590,24 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   } else if (int rc = prepare(c, m, n, w)) {
     return rc;
   }
-  const bool mixed = dt != kF64;
-  Timer tm{c, st, o.timing != 0};
   int gemv_calls = 0, syncs = 0;
   double* hs = c->h_scal;
+  if (small_ok(dt, m, n, o, kSmallMaxMN)) {
+    // the whole solve in one workgroup; its result record lands in the
+    // pinned scalar slots with the publish flag
+    const Pub pub = next_pub(c);
+    const SmallArgs a = small_args(A, lda, b, m, n, l1, l2, x0, tol, x, user_opts, w.wy, w.wd, w.uJ, w.J,
+                                   reinterpret_cast<SmallOut*>(pub.dst));
+    HIPCHK(solve_small(nullptr, &a, 1, m, small_opts(o), pub, st));
+    if (int rc = wait_pub(c, st, pub.seq, &syncs)) return rc;
+    SmallOut so;
+    std::memcpy(&so, hs, sizeof(so));
+    return small_result(c, so, tol,
+                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count(),
+                        info);
+  }
+  const bool mixed = dt != kF64;
+  Timer tm{c, st, o.timing != 0};
   HIPCHK(hipMemsetAsync(w.info, 0, sizeof(double), st));
 
   // ---- start: x = x0 (or 0), y = A x0 - b, w_y = A^T y
@@ -733,7 +858,7 @@ int ssnal_ctx_create(int device, ssnal_ctx** out) {
       hipHostMalloc((void**)&c->h_scal, (SC_SIZE + 1) * sizeof(double),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->d_scal, c->h_scal, 0) != hipSuccess ||
-      chol_init() != hipSuccess) {
+      chol_init() != hipSuccess || small_init() != hipSuccess) {
     ssnal_ctx_destroy(c);
     return fail(SSNAL_EHIP, "context initialisation failed");
   }
@@ -746,11 +871,12 @@ void ssnal_ctx_destroy(ssnal_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart,
-                    &c->V, &c->syrk, &c->mvec, &c->scal, &c->cv_a, &c->cv_x, &c->cv_m};
+  DevBuf* bufs[] = {&c->wy, &c->wd, &c->uJ, &c->J, &c->counts, &c->part, &c->gpart, &c->V,
+                    &c->syrk, &c->mvec, &c->scal, &c->cv_a, &c->cv_x, &c->cv_m, &c->sm_ws};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->h_small) (void)hipHostFree(c->h_small);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->ev_order) (void)hipEventDestroy(c->ev_order);
   for (ssnal_ctx* s : c->cv_sub) ssnal_ctx_destroy(s);
@@ -1025,27 +1151,111 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
   HIPCHK(hipSetDevice(ctx->device));
   const int want = opts && opts->workers > 0 ? opts->workers : 8;
   if (want > 64) return fail(SSNAL_EINVAL, "opts->workers must lie in [1, 64]");
-  const int nw = std::min(want, count);
-  if (nw == 1) {
-    int worst = 0;
-    for (int i = 0; i < count; ++i) {
+  ssnal_en_opts shared;
+  if (int rc = parse_opts(opts, shared)) return rc;
+  // the problems solved in one workgroup each (one launch on `stream`), and the rest
+  std::vector<int> small, rest;
+  for (int i = 0; i < count; ++i) {
+    const ssnal_en_problem& p = problems[i];
+    if (check_args(p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n) == 0 &&
+        small_ok((int)p.a_dtype, p.m, p.n, shared, kSmallBatchMaxMN))
+      small.push_back(i);
+    else
+      rest.push_back(i);
+  }
+  g_err[0] = 0;
+  const int nsmall = (int)small.size(), nrest = (int)rest.size();
+  const auto t_small = std::chrono::steady_clock::now();
+  SmallOut* h_out = nullptr;
+  int worst = 0;
+  if (nsmall > 0) {
+    size_t ws = 0;
+    int mmax = 1;
+    for (int i : small) {
+      const ssnal_en_problem& p = problems[i];
+      if (int rc = check_scalars((double*)p.x_out, p.lambda1, p.lambda2, p.tol))
+        return fail(rc, "problem %d: %s", i, std::string(g_err).c_str());
+      if (p.sigma0 > 0.0 && !std::isfinite(p.sigma0))
+        return fail(SSNAL_EINVAL, "problem %d: sigma0 = %g is not a positive number", i, p.sigma0);
+      ws += ((size_t)p.n * 28 + 255) / 256 * 256;
+      mmax = std::max(mmax, (int)p.m);
+    }
+    if (int rc = ensure(ctx->sm_ws, ws)) return rc;
+    if (ctx->small_cap < nsmall) {
+      if (ctx->h_small) HIPCHK(hipHostFree(ctx->h_small));
+      ctx->h_small = nullptr;
+      ctx->small_cap = 0;
+      HIPCHK(hipHostMalloc((void**)&ctx->h_small, (size_t)nsmall * (sizeof(SmallArgs) + sizeof(SmallOut)),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+      ctx->small_cap = nsmall;
+    }
+    SmallArgs* d_args = nullptr;
+    HIPCHK(hipHostGetDevicePointer((void**)&d_args, ctx->h_small, 0));
+    h_out = reinterpret_cast<SmallOut*>(ctx->h_small + ctx->small_cap);
+    SmallOut* d_out = reinterpret_cast<SmallOut*>(d_args + ctx->small_cap);
+    char* base = static_cast<char*>(ctx->sm_ws.p);
+    for (int k = 0; k < nsmall; ++k) {
+      const ssnal_en_problem& p = problems[small[k]];
+      const int64_t n = p.n;
+      double* wy = reinterpret_cast<double*>(base);
+      ssnal_en_opts local;
+      ctx->h_small[k] = small_args(p.A, p.lda, p.b, p.m, n, p.lambda1, p.lambda2, (const double*)p.x0, p.tol,
+                                   (double*)p.x_out, problem_opts(p, opts, local), wy, wy + n, wy + 2 * n,
+                                   reinterpret_cast<int32_t*>(wy + 3 * n), d_out + k);
+      base += ((size_t)n * 28 + 255) / 256 * 256;
+      if (p.ready) HIPCHK(hipStreamWaitEvent(stream, p.ready, 0));
+    }
+    // the other problems' workers start after the caller's earlier work, not after this launch
+    if (nrest > 0 && want > 1) {
+      if (!ctx->ev_order) HIPCHK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ctx->ev_order, stream));
+    }
+    HIPCHK(solve_small(d_args, nullptr, nsmall, mmax, small_opts(shared), Pub{}, stream));
+  }
+  // the results of the one-workgroup solves, once the launch has finished
+  auto small_results = [&]() -> int {
+    if (nsmall == 0) return 0;
+    HIPCHK(hipStreamSynchronize(stream));
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_small).count();
+    for (int k = 0; k < nsmall; ++k) {
+      const int i = small[k];
+      SmallOut so;
+      std::memcpy(&so, h_out + k, sizeof(so));
+      ssnal_en_info info_i;
+      const int rc = small_result(ctx, so, problems[i].tol, ms, &info_i);
+      if (rc < 0) return fail(rc, "problem %d: %s", i, std::string(g_err).c_str());
+      if (infos) infos[i] = info_i;
+      worst = std::max(worst, rc);
+    }
+    return 0;
+  };
+  const int nw = std::min(want, nrest);
+  if (nw <= 1) {
+    for (int i : rest) {
       const ssnal_en_problem& p = problems[i];
       if (p.ready) HIPCHK(hipStreamWaitEvent(stream, p.ready, 0));
       ssnal_en_opts local;
       ssnal_en_info info_i;
       const int rc = solve_impl(ctx, p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n, p.lambda1, p.lambda2,
                                 p.x0, p.tol, stream, p.x_out, problem_opts(p, opts, local), &info_i);
-      if (rc < 0) return rc;
+      if (rc < 0) {
+        if (nsmall > 0) (void)hipStreamSynchronize(stream);
+        return rc;
+      }
       if (infos) infos[i] = info_i;
       worst = std::max(worst, rc);
     }
+    if (int rc = small_results()) return rc;
     return worst;
   }
   if (int rc = ensure_workers(ctx, nw)) return rc;
   // the workers' streams start after the caller's earlier work on `stream`
-  if (!ctx->ev_order) HIPCHK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
+  if (nsmall == 0) {
+    if (!ctx->ev_order) HIPCHK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ctx->ev_order, stream));
+  }
   hipEvent_t start = ctx->ev_order;
-  HIPCHK(hipEventRecord(start, stream));
   for (int i = 0; i < nw; ++i) HIPCHK(hipStreamWaitEvent(ctx->cv_streams[i], start, 0));
   std::vector<int> rcs(count, 0);
   std::vector<std::string> msgs(count);
@@ -1053,7 +1263,8 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
   std::vector<std::thread> th;
   for (int w = 0; w < nw; ++w) {
     th.emplace_back([&, w]() {
-      for (int i = next++; i < count; i = next++) {
+      for (int k = next++; k < nrest; k = next++) {
+        const int i = rest[k];
         g_err[0] = 0;
         const ssnal_en_problem& p = problems[i];
         hipStream_t st = ctx->cv_streams[w];
@@ -1068,19 +1279,20 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
           if (infos && rcs[i] >= 0) infos[i] = info_i;
         }
         msgs[i] = g_err;
-        if (rcs[i] < 0) next = count;  // stop handing out problems
+        if (rcs[i] < 0) next = nrest;  // stop handing out problems
       }
     });
   }
   for (std::thread& t : th) t.join();
-  int worst = 0;
-  for (int i = 0; i < count; ++i) {
+  for (int i : rest) {
     if (rcs[i] < 0) {
+      if (nsmall > 0) (void)hipStreamSynchronize(stream);
       snprintf(g_err, sizeof(g_err), "problem %d: %s", i, msgs[i].c_str());
       return rcs[i];
     }
     worst = std::max(worst, rcs[i]);
   }
+  if (int rc = small_results()) return rc;
   return worst;
 }
 

@@ -1,0 +1,269 @@
+"""Parity of the one-workgroup solve (FP64, m <= 120, small m n: the whole of
+Algorithm 1 in one workgroup) against the FP64 oracle, through the C ABI, and
+its agreement with the multi-kernel path on the same problems."""
+import numpy as np
+import pytest
+
+from tests import pinlib
+from tests.certify import check_eta
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    return gpu.Context(0)
+
+
+def _upload(p, lda=None):
+    from paper_2006_03970_amd.device import design_to_device, vec_to_device
+    return design_to_device(p.AT, p.store, lda=lda), vec_to_device(p.b)
+
+
+def _support_ok(x, xr, thr=1e-8):
+    diff = (x != 0) ^ (xr != 0)
+    return np.all(np.abs(x[diff]) <= thr) and np.all(np.abs(xr[diff]) <= thr)
+
+
+def _rel_obj(F, Fr):
+    return abs(F - Fr) / abs(Fr)
+
+
+def _check_vs_oracle(orc, p, x, info, tol):
+    """eta <= tol on both sides' evaluation, relative objective 1e-10 to the
+    oracle's minimiser, the same support apart from coefficients within 1e-8
+    of zero."""
+    assert info["status"] == 0, info
+    check_eta(orc, p.AT, p.b, x, p.lam1, p.lam2, tol, eta_gpu=info["kkt_rel"])
+    xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=min(tol, 1e-10))
+    F = orc.primal_obj(p.AT, p.b, x, p.lam1, p.lam2)
+    assert _rel_obj(F, ir["primal_obj"]) <= 1e-10, (F, ir["primal_obj"])
+    assert _support_ok(x, xr)
+    return xr, ir
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_c1_one_workgroup_vs_oracle(gpu, ctx, orc, seed):
+    """m=100, n=2000 Gaussian design, tol 1e-10, in one workgroup."""
+    import datagen
+    p = datagen.make_problem("c1", seed=seed)
+    _say("c1 one workgroup seed", seed)
+    A, b = _upload(p)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    assert info["one_workgroup"] == 1
+    assert info["syncs"] == 1
+    _check_vs_oracle(orc, p, x.cpu().numpy(), info, p.tol)
+
+
+def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
+    """The same problem through both paths: both meet the oracle bar, and
+    their minimisers agree to 1e-9 (they differ only in summation order)."""
+    import datagen
+    p = datagen.make_problem("c1", seed=11)
+    A, b = _upload(p)
+    _say("one workgroup vs multi-kernel")
+    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x2, i2 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(no_small=1))
+    assert i1["one_workgroup"] == 1 and i2["one_workgroup"] == 0
+    x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+    _check_vs_oracle(orc, p, x1, i1, p.tol)
+    _check_vs_oracle(orc, p, x2, i2, p.tol)
+    assert np.max(np.abs(x1 - x2)) <= 1e-9
+    # the same sigma schedule: sigma0 from the column norms, x5 per outer iteration
+    assert i1["sigma0"] == pytest.approx(i2["sigma0"], rel=1e-14)
+    print(f"[report] outer {i1['outer_iters']}/{i2['outer_iters']} newton "
+          f"{i1['newton_iters']}/{i2['newton_iters']} passes {i1['gemv_calls']}/{i2['gemv_calls']}")
+
+
+@pytest.mark.parametrize("m,n,k,c_lam", [(37, 2001, 5, 0.5), (120, 4000, 12, 0.5), (64, 513, 40, 0.05),
+                                         (100, 40, 8, 0.5)])
+def test_ragged_and_maximum_shapes(gpu, ctx, orc, m, n, k, c_lam):
+    """m off the 16-row MFMA blocks and the 8-column Cholesky panels, n off the
+    512-feature chunks, the largest m (120) at m n <= 2^19, m > n, and an
+    active set larger than m (160 of 513 at m = 64: the m x m system)."""
+    import datagen
+    p = datagen.make_problem("c1", seed=m + n, m=m, n=n, k=k, c_lam=c_lam)
+    A, b = _upload(p)
+    _say("one workgroup shape", m, n, k)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    assert info["one_workgroup"] == 1
+    _check_vs_oracle(orc, p, x.cpu().numpy(), info, p.tol)
+
+
+def test_beyond_limits_takes_multi_kernel_path(gpu, ctx):
+    """m = 121, or m n above 2^19, or FP32 storage: the multi-kernel path."""
+    import datagen
+    for m, n, store in [(121, 1000, "f64"), (100, 5300, "f64"), (100, 2000, "f32")]:
+        p = datagen.make_problem("c1", seed=3, m=m, n=n, store=store)
+        A, b = _upload(p)
+        _say("multi-kernel", m, n, store)
+        x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-8)
+        assert info["status"] == 0 and info["one_workgroup"] == 0
+
+
+def test_lasso_limit(gpu, ctx, orc):
+    """lambda2 = 0: the Lasso, whose dual objective takes the scaled dual point."""
+    import datagen
+    p = datagen.make_problem("c1", seed=12)
+    p.lam2 = 0.0
+    A, b = _upload(p)
+    _say("lasso one workgroup")
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, 0.0, tol=1e-9)
+    assert info["one_workgroup"] == 1
+    x = x.cpu().numpy()
+    assert info["status"] == 0, info
+    check_eta(orc, p.AT, p.b, x, p.lam1, 0.0, 1e-9, eta_gpu=info["kkt_rel"])
+    xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, 0.0, tol=1e-11)
+    F = orc.primal_obj(p.AT, p.b, x, p.lam1, 0.0)
+    assert _rel_obj(F, ir["primal_obj"]) <= 1e-9
+    # the reported duality gap is the oracle's objectives' gap at this x
+    assert info["rel_gap"] >= -1e-12 and info["rel_gap"] <= 1e-5
+
+
+def test_woodbury_and_full_system_agree(gpu, ctx, orc):
+    """r < m takes the r x r system (eq. smw_formula); no_smw forces the m x m
+    one (eq. AJ_system): the same minimiser."""
+    import datagen
+    p = datagen.make_problem("c1", seed=13, k=4, c_lam=0.8)
+    A, b = _upload(p)
+    _say("woodbury vs m x m")
+    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x2, i2 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(no_smw=1))
+    assert i1["one_workgroup"] == 1 and i2["one_workgroup"] == 1
+    assert 0 < i1["nnz"] < p.m
+    x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+    _check_vs_oracle(orc, p, x1, i1, p.tol)
+    _check_vs_oracle(orc, p, x2, i2, p.tol)
+    assert np.max(np.abs(x1 - x2)) <= 1e-9
+
+
+def test_ridge_and_zero_solutions(gpu, ctx, orc):
+    """lambda1 = 0 (every feature active: the m x m system each step) against
+    the closed form; lambda1 above ||A^T b||_inf: x = 0 with r = 0."""
+    import torch
+    A_, b_, _, _ = pinlib.gaussian_problem(60, 900, 9)
+    l2 = 0.7
+    A = torch.from_numpy(np.ascontiguousarray(A_.T)).cuda()
+    b = torch.from_numpy(b_).cuda()
+    _say("ridge one workgroup")
+    x, info = gpu.ssnal_en_solve(ctx, A, b, 0.0, l2, tol=1e-11)
+    assert info["one_workgroup"] == 1 and info["status"] == 0
+    ref = A_.T @ np.linalg.solve(A_ @ A_.T + l2 * np.eye(60), b_)
+    assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-9
+    lmax = np.max(np.abs(A_.T @ b_))
+    x, info = gpu.ssnal_en_solve(ctx, A, b, lmax * 1.01, 0.3, tol=1e-10)
+    assert info["one_workgroup"] == 1 and info["status"] == 0 and info["nnz"] == 0
+    assert np.count_nonzero(x.cpu().numpy()) == 0
+
+
+@pytest.mark.parametrize("m,n", [(1, 50), (7, 1), (1, 1)])
+def test_degenerate_shapes(gpu, ctx, orc, m, n):
+    """One row, one column, one entry."""
+    import torch
+    g = np.random.default_rng(m * 100 + n + 7)
+    A_ = g.standard_normal((m, n))
+    b_ = g.standard_normal(m)
+    l1 = 0.3 * np.max(np.abs(A_.T @ b_))
+    l2 = 0.2
+    A = torch.from_numpy(np.ascontiguousarray(A_.T)).cuda()
+    b = torch.from_numpy(b_).cuda()
+    _say("degenerate", m, n)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, l1, l2, tol=1e-11)
+    assert info["one_workgroup"] == 1
+    xr, ir, _ = orc.en_solve(np.ascontiguousarray(A_.T), b_, l1, l2, tol=1e-12)
+    assert info["status"] == 0, info
+    assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-8
+
+
+def test_warm_start_padded_lda_aliased(gpu, ctx, orc):
+    """lda > m with NaN padding rows (never read); a warm start from another
+    point, with x0 the output buffer itself, reaches the same minimiser."""
+    import datagen
+    p = datagen.make_problem("c1", seed=14)
+    A, b = _upload(p, lda=p.m + 4)
+    _say("warm start, padded lda, x0 == x_out")
+    x_cold, ic = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, m=p.m)
+    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1 * 1.2, p.lam2 * 1.2, tol=1e-10, m=p.m)
+    x_warm, iw = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x1, x_out=x1, tol=1e-10, m=p.m)
+    assert ic["one_workgroup"] == 1 and iw["one_workgroup"] == 1
+    assert ic["status"] == 0 and iw["status"] == 0
+    xr, _, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-11)
+    assert np.max(np.abs(x_cold.cpu().numpy() - xr)) <= 1e-8
+    assert np.max(np.abs(x_warm.cpu().numpy() - xr)) <= 1e-8
+
+
+def test_errors_and_status(gpu, ctx):
+    """Non-finite b or x0: SSNAL_ENONFINITE; max_outer = 1 at a tight tol:
+    SSNAL_NOT_CONVERGED with the certificates of the returned point."""
+    import datagen
+    p = datagen.make_problem("c1", seed=15)
+    A, b = _upload(p)
+    _say("errors one workgroup")
+    bn = b.clone()
+    bn[5] = float("inf")
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, bn, p.lam1, p.lam2)
+    assert e.value.code == -2
+    import torch
+    x0 = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    x0[17] = float("nan")
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x0)
+    assert e.value.code == -2
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-14, opts=gpu.make_opts(max_outer=1))
+    assert info["one_workgroup"] == 1 and info["status"] == 1 and info["outer_iters"] == 1
+    assert np.isfinite(info["kkt_rel"]) and info["kkt_rel"] > 1e-14
+    # the same solve still works after the errors
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert info["status"] == 0
+
+
+def test_repeat_bitwise(gpu, ctx):
+    """Fixed-order sums: two one-workgroup solves agree bit for bit."""
+    import datagen
+    p = datagen.make_problem("c1", seed=16)
+    A, b = _upload(p)
+    _say("repeat one workgroup")
+    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    x2, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+
+
+def test_batch_one_launch_matches_single(gpu, ctx, orc):
+    """A batch of 40 problems: 32 small FP64 ones (m from 20 to 120, per-problem
+    sigma0 on some) run as one launch, one workgroup each, beside 8 others
+    (m = 160, FP32 storage) on the workers.  Each small problem's result is
+    bit for bit its single solve's (same kernel, same summation order), and
+    every problem meets the oracle bar."""
+    import datagen
+    import torch
+    probs, keep, ref = [], [], []
+    for i in range(40):
+        if i < 32:
+            m, n, store = 20 + (i * 13) % 101, 500 + 97 * i, "f64"
+        else:
+            m, n, store = 160, 1500, ("f32" if i % 2 else "f64")
+        p = datagen.make_problem("c1", seed=100 + i, m=m, n=n, store=store)
+        A, b = _upload(p)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        probs.append(dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=1e-10, x_out=x,
+                          sigma0=(0.01 * (i % 3) if i % 3 else 0.0), m=m))
+        keep.append(p)
+    _say("batch of 40 (32 one-workgroup)")
+    infos, rc = gpu.ssnal_en_solve_batch(ctx, probs)
+    assert rc == 0, infos
+    for i, (pr, p, info) in enumerate(zip(probs, keep, infos)):
+        assert info["status"] == 0, (i, info)
+        assert info["one_workgroup"] == (1 if i < 32 else 0), (i, info)
+        x = pr["x_out"].cpu().numpy()
+        AT64 = p.AT64 if p.store != "f64" else p.AT
+        check_eta(orc, AT64, p.b, x, p.lam1, p.lam2, 1e-10, eta_gpu=info["kkt_rel"])
+        if i < 32:
+            opts = gpu.make_opts(sigma0=pr["sigma0"]) if pr["sigma0"] > 0 else None
+            A, b = _upload(p)
+            xs, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=opts)
+            assert np.array_equal(xs.cpu().numpy(), x), i
