@@ -87,7 +87,7 @@ typedef struct {
   int32_t workers;       /* ssnal_en_solve_batch: <= 0: 8 concurrent workers (own context and
                             stream each, kept by the context); 1 = every problem in turn on
                             the caller's stream */
-  int32_t no_small;      /* 0 = a problem with A in FP64, m <= 120 and m n <= 2^19 runs its
+  int32_t no_small;      /* 0 = a problem with A in FP64, m <= 120 and m n <= 2^17 runs its
                             whole solve (Algorithm 1: both loops, the stopping tests, the
                             certificates) in one workgroup, one launch and one host wait,
                             unless trace, timing or newton_cg is asked for; a batch runs its
@@ -301,13 +301,19 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
                           hipStream_t stream, double* beta_out, ssnal_en_select* out);
 
 /* Independent solves (k-fold or grid-search style) of device-resident
- * problems, on opts->workers concurrent workers (default 8; each a context and
- * stream of its own, created on first use and kept by ctx) that start after
- * the caller's earlier work on `stream` and each problem's `ready` event; with
- * opts->workers = 1, one after the other on `stream` with ctx's workspace.
- * Every solve's result is the same bits under any worker count.  Returns
- * after every solve has completed.  infos: HOST, nullable, count entries.
- * Returns the most severe status; an error stops handing out problems. */
+ * problems.  Problems with A in FP64, m <= 120 and m n <= 2^21 (unless
+ * opts->no_small, trace, timing or newton_cg) run as one launch on `stream`,
+ * one workgroup each; the others run on opts->workers concurrent workers
+ * (default 8; each a context and stream of its own, created on first use and
+ * kept by ctx) that start after the caller's earlier work on `stream` and
+ * each problem's `ready` event; with opts->workers = 1, one after the other
+ * on `stream` with ctx's workspace.  Every solve's result is the same bits
+ * under any worker count, and the bits of the same problem solved alone when
+ * both take the same path (a single solve runs in one workgroup up to
+ * m n <= 2^17; see info->one_workgroup); otherwise the two agree to rounding.
+ * Returns after every solve has completed.  infos: HOST, nullable, count
+ * entries.  Returns the most severe status; an error stops handing out
+ * problems. */
 int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int count,
                          const ssnal_en_opts* opts, hipStream_t stream, ssnal_en_info* infos);
 

@@ -9,7 +9,11 @@
 // than by any pass over A; here a Newton step costs its passes over A at one
 // CU's rate plus a Cholesky of at most 120 x 120 in LDS.
 //
-// One workgroup of 512 threads (8 waves, two a SIMD) per problem.  A (FP64,
+// One workgroup of 256 threads per problem, single or batched (the same
+// summation orders, so a batched problem gives its single solve's bits);
+// at most 256 registers a lane and 69 KB of LDS at m = 120 (the Newton
+// matrix packed as a lower triangle), so two problems share a CU and hide
+// each other's memory waits.  A (FP64,
 // column-major, lda >= m) and the n-vectors (x, w_y = A^T y, w_d = A^T d,
 // the active set J and u_J) stay in global memory (cache-resident at these
 // sizes); the m-vectors (y, g, d, rho, b), the Newton matrix and its
@@ -43,13 +47,14 @@ typedef double __attribute__((address_space(1)))* GD;
 typedef const int32_t __attribute__((address_space(1)))* GCI;
 typedef int32_t __attribute__((address_space(1)))* GI;
 
-constexpr int kSmNT = 512;
+constexpr int kSmNT = 256;                        // threads a problem
 constexpr int kSmWaves = kSmNT / kWave;
 constexpr int kSmVec = 128;                       // LDS m-vector length (m <= kSmallMaxM < 128)
 constexpr int kSmRows = (kSmallMaxM + 15) / 16;   // rows a lane takes in the 16-lane column layout
 constexpr int kSmLsChunk = 8;                     // trial steps summed per pass of the line search
 
-// LDS: these fixed parts, then the Newton matrix M (N x P, P = m + 1).
+// LDS: these fixed parts, then the lower triangle of the Newton matrix M,
+// packed by rows (row i at offset i (i + 1) / 2).
 struct SmallLds {
   double y[kSmVec], g[kSmVec], d[kSmVec], rho[kSmVec], b[kSmVec], q[kSmVec];
   double idg[kSmVec];             // 1 / L_kk of the last factorisation
@@ -66,10 +71,12 @@ constexpr int kOffY = 0, kOffG = kSmVec, kOffD = 2 * kSmVec, kOffRho = 3 * kSmVe
 extern __shared__ __align__(16) double sm_dyn[];
 __device__ __forceinline__ SmallLds& sl() { return *reinterpret_cast<SmallLds*>(sm_dyn); }
 __device__ __forceinline__ double* sm_mat() { return sm_dyn + sizeof(SmallLds) / sizeof(double); }
+__device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }  // start of row i of M
 
 struct SmallCtx {
   int tid, lane, wid;
-  int m, P;  // rows; pitch of M
+  int nt, nw;  // threads and waves of the workgroup
+  int m;
 };
 
 // Sum of K values over the block (every thread receives the K sums; waves
@@ -87,7 +94,7 @@ __device__ __forceinline__ void bsum(double (&v)[K], const SmallCtx& c) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double t = sl().red[k];
-    for (int w = 1; w < kSmWaves; ++w) t += sl().red[w * K + k];
+    for (int w = 1; w < c.nw; ++w) t += sl().red[w * K + k];
     v[k] = t;
   }
 }
@@ -106,7 +113,7 @@ __device__ __forceinline__ double row16_sum(double v) {
 // ldsout.  Lane 16 q + s of a wave takes column 4 g + q of a group g and
 // rows s, s + 16, ..., s + 16 (R - 1), so each load instruction reads 128
 // contiguous bytes of 4 columns; a 16-lane sum finishes each column.  Wave w
-// takes groups w U .. w U + U - 1, then every 8 U-th.  With colsq, the sum
+// takes groups w U .. w U + U - 1, then every (waves * U)-th.  With colsq, the sum
 // of |a_j|^2 over the n columns (every thread receives it).
 template <int R, bool GATHER>
 __device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, GCI J, int voff, GD out, int ldsout,
@@ -124,7 +131,7 @@ __device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, GCI J, int 
   double sq = 0.0;
   constexpr int U = 32 / R > 8 ? 8 : 32 / R;  // groups per round (about 32 loads)
   const int64_t ngroups = (n + 3) / 4;
-  const int64_t stride = (int64_t)kSmWaves * U;
+  const int64_t stride = (int64_t)c.nw * U;
   // loads of a round (columns clamped to n - 1: a round past the end reads
   // in bounds and stores nothing)
   auto load = [&](double (&a)[U][R], int64_t g0) {
@@ -194,9 +201,9 @@ __device__ __forceinline__ void sm_atv(GCD A, int64_t lda, int64_t n, GCI J, int
 }
 
 // out[i] = sum_{k<r} A[i, J[k]] coef[k] for i < m (coef global), into LDS at
-// offset ooff.  Lane l takes rows l and l + 64; wave w takes k = w, w + 8,
-// ... (eight at a time); the per-wave partial m-vectors are added in wave
-// order.
+// offset ooff.  Lane l takes rows l and l + 64; wave w takes k = w, w +
+// waves, ... (eight at a time); the per-wave partial m-vectors are added in
+// wave order.
 __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int64_t r, int ooff, SmallCtx c) {
   const int m = c.m;
   const int l0 = c.lane, l1 = c.lane + kWave;
@@ -204,11 +211,11 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int6
   const bool two = m > kWave;
   double s0 = 0.0, s1 = 0.0;
   constexpr int U = 8;
-  for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)kSmWaves * U) {
+  for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)c.nw * U) {
     double a0[U], a1[U], cf[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t k = k0 + (int64_t)kSmWaves * u;
+      const int64_t k = k0 + (int64_t)c.nw * u;
       const int64_t kc = k < r ? k : r - 1;
       GCD col = A + (int64_t)J[kc] * lda;
       a0[u] = col[r0];
@@ -226,7 +233,7 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int6
   __syncthreads();
   if (c.tid < m) {
     double t = sl().part[0][c.tid];
-    for (int w = 1; w < kSmWaves; ++w) t += sl().part[w][c.tid];
+    for (int w = 1; w < c.nw; ++w) t += sl().part[w][c.tid];
     sm_dyn[ooff + c.tid] = t;
   }
   __syncthreads();
@@ -243,7 +250,7 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, GCI J, int64_t r, int f
   const int64_t K = form ? (int64_t)m : r;
   const int nbk = (N + 15) / 16;
   const int nblk = nbk * (nbk + 1) / 2;
-  for (int blk = c.wid; blk < nblk; blk += kSmWaves) {
+  for (int blk = c.wid; blk < nblk; blk += c.nw) {
     int bi = (int)((sqrtf(8.0f * (float)blk + 1.0f) - 1.0f) * 0.5f);
     while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
     while (bi * (bi + 1) / 2 > blk) --bi;
@@ -287,7 +294,7 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, GCI J, int64_t r, int f
       if (row < N && col <= row) {
         const double e = form ? acc[v] + (row == col ? 1.0 / kappa : 0.0)
                               : fma(kappa, acc[v], row == col ? 1.0 : 0.0);
-        M[row * c.P + col] = e;
+        M[tri(row) + col] = e;
       }
     }
   }
@@ -317,14 +324,13 @@ constexpr double kSmMinPivot = 2.2250738585072014e-308;
 // Returns the first non-positive pivot's row + 1, or 0.
 __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
   double* M = sm_mat();
-  const int P = c.P;
   for (int j0 = 0; j0 < N; j0 += 8) {
     const int w = N - j0 < 8 ? N - j0 : 8;
     double l[8][8], rl[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int k = 0; k <= i; ++k) l[i][k] = (i < w) ? M[(j0 + i) * P + j0 + k] : (i == k ? 1.0 : 0.0);
+      for (int k = 0; k <= i; ++k) l[i][k] = (i < w) ? M[tri(j0 + i) + j0 + k] : (i == k ? 1.0 : 0.0);
     int bad = -1;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -348,18 +354,18 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
       return j0 + bad + 1;  // the same in every thread
     }
     // the rows below the pivot block: x L^T = (their 8 entries)
-    for (int R = j0 + w + c.tid; R < N; R += kSmNT) {
+    for (int R = j0 + w + c.tid; R < N; R += c.nt) {
       double x[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        double u = k < w ? M[R * P + j0 + k] : 0.0;
+        double u = k < w ? M[tri(R) + j0 + k] : 0.0;
 #pragma unroll
         for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
         x[k] = u * rl[k];
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (k < w) M[R * P + j0 + k] = x[k];
+        if (k < w) M[tri(R) + j0 + k] = x[k];
     }
     __syncthreads();
     // the pivot block's L and 1 / L_kk (compile-time row index: l stays in registers)
@@ -369,24 +375,24 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
         if (c.tid == i) {
           sl().idg[j0 + i] = rl[i];
 #pragma unroll
-          for (int k = 0; k <= i; ++k) M[(j0 + i) * P + j0 + k] = l[i][k];
+          for (int k = 0; k <= i; ++k) M[tri(j0 + i) + j0 + k] = l[i][k];
         }
     }
     // trailing update: M[i][j] -= sum_k L[i][j0+k] L[j][j0+k], j0+w <= j <= i < N
     const int b = j0 + w, nt = N - b;
     const int ne = nt * (nt + 1) / 2;
-    for (int e = c.tid; e < ne; e += kSmNT) {
+    for (int e = c.tid; e < ne; e += c.nt) {
       int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
       while ((i + 1) * (i + 2) / 2 <= e) ++i;
       while (i * (i + 1) / 2 > e) --i;
       const int j = e - i * (i + 1) / 2;
-      const double* Li = M + (b + i) * P + j0;
-      const double* Lj = M + (b + j) * P + j0;
-      double s = M[(b + i) * P + b + j];
+      const double* Li = M + tri(b + i) + j0;
+      const double* Lj = M + tri(b + j) + j0;
+      double s = M[tri(b + i) + b + j];
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (k < w) s = fma(-Li[k], Lj[k], s);
-      M[(b + i) * P + b + j] = s;
+      M[tri(b + i) + b + j] = s;
     }
     __syncthreads();
   }
@@ -401,7 +407,6 @@ __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallC
   if (c.wid == 0) {
     const double* M = sm_mat();
     const double* idg = sl().idg;
-    const int P = c.P;
     const int l0 = c.lane, l1 = c.lane + kWave;
     const int c0 = l0 < N ? l0 : N - 1, c1 = l1 < N ? l1 : N - 1;  // rows read (in the factor)
     double z0 = l0 < N ? sm_dyn[rhs_off + l0] : 0.0, z1 = l1 < N ? sm_dyn[rhs_off + l1] : 0.0;
@@ -413,8 +418,8 @@ __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallC
       for (int u = 0; u < 8; ++u) {
         const int k = k0 + u < N ? k0 + u : N - 1;
         ig[u] = idg[k];
-        m0[u] = M[c0 * P + k];
-        m1[u] = M[c1 * P + k];
+        m0[u] = M[tri(c0) + k];  // used for k < c0 only; in bounds for any k < N
+        m1[u] = M[tri(c1) + k];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -436,8 +441,8 @@ __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallC
       for (int u = 0; u < 8; ++u) {
         const int k = k0 - u >= 0 ? k0 - u : 0;
         ig[u] = idg[k];
-        m0[u] = M[k * P + c0];
-        m1[u] = M[k * P + c1];
+        m0[u] = M[tri(k) + c0];  // used for c0 < k only; in bounds for any c0 < N
+        m1[u] = M[tri(k) + c1];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -465,7 +470,7 @@ __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallC
 // and u_J at the wave's offset.  Returns r.
 __device__ __noinline__ int64_t sm_prox(GD x, GD wy, GCD wd, int64_t n, double s, double sigma, double thr,
                                         double den, GI J, GD uJ, SmallCtx c) {
-  const int64_t S = ((n + kSmNT - 1) / kSmNT) * kWave;
+  const int64_t S = ((n + c.nt - 1) / c.nt) * kWave;
   const int64_t lo = (int64_t)c.wid * S;
   const int64_t hi = lo + S < n ? lo + S : n;
   int cnt = 0;
@@ -485,7 +490,7 @@ __device__ __noinline__ int64_t sm_prox(GD x, GD wy, GCD wd, int64_t n, double s
   if (c.lane == 0) sl().cnt[c.wid] = cnt;
   __syncthreads();
   int base = 0, r = 0;
-  for (int w2 = 0; w2 < kSmWaves; ++w2) {
+  for (int w2 = 0; w2 < c.nw; ++w2) {
     const int v = sl().cnt[w2];
     base += w2 < c.wid ? v : 0;
     r += v;
@@ -527,7 +532,7 @@ __device__ __noinline__ int sm_linesearch(GCD x, GCD wy, GCD wd, int64_t n, doub
 #pragma unroll
     for (int k = 0; k < kSmLsChunk; ++k) sk[k] = k0 + k < K ? ts[k0 + k] : 0.0;
 #pragma unroll 1
-    for (int64_t i = c.tid; i < n; i += kSmNT) {
+    for (int64_t i = c.tid; i < n; i += c.nt) {
       const double t0 = fma(-sigma, wy[i], x[i]);
       const double wi = wd[i];
       const double a0 = fabs(t0);
@@ -562,12 +567,14 @@ __device__ __noinline__ int sm_linesearch(GCD x, GCD wy, GCD wd, int64_t n, doub
 
 }  // namespace
 
-__global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restrict__ probs, SmallArgs one,
+__global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __restrict__ probs, SmallArgs one,
                                                        SmallOpts o, Pub pub) {
   SmallCtx c;
   c.tid = threadIdx.x;
   c.lane = c.tid & (kWave - 1);
   c.wid = __builtin_amdgcn_readfirstlane(c.tid / kWave);
+  c.nt = blockDim.x;
+  c.nw = c.nt / kWave;
   const SmallArgs pr = probs ? probs[blockIdx.x] : one;
   GCD A = (GCD)pr.A;
   GCD bvec = (GCD)pr.b;
@@ -580,7 +587,6 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
   const int64_t lda = pr.lda, n = pr.n;
   const int m = pr.m;
   c.m = m;
-  c.P = m + 1;
   SmallLds& L = sl();
   const double l1 = pr.l1, l2 = pr.l2, tol = pr.tol;
 
@@ -592,7 +598,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
   if (pr.x0) {
     // support of x0 (as a compaction with threshold 0), then y = A_S x0_S - b
     int bad_x0 = 0;
-    for (int64_t i = c.tid; i < n; i += kSmNT) {
+    for (int64_t i = c.tid; i < n; i += c.nt) {
       const double xi = x0[i];
       bad_x0 |= !(fabs(xi) < INFINITY);
       x[i] = xi;
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
     sm_gather(A, lda, J, uJ, r, kOffY, c);
     if (c.tid < m) L.y[c.tid] -= L.b[c.tid];
   } else {
-    for (int64_t i = c.tid; i < n; i += kSmNT) x[i] = 0.0;
+    for (int64_t i = c.tid; i < n; i += c.nt) x[i] = 0.0;
     if (c.tid < m) L.y[c.tid] = -L.b[c.tid];
   }
   __syncthreads();
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
         }
         sm_chol_solve(N, kOffQ, kOffQ, c);
         // d = -g + A_J q (q staged in w_d, which the pass below rewrites)
-        for (int k = c.tid; k < N; k += kSmNT) wd[k] = L.q[k];
+        for (int k = c.tid; k < N; k += c.nt) wd[k] = L.q[k];
         __syncthreads();
         sm_gather(A, lda, J, wd, r, kOffD, c);
         if (c.tid < m) L.d[c.tid] -= L.g[c.tid];
@@ -718,7 +724,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
     if (chol_bad || nonfinite) break;
     // ---- multiplier update x <- prox(x - sigma w_y), kkt3
     double s3[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = c.tid; i < n; i += kSmNT) {
+    for (int64_t i = c.tid; i < n; i += c.nt) {
       const double xi = x[i];
       const double t = fma(-sigma, wy[i], xi);
       const double u = prox_en(t, thr, den);
@@ -741,7 +747,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
       double s4[4] = {0.0, 0.0, 0.0, 0.0};
       double mx = 0.0;  // |A^T rho|_inf, for the Lasso's scaled dual point
       const double den1 = 1.0 + l2;
-      for (int64_t i = c.tid; i < n; i += kSmNT) {
+      for (int64_t i = c.tid; i < n; i += c.nt) {
         const double xi = x[i], qi = wd[i];
         const double p = prox_en(xi - qi, l1, den1);
         const double ee = xi - p;
@@ -758,7 +764,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
       if (c.lane == 0) L.red[c.wid] = mx;
       __syncthreads();
       double am = L.red[0];
-      for (int w2 = 1; w2 < kSmWaves; ++w2) am = fmax(am, L.red[w2]);
+      for (int w2 = 1; w2 < c.nw; ++w2) am = fmax(am, L.red[w2]);
       __syncthreads();
       eta = sqrt(s4[0]) / (1.0 + sqrt(s4[1]) + sqrt(RR));
       F = 0.5 * RR + l1 * s4[2] + 0.5 * l2 * s4[1];
@@ -805,7 +811,7 @@ __global__ __launch_bounds__(kSmNT) void k_solve_small(const SmallArgs* __restri
 }
 
 size_t small_lds_bytes(int mmax) {
-  return sizeof(SmallLds) + sizeof(double) * (size_t)mmax * (size_t)(mmax + 1);
+  return sizeof(SmallLds) + sizeof(double) * (size_t)mmax * (size_t)(mmax + 1) / 2;
 }
 
 hipError_t small_init() {

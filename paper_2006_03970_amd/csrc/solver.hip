@@ -444,7 +444,7 @@ void certificate_values(const double* hs, double l1, double l2, double* eta, dou
 // kSmallMaxMN = m n (where the per-step passes of one CU over A catch up with
 // the launch overhead they replace); a batch, whose problems fill the CUs side
 // by side, up to kSmallBatchMaxMN.
-constexpr int64_t kSmallMaxMN = (int64_t)1 << 19;
+constexpr int64_t kSmallMaxMN = (int64_t)1 << 17;
 constexpr int64_t kSmallBatchMaxMN = (int64_t)1 << 21;
 
 bool small_ok(int dt, int64_t m, int64_t n, const ssnal_en_opts& o, int64_t max_mn) {

@@ -243,7 +243,8 @@ def test_server_refuses_bad_requests(gpu):
 def test_batch_workers_bitwise(gpu, ctx, workers):
     """The batch entry on 1, 3 and 8 concurrent workers gives the bits of each
     problem solved alone (small Gaussian problems of the single-solve
-    workload's shape, two with their own sigma0)."""
+    workload's shape, two with their own sigma0), on the multi-kernel path
+    (opts.no_small; in one workgroup a batch takes no workers)."""
     import datagen
     import torch
     from paper_2006_03970_amd.device import design_to_device, vec_to_device
@@ -253,13 +254,13 @@ def test_batch_workers_bitwise(gpu, ctx, workers):
         p = datagen.make_problem("c1", seed=200 + s)
         A, b = design_to_device(p.AT, "f64"), vec_to_device(p.b)
         sig = 0.05 if s in (3, 7) else 0.0
-        opts = gpu.make_opts(sigma0=sig) if sig else None
+        opts = gpu.make_opts(sigma0=sig, no_small=1) if sig else gpu.make_opts(no_small=1)
         xa, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=opts)
         assert info["status"] == 0
         alone.append(xa.clone())
         probs.append(dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, sigma0=sig,
                           x_out=torch.full((p.n,), float("nan"), dtype=torch.float64, device=A.device)))
-    infos, rc = gpu.ssnal_en_solve_batch(ctx, probs, workers=workers)
+    infos, rc = gpu.ssnal_en_solve_batch(ctx, probs, opts=gpu.make_opts(no_small=1), workers=workers)
     torch.cuda.synchronize()
     assert rc == 0
     for q, xa, info in zip(probs, alone, infos):

@@ -46,17 +46,37 @@ def _check_vs_oracle(orc, p, x, info, tol):
     return xr, ir
 
 
+def _solve1(gpu, ctx, A, b, p, tol, x0=None, x_out=None, opts=None, m=None):
+    """A single solve that runs in one workgroup: ssnal_en_solve below the
+    single-solve limit (m n <= 2^17), else a batch of one (m n <= 2^21)."""
+    import torch
+    if p.m * p.n <= 1 << 17:
+        return gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x0, x_out=x_out, tol=tol, opts=opts, m=m)
+    assert m is None or m == A.shape[1]
+    if x_out is None:
+        x_out = torch.empty(p.n, dtype=torch.float64, device=A.device)
+    pr = dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=tol, x_out=x_out, x0=x0,
+              sigma0=opts.sigma0 if opts is not None else 0.0)
+    infos, _ = gpu.ssnal_en_solve_batch(ctx, [pr], opts=opts)
+    return x_out, infos[0]
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_c1_one_workgroup_vs_oracle(gpu, ctx, orc, seed):
-    """m=100, n=2000 Gaussian design, tol 1e-10, in one workgroup."""
+    """m=100, n=2000 Gaussian design, tol 1e-10, in one workgroup (a batch of
+    one: a single C1 solve is above the single-solve limit)."""
     import datagen
     p = datagen.make_problem("c1", seed=seed)
     _say("c1 one workgroup seed", seed)
     A, b = _upload(p)
-    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x, info = _solve1(gpu, ctx, A, b, p, p.tol)
     assert info["one_workgroup"] == 1
     assert info["syncs"] == 1
     _check_vs_oracle(orc, p, x.cpu().numpy(), info, p.tol)
+    # alone it takes the multi-kernel path and reaches the same minimiser
+    xs, si = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    assert si["one_workgroup"] == 0
+    assert np.max(np.abs(xs.cpu().numpy() - x.cpu().numpy())) <= 1e-9
 
 
 def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
@@ -66,7 +86,7 @@ def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
     p = datagen.make_problem("c1", seed=11)
     A, b = _upload(p)
     _say("one workgroup vs multi-kernel")
-    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x1, i1 = _solve1(gpu, ctx, A, b, p, p.tol)
     x2, i2 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(no_small=1))
     assert i1["one_workgroup"] == 1 and i2["one_workgroup"] == 0
     x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
@@ -79,25 +99,27 @@ def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
           f"{i1['newton_iters']}/{i2['newton_iters']} passes {i1['gemv_calls']}/{i2['gemv_calls']}")
 
 
-@pytest.mark.parametrize("m,n,k,c_lam", [(37, 2001, 5, 0.5), (120, 4000, 12, 0.5), (64, 513, 40, 0.05),
-                                         (100, 40, 8, 0.5)])
+@pytest.mark.parametrize("m,n,k,c_lam", [(37, 2001, 5, 0.5), (120, 1092, 12, 0.5), (64, 513, 40, 0.05),
+                                         (100, 40, 8, 0.5), (120, 17000, 12, 0.5)])
 def test_ragged_and_maximum_shapes(gpu, ctx, orc, m, n, k, c_lam):
     """m off the 16-row MFMA blocks and the 8-column Cholesky panels, n off the
-    512-feature chunks, the largest m (120) at m n <= 2^19, m > n, and an
-    active set larger than m (160 of 513 at m = 64: the m x m system)."""
+    feature slabs, the largest m (120) at the single-solve limit m n <= 2^17
+    and near the batch limit 2^21 (a batch of one), m > n, and an active set
+    larger than m (160 of 513 at m = 64: the m x m system)."""
     import datagen
     p = datagen.make_problem("c1", seed=m + n, m=m, n=n, k=k, c_lam=c_lam)
     A, b = _upload(p)
     _say("one workgroup shape", m, n, k)
-    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
+    x, info = _solve1(gpu, ctx, A, b, p, p.tol)
     assert info["one_workgroup"] == 1
     _check_vs_oracle(orc, p, x.cpu().numpy(), info, p.tol)
 
 
 def test_beyond_limits_takes_multi_kernel_path(gpu, ctx):
-    """m = 121, or m n above 2^19, or FP32 storage: the multi-kernel path."""
+    """m = 121, or m n above 2^17 for a single solve, or FP32 storage: the
+    multi-kernel path."""
     import datagen
-    for m, n, store in [(121, 1000, "f64"), (100, 5300, "f64"), (100, 2000, "f32")]:
+    for m, n, store in [(121, 1000, "f64"), (100, 1400, "f64"), (100, 1000, "f32")]:
         p = datagen.make_problem("c1", seed=3, m=m, n=n, store=store)
         A, b = _upload(p)
         _say("multi-kernel", m, n, store)
@@ -112,7 +134,7 @@ def test_lasso_limit(gpu, ctx, orc):
     p.lam2 = 0.0
     A, b = _upload(p)
     _say("lasso one workgroup")
-    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, 0.0, tol=1e-9)
+    x, info = _solve1(gpu, ctx, A, b, p, 1e-9)
     assert info["one_workgroup"] == 1
     x = x.cpu().numpy()
     assert info["status"] == 0, info
@@ -131,8 +153,8 @@ def test_woodbury_and_full_system_agree(gpu, ctx, orc):
     p = datagen.make_problem("c1", seed=13, k=4, c_lam=0.8)
     A, b = _upload(p)
     _say("woodbury vs m x m")
-    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
-    x2, i2 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(no_smw=1))
+    x1, i1 = _solve1(gpu, ctx, A, b, p, p.tol)
+    x2, i2 = _solve1(gpu, ctx, A, b, p, p.tol, opts=gpu.make_opts(no_smw=1))
     assert i1["one_workgroup"] == 1 and i2["one_workgroup"] == 1
     assert 0 < i1["nnz"] < p.m
     x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
@@ -183,7 +205,7 @@ def test_warm_start_padded_lda_aliased(gpu, ctx, orc):
     """lda > m with NaN padding rows (never read); a warm start from another
     point, with x0 the output buffer itself, reaches the same minimiser."""
     import datagen
-    p = datagen.make_problem("c1", seed=14)
+    p = datagen.make_problem("c1", seed=14, n=1000)
     A, b = _upload(p, lda=p.m + 4)
     _say("warm start, padded lda, x0 == x_out")
     x_cold, ic = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, m=p.m)
@@ -200,7 +222,7 @@ def test_errors_and_status(gpu, ctx):
     """Non-finite b or x0: SSNAL_ENONFINITE; max_outer = 1 at a tight tol:
     SSNAL_NOT_CONVERGED with the certificates of the returned point."""
     import datagen
-    p = datagen.make_problem("c1", seed=15)
+    p = datagen.make_problem("c1", seed=15, n=1000)
     A, b = _upload(p)
     _say("errors one workgroup")
     bn = b.clone()
@@ -225,20 +247,23 @@ def test_errors_and_status(gpu, ctx):
 def test_repeat_bitwise(gpu, ctx):
     """Fixed-order sums: two one-workgroup solves agree bit for bit."""
     import datagen
-    p = datagen.make_problem("c1", seed=16)
+    p = datagen.make_problem("c1", seed=16, n=1000)
     A, b = _upload(p)
     _say("repeat one workgroup")
-    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
     x2, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert i1["one_workgroup"] == 1
     assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
 
 
 def test_batch_one_launch_matches_single(gpu, ctx, orc):
-    """A batch of 40 problems: 32 small FP64 ones (m from 20 to 120, per-problem
-    sigma0 on some) run as one launch, one workgroup each, beside 8 others
-    (m = 160, FP32 storage) on the workers.  Each small problem's result is
-    bit for bit its single solve's (same kernel, same summation order), and
-    every problem meets the oracle bar."""
+    """A batch of 40 problems: 32 small FP64 ones (m from 20 to 120, m n up to
+    4.2e5, above the single-solve limit of 2^17; per-problem sigma0 on some)
+    run as one launch, one workgroup each, beside 8 others (m = 160, FP32
+    storage) on the workers.  A small problem whose single solve also runs in
+    one workgroup gives the same bits (same kernel, same summation order);
+    one past the single-solve limit agrees with the multi-kernel solve to
+    1e-9; every problem meets the oracle bar."""
     import datagen
     import torch
     probs, keep, ref = [], [], []
@@ -265,5 +290,9 @@ def test_batch_one_launch_matches_single(gpu, ctx, orc):
         if i < 32:
             opts = gpu.make_opts(sigma0=pr["sigma0"]) if pr["sigma0"] > 0 else None
             A, b = _upload(p)
-            xs, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=opts)
-            assert np.array_equal(xs.cpu().numpy(), x), i
+            xs, si = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=opts)
+            assert si["one_workgroup"] == (1 if p.m * p.n <= 1 << 17 else 0), (i, si)
+            if si["one_workgroup"]:
+                assert np.array_equal(xs.cpu().numpy(), x), i
+            else:
+                assert np.max(np.abs(xs.cpu().numpy() - x)) <= 1e-9, i
