@@ -24,8 +24,10 @@ against the FP64 peak; `concurrent`, 64 copies of the same solve through
 the batch entry on 4 and 8 workers (aggregate solves/s of independent
 solves sharing the GPU, FP32 and FP64 storage; --no-concurrent); and
 further sections (each can be skipped): the
-m=100, n=2000 single solve, alone and batched B in {1, 64, 1024} over the
-batch entry's 8 workers (--no-c1); the m=1000, n=1e6 single solve in
+m=100, n=2000 single solve, alone and batched B in {1, 64, 1024}, batches
+as one launch with one workgroup a problem and, beside it, on the batch
+entry's 8 workers with the multi-kernel path (--no-c1, or --c1-only); the
+m=1000, n=1e6 single solve in
 FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
 gcv / e-bic at every point and 10-fold cross validation (--no-path); a
 long-column Newton-CG solve, m=20000, n=2e5 (--no-cg, or --cg-only); the
@@ -255,10 +257,13 @@ def cg_bench(reps=2, r_fixed=16000):
 
 def c1_bench(single_reps=200, batches=(1, 64, 1024)):
     """The single-solve workload (m=100, n=2000 Gaussian, FP64, tol 1e-10):
-    back-to-back single solves of one problem on one stream, then batches of
-    B independent problems (B seeds) through ssnal_en_solve_batch on its
-    default 8 concurrent workers.  Latency-bound: the design (1.6 MB) lives in
-    the caches, so solves/s is the figure, not bandwidth."""
+    back-to-back single solves of one problem on one stream (the multi-kernel
+    path: m n = 2e5 is above the one-workgroup limit of a single solve), then
+    batches of B independent problems (B seeds) through ssnal_en_solve_batch:
+    one launch, one workgroup a problem (the default; B = 1 is the same
+    problem in one workgroup), and on 8 concurrent workers with the
+    multi-kernel path (opts.no_small).  Latency-bound: the design (1.6 MB)
+    lives in the caches, so solves/s is the figure, not bandwidth."""
     import torch
 
     import datagen
@@ -296,38 +301,27 @@ def c1_bench(single_reps=200, batches=(1, 64, 1024)):
            "batched": {}}
     print(f"[bench] c1 single: {1.0 / el:.0f} solves/s (one workgroup: {info['one_workgroup']})",
           file=sys.stderr, flush=True)
-    # the multi-kernel path on the same problem (opts.no_small = 1), for comparison
-    multi = binding.make_opts(no_small=1)
-    for _ in range(3):
-        binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
-                               x_out=q["x_out"], stream=stream, opts=multi)
-    torch.cuda.synchronize()
-    reps = max(single_reps // 4, 10)
-    t = time.perf_counter()
-    for _ in range(reps):
-        _, info = binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
-                                         x_out=q["x_out"], stream=stream, opts=multi)
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t) / reps
-    out["single_multi_kernel"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "status": info["status"],
-                                  "iterations": [info["outer_iters"], info["newton_iters"]]}
     binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream)
     binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream, opts=binding.make_opts(no_small=1))  # workers
+    # the problem descriptors are marshalled before the timed call (host-side
+    # preparation, like the upload of the designs); the timed region is the
+    # library's batch call
     for B in batches:
+        args = binding.batch_args(probs[:B])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        infos, rc = binding.ssnal_en_solve_batch(ctx, probs[:B], stream=stream)
+        infos, rc = binding.solve_batch_args(ctx, args, stream=stream)
         el = time.perf_counter() - t
         out["batched"][str(B)] = {"solves_per_s": B / el, "ms": el * 1e3, "worst_status": rc,
-                                  "max_eta": max(i["kkt_rel"] for i in infos)}
+                                  "max_eta": max(infos[i].kkt_rel for i in range(B))}
         print(f"[bench] c1 batch {B}: {B / el:.0f} solves/s", file=sys.stderr, flush=True)
     out["batched"]["launch"] = "one launch, one workgroup per problem"
     out["batched_multi_kernel"] = {}
     for B in batches:
+        args = binding.batch_args(probs[:B])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        infos, rc = binding.ssnal_en_solve_batch(ctx, probs[:B], stream=stream,
-                                                 opts=binding.make_opts(no_small=1))
+        infos, rc = binding.solve_batch_args(ctx, args, stream=stream, opts=binding.make_opts(no_small=1))
         el = time.perf_counter() - t
         out["batched_multi_kernel"][str(B)] = {"solves_per_s": B / el, "ms": el * 1e3, "worst_status": rc}
         print(f"[bench] c1 batch {B} multi-kernel: {B / el:.0f} solves/s", file=sys.stderr, flush=True)
@@ -759,6 +753,8 @@ def main():
     ap.add_argument("--cg-only", action="store_true", help="run only the Newton-CG section")
     ap.add_argument("--c3-only", action="store_true", help="run only the m=1000, n=1e6 section")
     ap.add_argument("--no-c1", action="store_true", help="skip the m=100, n=2000 single/batched section")
+    ap.add_argument("--c1-only", action="store_true", help="run only the m=100, n=2000 single/batched section")
+    ap.add_argument("--c1-reps", type=int, default=200, help="timed single solves of that section")
     ap.add_argument("--serving", type=int, default=512, help="requests in the serving stream (0 = off)")
     ap.add_argument("--serving-host", type=int, default=128,
                     help="requests of the stream (its first ones) also served from pinned host memory (0 = off)")
@@ -794,6 +790,9 @@ def main():
         return
     if args.c3_only:
         print(json.dumps({"large_single_solve": large_bench()}), flush=True)
+        return
+    if args.c1_only:
+        print(json.dumps({"small_single_solve": c1_bench(single_reps=args.c1_reps)}), flush=True)
         return
     if args.profile_syrk:
         syrk_bench(launches=args.profile_syrk)
@@ -923,7 +922,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_c1:
-        out["small_single_solve"] = c1_bench()
+        out["small_single_solve"] = c1_bench(single_reps=args.c1_reps)
     if not args.no_c3:
         out["large_single_solve"] = large_bench()
     if not args.no_path:

@@ -143,9 +143,14 @@ def _stream(stream):
     return _vp(stream.cuda_stream)
 
 
+_DTYPES = {}
+
+
 def _dtype_code(A):
-    import torch
-    return {torch.float64: SSNAL_F64, torch.float32: SSNAL_F32, torch.bfloat16: SSNAL_BF16}[A.dtype]
+    if not _DTYPES:
+        import torch
+        _DTYPES.update({torch.float64: SSNAL_F64, torch.float32: SSNAL_F32, torch.bfloat16: SSNAL_BF16})
+    return _DTYPES[A.dtype]
 
 
 def _design(A, m):
@@ -392,9 +397,9 @@ def _problem(A, b, lambda1, lambda2, tol, x_out, x0=None, m=None, sigma0=0.0, re
     """ssnal_en_problem of tensors that all live on the device, or all in host
     memory (a served host-resident request)."""
     pA, dt, lda, m, n = _design(A, m)
-    on_host = A.device.type == "cpu"
+    on_host = not A.is_cuda
     for t in (b, x_out, x0):
-        assert t is None or (t.device.type == "cpu") == on_host, "A, b, x0, x_out: all host or all device"
+        assert t is None or t.is_cuda != on_host, "A, b, x0, x_out: all host or all device"
     return Problem(pA, dt, lda, m, n, _ptr(b), float(lambda1), float(lambda2), _ptr(x0), float(tol),
                    _ptr(x_out), float(sigma0), SSNAL_ON_HOST if on_host else SSNAL_ON_DEVICE,
                    None if ready is None else _vp(ready.cuda_event))
@@ -410,20 +415,36 @@ def srv_footprint(A, m=None):
     return int(lib().ssnal_srv_footprint(C.byref(p)))
 
 
-def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None, workers=0):
-    """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0,
-    sigma0].  workers: concurrent workers (0 = the library's default of 8, 1 =
-    in turn on `stream`).  Returns (list of info dicts, worst status)."""
-    cnt = len(problems)
-    arr = (Problem * cnt)(*[_problem(p["A"], p["b"], p["lambda1"], p["lambda2"], p["tol"], p["x_out"],
-                                     p.get("x0"), sigma0=p.get("sigma0", 0.0)) for p in problems])
+def batch_args(problems):
+    """The ssnal_en_problem array of a batch (problems: list of dicts with A,
+    b, lambda1, lambda2, tol, x_out[, x0, sigma0]); the caller keeps the
+    tensors alive while it is in use."""
+    arr = (Problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = _problem(p["A"], p["b"], p["lambda1"], p["lambda2"], p["tol"], p["x_out"], p.get("x0"),
+                          sigma0=p.get("sigma0", 0.0))
+    return arr
+
+
+def solve_batch_args(ctx, arr, opts=None, stream=None, workers=0):
+    """ssnal_en_solve_batch over an array from batch_args.  Returns (the
+    ctypes Info array, worst status)."""
+    cnt = len(arr)
     infos = (Info * cnt)()
     o = opts if opts is not None else make_opts()
     if workers:
         o.workers = int(workers)
     rc = lib().ssnal_en_solve_batch(ctx.ptr, arr, cnt, C.byref(o), _stream(stream), infos)
     _check(rc, allow_warn=True)
-    return [infos[i].as_dict() for i in range(cnt)], rc
+    return infos, rc
+
+
+def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None, workers=0):
+    """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0,
+    sigma0].  workers: concurrent workers (0 = the library's default of 8, 1 =
+    in turn on `stream`).  Returns (list of info dicts, worst status)."""
+    infos, rc = solve_batch_args(ctx, batch_args(problems), opts, stream, workers)
+    return [infos[i].as_dict() for i in range(len(infos))], rc
 
 
 class Server:
