@@ -19,22 +19,47 @@ namespace ssnal {
 // Columns in flight per wave for ITERS loads per lane and element size ES
 // (ES = 0: the long-column kernel).  FP32 columns of two loads per lane keep
 // 4 in flight (fewer registers, more waves: measured faster than 8), BF16
-// ones 8.
-constexpr int cols_for(int iters, int es) {
-  return iters <= 1 ? 8 : (iters <= 2 ? (es == 4 ? 4 : 8) : (iters <= 4 ? 4 : (iters <= 8 ? 2 : 1)));
+// ones 8; FP64 columns of four loads with non-temporal loads 2 (measured at
+// m = 500: 60.2 against 66.0 us for 4 cached).
+constexpr int cols_for(int iters, int es, bool nt = false) {
+  return iters <= 1 ? 8
+                    : (iters <= 2 ? (es == 4 ? 4 : 8)
+                                  : (iters <= 4 ? (nt && es == 8 ? 2 : 4) : (iters <= 8 ? 2 : 1)));
 }
-template <int ITERS, int ES = 0>
+template <int ITERS, int ES = 0, bool NT = false>
 struct ColsFor {
-  static constexpr int value = cols_for(ITERS, ES);
+  static constexpr int value = cols_for(ITERS, ES, NT);
 };
 
-template <typename T, typename ACC, int ITERS, bool COLSQ, int VB>
+// Designs larger than this stream past the Infinity Cache (256 MB): their
+// FP64 passes take non-temporal loads, which do not allocate in the caches
+// (measured: m = 500, n = 1e5, 400 MB: 60.2 against 66.0 us; m = 1000,
+// n = 1e6, 8 GB: 1138 against 1214 us; FP32 and BF16 gain nothing or lose,
+// their smaller designs partly hitting the cache from pass to pass).
+constexpr double kNtBytes = 256.0 * 1024 * 1024;
+
+// VB-byte vector load of VB / 8 doubles that does not allocate in the caches.
+template <int VB>
+__device__ __forceinline__ void loadv_nt(const double* p, double* e) {
+  if constexpr (VB == 16) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 q = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    e[0] = q[0];
+    e[1] = q[1];
+  } else {
+    e[0] = __builtin_nontemporal_load(p);
+  }
+}
+
+// NT: non-temporal loads (FP64 only).
+template <typename T, typename ACC, int ITERS, bool COLSQ, int VB, bool NT = false>
 __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t lda, int m,
                                                 int64_t ncols, const double* __restrict__ v,
                                                 double* __restrict__ w, int64_t cpb,
                                                 double* __restrict__ colsq_part) {
   constexpr int VN = VB / (int)sizeof(T);
-  constexpr int COLS = ColsFor<ITERS, (int)sizeof(T)>::value;
+  constexpr int COLS = ColsFor<ITERS, (int)sizeof(T), NT>::value;
+  static_assert(!NT || (sizeof(T) == 8 && sizeof(ACC) == 8), "non-temporal loads for FP64 designs");
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
 
@@ -65,7 +90,10 @@ __global__ __launch_bounds__(256) void k_gemv_t(const T* __restrict__ A, int64_t
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         const int r0 = (it * kWave + lane) * VN;
-        loadv<VB>(a + (r0 < m ? r0 : 0), e[c][it]);
+        if constexpr (NT)
+          loadv_nt<VB>(reinterpret_cast<const double*>(a + (r0 < m ? r0 : 0)), reinterpret_cast<double*>(e[c][it]));
+        else
+          loadv<VB>(a + (r0 < m ? r0 : 0), e[c][it]);
       }
     }
 #pragma unroll
@@ -238,14 +266,14 @@ bool fits_fast(int vb, int m) {
 }
 
 // ev0/ev1 (nullable): events stamped by the dispatch itself around the kernel.
-template <typename T, typename ACC, bool COLSQ, int VB>
+template <typename T, typename ACC, bool COLSQ, int VB, bool NT = false>
 hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
                        double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
                        hipEvent_t ev1) {
   constexpr int VN = VB / (int)sizeof(T);
   const int need = (m + kWave * VN - 1) / (kWave * VN);
   int iters = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
-  const int cols = cols_for(iters, (int)sizeof(T));
+  const int cols = cols_for(iters, (int)sizeof(T), NT);
   const int64_t step = 4 * (int64_t)cols;
   const int64_t nsteps = (n + step - 1) / step;
   // one column step (4 waves x cols columns) per block: the many short blocks
@@ -263,11 +291,11 @@ hipError_t launch_fast(const T* A, int64_t lda, int m, int64_t n, const double* 
   case IT:                                                                                   \
     if constexpr (IT <= max_iters<T, ACC, VB>()) {                                           \
       if (ev0)                                                                               \
-        hipExtLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, ev0, ev1, 0, A,  \
-                              lda, m, n, v, w, cpb, colsq_part);                             \
+        hipExtLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB, NT>), g, b, 0, st, ev0, ev1, 0, \
+                              A, lda, m, n, v, w, cpb, colsq_part);                          \
       else                                                                                   \
-        hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB>), g, b, 0, st, A, lda, m, n, v, w, \
-                           cpb, colsq_part);                                                 \
+        hipLaunchKernelGGL((k_gemv_t<T, ACC, IT, COLSQ, VB, NT>), g, b, 0, st, A, lda, m, n, v, \
+                           w, cpb, colsq_part);                                              \
     } else {                                                                                 \
       return hipErrorInvalidValue;                                                           \
     }                                                                                        \
@@ -362,6 +390,13 @@ template <typename T, typename ACC, bool COLSQ>
 hipError_t launch_vb(int vb, const T* A, int64_t lda, int m, int64_t n, const double* v, double* w,
                      double* colsq_part, int* nparts, hipStream_t st, hipEvent_t ev0,
                      hipEvent_t ev1) {
+  if constexpr (sizeof(T) == 8 && sizeof(ACC) == 8 && !COLSQ) {
+    if ((double)lda * (double)n * 8.0 > kNtBytes) {
+      if (vb == 16)
+        return launch_fast<T, ACC, COLSQ, 16, true>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
+      return launch_fast<T, ACC, COLSQ, 8, true>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
+    }
+  }
   if (vb == 16)
     return launch_fast<T, ACC, COLSQ, 16>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);
   return launch_fast<T, ACC, COLSQ, 8>(A, lda, m, n, v, w, colsq_part, nparts, st, ev0, ev1);

@@ -47,6 +47,10 @@ GEMV_CASES = [
     # element-wise kernel (stride not a multiple of 8 bytes)
     (502, 1001, "f32", None), (252, 700, "bf16", None), (4000, 300, "bf16", 4004),
     (250, 1500, "bf16", None),
+    # column stride 8 mod 16 bytes with odd column counts, m at the 8-byte
+    # kernel's register caps, and columns shorter than one load
+    (101, 777, "f64", None), (2046, 301, "f32", None), (1020, 1001, "bf16", None),
+    (4, 101, "bf16", None), (2, 3, "f64", 3),
 ]
 
 
