@@ -417,12 +417,13 @@ def srv_footprint(A, m=None):
 
 def batch_args(problems):
     """The ssnal_en_problem array of a batch (problems: list of dicts with A,
-    b, lambda1, lambda2, tol, x_out[, x0, sigma0]); the caller keeps the
-    tensors alive while it is in use."""
+    b, lambda1, lambda2, tol, x_out[, x0, sigma0, m (rows when A's leading
+    dimension is padded)]); the caller keeps the tensors alive while it is in
+    use."""
     arr = (Problem * len(problems))()
     for i, p in enumerate(problems):
         arr[i] = _problem(p["A"], p["b"], p["lambda1"], p["lambda2"], p["tol"], p["x_out"], p.get("x0"),
-                          sigma0=p.get("sigma0", 0.0))
+                          m=p.get("m"), sigma0=p.get("sigma0", 0.0))
     return arr
 
 
@@ -441,7 +442,7 @@ def solve_batch_args(ctx, arr, opts=None, stream=None, workers=0):
 
 def ssnal_en_solve_batch(ctx, problems, opts=None, stream=None, workers=0):
     """problems: list of dicts with A, b, lambda1, lambda2, tol, x_out[, x0,
-    sigma0].  workers: concurrent workers (0 = the library's default of 8, 1 =
+    sigma0, m].  workers: concurrent workers (0 = the library's default of 8, 1 =
     in turn on `stream`).  Returns (list of info dicts, worst status)."""
     infos, rc = solve_batch_args(ctx, batch_args(problems), opts, stream, workers)
     return [infos[i].as_dict() for i in range(len(infos))], rc

@@ -52,10 +52,9 @@ def _solve1(gpu, ctx, A, b, p, tol, x0=None, x_out=None, opts=None, m=None):
     import torch
     if p.m * p.n <= 1 << 17:
         return gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x0, x_out=x_out, tol=tol, opts=opts, m=m)
-    assert m is None or m == A.shape[1]
     if x_out is None:
         x_out = torch.empty(p.n, dtype=torch.float64, device=A.device)
-    pr = dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=tol, x_out=x_out, x0=x0,
+    pr = dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=tol, x_out=x_out, x0=x0, m=m,
               sigma0=opts.sigma0 if opts is not None else 0.0)
     infos, _ = gpu.ssnal_en_solve_batch(ctx, [pr], opts=opts)
     return x_out, infos[0]
@@ -296,3 +295,56 @@ def test_batch_one_launch_matches_single(gpu, ctx, orc):
                 assert np.array_equal(xs.cpu().numpy(), x), i
             else:
                 assert np.max(np.abs(xs.cpu().numpy() - x)) <= 1e-9, i
+
+
+def test_batch_padded_lda_warm_start(gpu, ctx, orc):
+    """Batched one-workgroup solves of a C1 problem (above the single-solve
+    limit) with lda > m and NaN padding rows, cold and warm-started from
+    another point with x0 the output buffer itself: both reach the oracle's
+    minimiser."""
+    import datagen
+    p = datagen.make_problem("c1", seed=17)
+    A, b = _upload(p, lda=p.m + 4)
+    _say("batch: padded lda + warm start")
+    x_cold, ic = _solve1(gpu, ctx, A, b, p, 1e-10, m=p.m)
+    assert ic["one_workgroup"] == 1 and ic["status"] == 0
+    q = datagen.make_problem("c1", seed=17)
+    q.lam1, q.lam2 = p.lam1 * 1.2, p.lam2 * 1.2
+    x1, _ = _solve1(gpu, ctx, A, b, q, 1e-10, m=p.m)
+    x_warm, iw = _solve1(gpu, ctx, A, b, p, 1e-10, x0=x1, x_out=x1, m=p.m)
+    assert iw["one_workgroup"] == 1 and iw["status"] == 0
+    xr, _, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-11)
+    assert np.max(np.abs(x_cold.cpu().numpy() - xr)) <= 1e-8
+    assert np.max(np.abs(x_warm.cpu().numpy() - xr)) <= 1e-8
+
+
+def test_served_small_requests(gpu, ctx, orc):
+    """Small FP64 requests through the serving loop run in one workgroup:
+    each result is its single solve's bits, alone or in a mix with a larger
+    FP32 request, and meets the oracle bar."""
+    import datagen
+    import torch
+    reqs = []
+    for i, (m, n, store) in enumerate([(40, 900, "f64"), (100, 1200, "f64"), (300, 20000, "f32"),
+                                       (64, 2000, "f64")]):
+        p = datagen.make_problem("c1", seed=300 + i, m=m, n=n, store=store)
+        A, b = _upload(p)
+        xa, ia = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-9)
+        assert ia["status"] == 0 and ia["one_workgroup"] == (1 if store == "f64" else 0)
+        reqs.append((p, A, b, xa.clone(), torch.full((n,), float("nan"), dtype=torch.float64,
+                                                   device=A.device)))
+    torch.cuda.synchronize()
+    _say("served small requests")
+    srv = gpu.Server(0, hbm_budget=2 << 30, max_slots=3)
+    try:
+        tickets = [srv.submit(A, b, p.lam1, p.lam2, 1e-9, x) for p, A, b, _, x in reqs]
+        infos = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    for (p, A, b, xa, x), info in zip(reqs, infos):
+        assert info["status"] == 0, info
+        assert bool((x == xa).all())
+        if p.store == "f64":
+            assert info["one_workgroup"] == 1
+            check_eta(orc, p.AT, p.b, x.cpu().numpy(), p.lam1, p.lam2, 1e-9, eta_gpu=info["kkt_rel"])
