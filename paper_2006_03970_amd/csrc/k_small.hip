@@ -35,6 +35,8 @@
 // the kernel's dynamic LDS array and global memory through address-space-1
 // pointers, so the compiler emits LDS and global instructions rather than
 // generic ones.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -208,7 +210,6 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int6
   const int m = c.m;
   const int l0 = c.lane, l1 = c.lane + kWave;
   const int r0 = l0 < m ? l0 : 0, r1 = l1 < m ? l1 : 0;
-  const bool two = m > kWave;
   double s0 = 0.0, s1 = 0.0;
   constexpr int U = 8;
   for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)c.nw * U) {
@@ -219,8 +220,9 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int6
       const int64_t kc = k < r ? k : r - 1;
       GCD col = A + (int64_t)J[kc] * lda;
       a0[u] = col[r0];
-      a1[u] = two ? col[r1] : 0.0;
-      cf[u] = k < r ? coef[kc] : 0.0;
+      a1[u] = col[r1];  // unconditional (row clamped): a load in a branch would wait at the join
+      cf[u] = coef[kc];
+      cf[u] = k < r ? cf[u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -263,30 +265,38 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, GCI J, int64_t r, int f
     GCD cb = A + (int64_t)(form ? J[pbc] : 0) * lda;
     dbl4 acc = dbl4{0, 0, 0, 0};
     constexpr int U = 16;
-    for (int64_t k0 = 0; k0 < K; k0 += 4 * U) {
-      double av[U], bv[U];
-      bool ok[U];
+    // the form is decided outside the load loops: a load in a branch would
+    // wait at the join, serialising the U loads
+    auto contract = [&](auto gathered_rows) {
+      for (int64_t k0 = 0; k0 < K; k0 += 4 * U) {
+        double av[U], bv[U];
+        bool ok[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t kk = k0 + 4 * u + c.lane / 16;
-        ok[u] = kk < K;
-        const int64_t kc = ok[u] ? kk : K - 1;
-        if (form) {
-          av[u] = ca[kc];
-          bv[u] = cb[kc];
-        } else {
-          GCD col = A + (int64_t)J[kc] * lda;
-          av[u] = col[pac];
-          bv[u] = col[pbc];
+        for (int u = 0; u < U; ++u) {
+          const int64_t kk = k0 + 4 * u + c.lane / 16;
+          ok[u] = kk < K;
+          const int64_t kc = ok[u] ? kk : K - 1;
+          if constexpr (decltype(gathered_rows)::value) {
+            GCD col = A + (int64_t)J[kc] * lda;
+            av[u] = col[pac];
+            bv[u] = col[pbc];
+          } else {
+            av[u] = ca[kc];
+            bv[u] = cb[kc];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double a = (ok[u] & oka) ? av[u] : 0.0;
+          const double b = (ok[u] & okb) ? bv[u] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double a = (ok[u] & oka) ? av[u] : 0.0;
-        const double b = (ok[u] & okb) ? bv[u] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-      }
-    }
+    };
+    if (form)
+      contract(std::false_type{});
+    else
+      contract(std::true_type{});
     // accumulator v holds row lane/16 + 4v, column lane%16 of the block
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -327,10 +337,19 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
   for (int j0 = 0; j0 < N; j0 += 8) {
     const int w = N - j0 < 8 ? N - j0 : 8;
     double l[8][8], rl[8];
+    // unconditional loads (rows and columns clamped into the block), then
+    // the identity past its w rows: a load in a branch would wait at the join
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int k = 0; k <= i; ++k) l[i][k] = (i < w) ? M[tri(j0 + i) + j0 + k] : (i == k ? 1.0 : 0.0);
+      for (int k = 0; k <= i; ++k) {
+        const int ic = i < w ? i : w - 1, kc = k <= ic ? k : ic;
+        l[i][k] = M[tri(j0 + ic) + j0 + kc];
+      }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int k = 0; k <= i; ++k) l[i][k] = (i < w) ? l[i][k] : (i == k ? 1.0 : 0.0);
     int bad = -1;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -355,10 +374,12 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
     }
     // the rows below the pivot block: x L^T = (their 8 entries)
     for (int R = j0 + w + c.tid; R < N; R += c.nt) {
-      double x[8];
+      double x[8], raw[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) raw[k] = M[tri(R) + j0 + (k < w ? k : w - 1)];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        double u = k < w ? M[tri(R) + j0 + k] : 0.0;
+        double u = k < w ? raw[k] : 0.0;
 #pragma unroll
         for (int q = 0; q < k; ++q) u = fma(-x[q], l[k][q], u);
         x[k] = u * rl[k];
@@ -389,9 +410,14 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
       const double* Li = M + tri(b + i) + j0;
       const double* Lj = M + tri(b + j) + j0;
       double s = M[tri(b + i) + b + j];
+      double li[8], lj[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < w) s = fma(-Li[k], Lj[k], s);
+      for (int k = 0; k < 8; ++k) {
+        li[k] = Li[k < w ? k : w - 1];
+        lj[k] = Lj[k < w ? k : w - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s = fma(k < w ? -li[k] : 0.0, lj[k], s);
       M[tri(b + i) + b + j] = s;
     }
     __syncthreads();
@@ -399,68 +425,85 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
   return 0;
 }
 
-// x = (L L^T)^{-1} rhs with the factor in M and 1 / L_kk in idg (N <=
-// kSmVec); rhs and x at LDS offsets (may alias).  Wave 0 runs both
-// triangular solves, lane = row, the new unknown broadcast from a register
-// lane.
+// x = (L L^T)^{-1} rhs with the factor in M (rows packed) and 1 / L_kk in
+// idg (N <= kSmVec); rhs and x at LDS offsets (may alias; rhs is consumed).
+// Blocked by 8 rows: every thread solves the 8 x 8 diagonal block itself
+// from LDS (same bits everywhere), then the rows below (forward) or above
+// (backward) take the block's contribution in parallel; one barrier per
+// block.  The forward result goes to a buffer of its own, so no thread
+// overwrites a block value another thread has still to read.
 __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallCtx c) {
-  if (c.wid == 0) {
-    const double* M = sm_mat();
-    const double* idg = sl().idg;
-    const int l0 = c.lane, l1 = c.lane + kWave;
-    const int c0 = l0 < N ? l0 : N - 1, c1 = l1 < N ? l1 : N - 1;  // rows read (in the factor)
-    double z0 = l0 < N ? sm_dyn[rhs_off + l0] : 0.0, z1 = l1 < N ? sm_dyn[rhs_off + l1] : 0.0;
-    // forward: L z = rhs, column by column; the LDS operands of 8 columns
-    // are read before their dependent steps
-    for (int k0 = 0; k0 < N; k0 += 8) {
-      double ig[8], m0[8], m1[8];
+  const double* M = sm_mat();
+  const double* idg = sl().idg;
+  double* z = sm_dyn + rhs_off;   // forward: right-hand side, updated below each block
+  double* yv = sl().part[0];      // forward result, updated above each block going back
+  // forward: L y = rhs
+  for (int j0 = 0; j0 < N; j0 += 8) {
+    const int w = N - j0 < 8 ? N - j0 : 8;
+    double lb[8][8], zb[8], ib[8], yb[8];
+    // unconditional loads, indices clamped into the block
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + u < N ? k0 + u : N - 1;
-        ig[u] = idg[k];
-        m0[u] = M[tri(c0) + k];  // used for k < c0 only; in bounds for any k < N
-        m1[u] = M[tri(c1) + k];
-      }
+    for (int i = 0; i < 8; ++i) {
+      const int ic = i < w ? i : w - 1;
+      zb[i] = z[j0 + ic];
+      ib[i] = idg[j0 + ic];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + u;
-        if (k < N) {
-          const double rk = k < kWave ? readlane_d(z0, k) : readlane_d(z1, k - kWave);
-          const double zk = rk * ig[u];
-          if (l0 == k) z0 = zk;
-          if (l1 == k) z1 = zk;
-          if (l0 > k && l0 < N) z0 = fma(-m0[u], zk, z0);
-          if (l1 > k && l1 < N) z1 = fma(-m1[u], zk, z1);
-        }
-      }
+      for (int k = 0; k < i; ++k) lb[i][k] = M[tri(j0 + ic) + j0 + (k < ic ? k : 0)];
     }
-    // backward: L^T x = z, row k of L^T is column k of L
-    for (int k0 = N - 1; k0 >= 0; k0 -= 8) {
-      double ig[8], m0[8], m1[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 - u >= 0 ? k0 - u : 0;
-        ig[u] = idg[k];
-        m0[u] = M[tri(k) + c0];  // used for c0 < k only; in bounds for any c0 < N
-        m1[u] = M[tri(k) + c1];
-      }
+    for (int i = 0; i < 8; ++i) {
+      double y = zb[i];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 - u;
-        if (k >= 0) {
-          const double rk = k < kWave ? readlane_d(z0, k) : readlane_d(z1, k - kWave);
-          const double xk = rk * ig[u];
-          if (l0 == k) z0 = xk;
-          if (l1 == k) z1 = xk;
-          if (l0 < k) z0 = fma(-m0[u], xk, z0);
-          if (l1 < k) z1 = fma(-m1[u], xk, z1);
-        }
-      }
+      for (int k = 0; k < i; ++k) y = fma(-lb[i][k], yb[k], y);
+      yb[i] = y * ib[i];
     }
-    if (l0 < N) sm_dyn[x_off + l0] = z0;
-    if (l1 < N) sm_dyn[x_off + l1] = z1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (c.tid == i && i < w) yv[j0 + i] = yb[i];
+    for (int R = j0 + 8 + c.tid; R < N; R += c.nt) {
+      double lr[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lr[k] = M[tri(R) + j0 + k];  // j0 + 8 <= R: in the row
+      double u = z[R];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) u = fma(-lr[k], yb[k], u);
+      z[R] = u;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  // backward: L^T x = y, row k of L^T is column k of L
+  for (int j0 = ((N - 1) / 8) * 8; j0 >= 0; j0 -= 8) {
+    const int w = N - j0 < 8 ? N - j0 : 8;
+    double lb[8][8], vb[8], ib[8], xb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int ic = i < w ? i : w - 1;
+      vb[i] = yv[j0 + ic];
+      ib[i] = idg[j0 + ic];
+#pragma unroll
+      for (int k = 0; k < i; ++k) lb[i][k] = M[tri(j0 + ic) + j0 + (k < ic ? k : 0)];
+    }
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+      double x = vb[i];
+#pragma unroll
+      for (int k = i + 1; k < 8; ++k) x = fma(k < w ? -lb[k][i] : 0.0, xb[k], x);
+      xb[i] = x * ib[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (c.tid == i && i < w) sm_dyn[x_off + j0 + i] = xb[i];
+    for (int R = c.tid; R < j0; R += c.nt) {
+      double lc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lc[k] = M[tri(j0 + (k < w ? k : w - 1)) + R];  // R < j0: in the row
+      double u = yv[R];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) u = fma(k < w ? -lc[k] : 0.0, xb[k], u);
+      yv[R] = u;
+    }
+    __syncthreads();
+  }
 }
 
 // The active set of t = x - sigma w_y (after w_y += s w_d when s != 0):
@@ -479,11 +522,13 @@ __device__ __noinline__ int64_t sm_prox(GD x, GD wy, GCD wd, int64_t n, double s
     const bool in = i < hi;
     const int64_t ic = in ? i : hi - 1;
     double w = wy[ic];
+    const double dw = wd[ic];  // unconditional: a load in a branch would wait at the join
+    const double xi = x[ic];
     if (s != 0.0) {
-      w = fma(s, wd[ic], w);
+      w = fma(s, dw, w);
       if (in) wy[i] = w;
     }
-    const double t = fma(-sigma, w, x[ic]);
+    const double t = fma(-sigma, w, xi);
     const bool act = in & ((t > thr) | (t < -thr));
     cnt += __builtin_popcountll(__builtin_amdgcn_ballot_w64(act));
   }
