@@ -869,6 +869,33 @@ def main():
     avg64, bpl64, calls64 = atd_stats(inf64, 8)
     avgbf, bplbf, _ = atd_stats(infbf, 2)
     achieved = bpl32 / avg32 / 1e9
+
+    # measured stream bandwidths on this GPU over the FP32 design's bytes: a
+    # read-only stream (torch's sum over the array) and a device-to-device
+    # copy (bytes read + bytes written over the copy time)
+    src = A32.reshape(-1)
+    dst = torch.empty_like(src)
+    nbytes = src.numel() * src.element_size()
+    nrep = 20
+
+    def stream_rate(fn, moved):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(nrep):
+            fn()
+        torch.cuda.synchronize()
+        return moved * nrep / (time.perf_counter() - t) / 1e9
+
+    stream_gbs = stream_rate(lambda: src.sum(), nbytes)
+    copy_gbs = stream_rate(lambda: dst.copy_(src), 2.0 * nbytes)
+    del dst
+
+    def solve_gbs(infos, el, s_a):
+        """Effective solve bandwidth: full A^T v passes per solve x m n s_A / solve time."""
+        passes = sum(i["gemv_calls"] for i in infos) / len(infos)
+        return passes * float(p64.m) * p64.n * s_a / (el / args.steps) / 1e9, passes
     traffic = _traffic_from_profile(os.path.join(ROOT, "paper_2006_03970_amd", "csrc", "k_gemv.hip"), "f32")
 
     out = {
@@ -903,6 +930,13 @@ def main():
         "atd_launches_per_solve": {"mixed_f32": calls32, "fp64": calls64},
         "atd_gbs": {"mixed_f32": achieved, "fp64": bpl64 / avg64 / 1e9,
                     "mixed_bf16": bplbf / avgbf / 1e9},
+        "stream_read_gbs": stream_gbs,
+        "stream_copy_gbs": copy_gbs,
+        "atd_frac_of_stream": {"mixed_f32": achieved / stream_gbs, "fp64": bpl64 / avg64 / 1e9 / stream_gbs,
+                               "mixed_bf16": bplbf / avgbf / 1e9 / stream_gbs},
+        "effective_solve_gbs": {k: {"gbs": g, "passes_per_solve": ps} for k, (g, ps) in
+                                (("mixed_f32", solve_gbs(inf32, el32, 4)), ("fp64", solve_gbs(inf64, el64, 8)),
+                                 ("mixed_bf16", solve_gbs(infbf, elbf, 2)))},
         "roofline": {
             "bound": "hbm",
             "kernel": "Newton pass w_d = A^T d: k_gemv_t<float, float, 2> (FP32 design, FP32 accumulation)",

@@ -12,9 +12,8 @@
 // One workgroup of 256 threads per problem, single or batched (the same
 // summation orders, so a batched problem gives its single solve's bits);
 // at most 256 registers a lane and 69 KB of LDS at m = 120 (the Newton
-// matrix packed as a lower triangle), so two problems share a CU and hide
-// each other's memory waits.  A (FP64,
-// column-major, lda >= m) and the n-vectors (x, w_y = A^T y, w_d = A^T d,
+// matrix packed as a lower triangle), so two problems can share a CU.
+// A (FP64, column-major, lda >= m) and the n-vectors (x, w_y = A^T y, w_d = A^T d,
 // the active set J and u_J) stay in global memory (cache-resident at these
 // sizes); the m-vectors (y, g, d, rho, b), the Newton matrix and its
 // Cholesky factor live in LDS.  Per Newton step, in the order of the
