@@ -47,6 +47,27 @@ typedef const double __attribute__((address_space(1)))* GCD;
 typedef double __attribute__((address_space(1)))* GD;
 typedef const int32_t __attribute__((address_space(1)))* GCI;
 typedef int32_t __attribute__((address_space(1)))* GI;
+typedef const double __attribute__((address_space(3)))* LCD;
+typedef double __attribute__((address_space(3)))* LD;
+typedef const int32_t __attribute__((address_space(3)))* LCI;
+typedef int32_t __attribute__((address_space(3)))* LI;
+
+// Where the n-vectors of a solve (x, w_y, w_d, u_J, J) live: in global
+// memory, or in LDS after the Newton matrix when they fit (36 bytes a
+// feature), which takes the global round trips out of every phase but the
+// passes over A.
+struct InGlobal {
+  typedef GD D;
+  typedef GCD CD;
+  typedef GI I;
+  typedef GCI CI;
+};
+struct InLds {
+  typedef LD D;
+  typedef LCD CD;
+  typedef LI I;
+  typedef LCI CI;
+};
 
 constexpr int kSmNT = 256;                        // threads a problem
 constexpr int kSmWaves = kSmNT / kWave;
@@ -116,9 +137,9 @@ __device__ __forceinline__ double row16_sum(double v) {
 // contiguous bytes of 4 columns; a 16-lane sum finishes each column.  Wave w
 // takes groups w U .. w U + U - 1, then every (waves * U)-th.  With colsq, the sum
 // of |a_j|^2 over the n columns (every thread receives it).
-template <int R, bool GATHER>
-__device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, GCI J, int voff, GD out, int ldsout,
-                                      double* colsq, SmallCtx c) {
+template <int R, bool GATHER, class V>
+__device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, typename V::CI J, int voff,
+                                      typename V::D out, int ldsout, double* colsq, SmallCtx c) {
   const int m = c.m;
   const int q = c.lane >> 4, s = c.lane & 15;
   double vv[R];
@@ -186,26 +207,28 @@ __device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, GCI J, int 
   __syncthreads();  // out complete for every thread
 }
 
-template <bool GATHER>
-__device__ __forceinline__ void sm_atv(GCD A, int64_t lda, int64_t n, GCI J, int voff, GD out, int ldsout,
-                                       double* colsq, const SmallCtx& c) {
+template <bool GATHER, class V>
+__device__ __forceinline__ void sm_atv(GCD A, int64_t lda, int64_t n, typename V::CI J, int voff,
+                                       typename V::D out, int ldsout, double* colsq, const SmallCtx& c) {
   switch ((c.m + 15) / 16) {
-    case 1: sm_atv_r<1, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 2: sm_atv_r<2, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 3: sm_atv_r<3, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 4: sm_atv_r<4, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 5: sm_atv_r<5, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 6: sm_atv_r<6, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 7: sm_atv_r<7, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    default: sm_atv_r<kSmRows, GATHER>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 1: sm_atv_r<1, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 2: sm_atv_r<2, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 3: sm_atv_r<3, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 4: sm_atv_r<4, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 5: sm_atv_r<5, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 6: sm_atv_r<6, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 7: sm_atv_r<7, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    default: sm_atv_r<kSmRows, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
   }
 }
 
-// out[i] = sum_{k<r} A[i, J[k]] coef[k] for i < m (coef global), into LDS at
+// out[i] = sum_{k<r} A[i, J[k]] coef[k] for i < m (coef an n-vector), into LDS at
 // offset ooff.  Lane l takes rows l and l + 64; wave w takes k = w, w +
 // waves, ... (eight at a time); the per-wave partial m-vectors are added in
 // wave order.
-__device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int64_t r, int ooff, SmallCtx c) {
+template <class V>
+__device__ __noinline__ void sm_gather(GCD A, int64_t lda, typename V::CI J, typename V::CD coef, int64_t r,
+                                       int ooff, SmallCtx c) {
   const int m = c.m;
   const int l0 = c.lane, l1 = c.lane + kWave;
   const int r0 = l0 < m ? l0 : 0, r1 = l1 < m ? l1 : 0;
@@ -244,7 +267,9 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, GCI J, GCD coef, int6
 //   form 0: M = I_m + kappa A_J A_J^T      (N = m, contraction over the r columns)
 //   form 1: M = I_r / kappa + A_J^T A_J    (N = r, contraction over the m rows)
 // 16 x 16 blocks of the lower triangle round-robin over the waves.
-__device__ __noinline__ void sm_gram(GCD A, int64_t lda, GCI J, int64_t r, int form, double kappa, SmallCtx c) {
+template <class V>
+__device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64_t r, int form, double kappa,
+                                     SmallCtx c) {
   double* M = sm_mat();
   const int m = c.m;
   const int N = form ? (int)r : m;
@@ -510,8 +535,10 @@ __device__ __noinline__ void sm_chol_solve(int N, int rhs_off, int x_off, SmallC
 // of the features (S a multiple of 64): it counts its actives with wave
 // ballots, the counts are scanned once in LDS, and a second walk writes J
 // and u_J at the wave's offset.  Returns r.
-__device__ __noinline__ int64_t sm_prox(GD x, GD wy, GCD wd, int64_t n, double s, double sigma, double thr,
-                                        double den, GI J, GD uJ, SmallCtx c) {
+template <class V>
+__device__ __noinline__ int64_t sm_prox(typename V::D x, typename V::D wy, typename V::CD wd, int64_t n, double s,
+                                        double sigma, double thr, double den, typename V::I J, typename V::D uJ,
+                                        SmallCtx c) {
   const int64_t S = ((n + c.nt - 1) / c.nt) * kWave;
   const int64_t lo = (int64_t)c.wid * S;
   const int64_t hi = lo + S < n ? lo + S : n;
@@ -562,7 +589,9 @@ __device__ __noinline__ int64_t sm_prox(GD x, GD wy, GCD wd, int64_t n, double s
 // stays inactive contributes nothing; one that stays on its active side,
 // s^2 kappa wd_i^2 / 2), the trial steps in chunks of 8 in order: the index
 // of the first step with Delta(s) <= mu s g^T d, or -1.
-__device__ __noinline__ int sm_linesearch(GCD x, GCD wy, GCD wd, int64_t n, double sigma, double thr, double den,
+template <class V>
+__device__ __noinline__ int sm_linesearch(typename V::CD x, typename V::CD wy, typename V::CD wd, int64_t n,
+                                          double sigma, double thr, double den,
                                           double kappa, double gd, double dd, int K, double mu, SmallCtx c) {
   const double* ts = sl().ts;
   const double rden = 1.0 / den, h = den / (2.0 * sigma);
@@ -609,25 +638,15 @@ __device__ __noinline__ int sm_linesearch(GCD x, GCD wy, GCD wd, int64_t n, doub
   return -1;
 }
 
-}  // namespace
-
-__global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __restrict__ probs, SmallArgs one,
-                                                       SmallOpts o, Pub pub) {
-  SmallCtx c;
-  c.tid = threadIdx.x;
-  c.lane = c.tid & (kWave - 1);
-  c.wid = __builtin_amdgcn_readfirstlane(c.tid / kWave);
-  c.nt = blockDim.x;
-  c.nw = c.nt / kWave;
-  const SmallArgs pr = probs ? probs[blockIdx.x] : one;
+// The solve of one problem with its n-vectors in V's memory (x, wy, wd, uJ,
+// J); in LDS, x is written back to the problem's x at the end.
+template <class V>
+__device__ __forceinline__ void solve_body(const SmallArgs& pr, const SmallOpts& o, const Pub& pub, SmallCtx c,
+                                           typename V::D x, typename V::D wy, typename V::D wd,
+                                           typename V::D uJ, typename V::I J) {
   GCD A = (GCD)pr.A;
   GCD bvec = (GCD)pr.b;
   GCD x0 = (GCD)pr.x0;
-  GD x = (GD)pr.x;
-  GD wy = (GD)pr.wy;
-  GD wd = (GD)pr.wd;
-  GD uJ = (GD)pr.uJ;
-  GI J = (GI)pr.J;
   const int64_t lda = pr.lda, n = pr.n;
   const int m = pr.m;
   c.m = m;
@@ -650,8 +669,8 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
     }
     x0_nonfinite = __syncthreads_or(bad_x0) != 0;
     // u_J = prox(t) with thr 0, den 1: t = x (w_y = 0), so u_J = x_J
-    r = sm_prox(x, wy, wd, n, 0.0, 1.0, 0.0, 1.0, J, uJ, c);
-    sm_gather(A, lda, J, uJ, r, kOffY, c);
+    r = sm_prox<V>(x, wy, wd, n, 0.0, 1.0, 0.0, 1.0, J, uJ, c);
+    sm_gather<V>(A, lda, J, uJ, r, kOffY, c);
     if (c.tid < m) L.y[c.tid] -= L.b[c.tid];
   } else {
     for (int64_t i = c.tid; i < n; i += c.nt) x[i] = 0.0;
@@ -659,7 +678,7 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
   }
   __syncthreads();
   double colsq = 0.0;
-  sm_atv<false>(A, lda, n, nullptr, kOffY, wy, -1, &colsq, c);
+  sm_atv<false, V>(A, lda, n, nullptr, kOffY, wy, -1, &colsq, c);
   double nb2[1] = {c.tid < m ? L.b[c.tid] * L.b[c.tid] : 0.0};
   bsum<1>(nb2, c);
   const double normb = sqrt(nb2[0]);
@@ -688,9 +707,9 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
     int inner = 0;
     for (;;) {
       // ---- prox, active set, gradient (eq. grad_phy), kkt1 (eq. kkt_res)
-      r = sm_prox(x, wy, wd, n, pend, sigma, thr, den, J, uJ, c);
+      r = sm_prox<V>(x, wy, wd, n, pend, sigma, thr, den, J, uJ, c);
       pend = 0.0;
-      sm_gather(A, lda, J, uJ, r, kOffRho, c);  // A_J u_J
+      sm_gather<V>(A, lda, J, uJ, r, kOffRho, c);  // A_J u_J
       double s3[3] = {0.0, 0.0, 0.0};
       if (c.tid < m) {
         const double au = L.rho[c.tid];
@@ -719,8 +738,8 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
       } else if (r < m && !o.no_smw) {
         // q: W q = A_J^T g, W = I/kappa + A_J^T A_J; d = -g + A_J q
         const int N = (int)r;
-        sm_atv<true>(A, lda, r, J, kOffG, nullptr, kOffQ, nullptr, c);  // A_J^T g into q
-        sm_gram(A, lda, J, r, 1, kappa, c);
+        sm_atv<true, V>(A, lda, r, J, kOffG, nullptr, kOffQ, nullptr, c);  // A_J^T g into q
+        sm_gram<V>(A, lda, J, r, 1, kappa, c);
         const int bad = sm_cholesky(N, c);
         if (bad) {
           chol_bad = true;
@@ -731,11 +750,11 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
         // d = -g + A_J q (q staged in w_d, which the pass below rewrites)
         for (int k = c.tid; k < N; k += c.nt) wd[k] = L.q[k];
         __syncthreads();
-        sm_gather(A, lda, J, wd, r, kOffD, c);
+        sm_gather<V>(A, lda, J, wd, r, kOffD, c);
         if (c.tid < m) L.d[c.tid] -= L.g[c.tid];
         __syncthreads();
       } else {
-        sm_gram(A, lda, J, r, 0, kappa, c);
+        sm_gram<V>(A, lda, J, r, 0, kappa, c);
         const int bad = sm_cholesky(m, c);
         if (bad) {
           chol_bad = true;
@@ -747,13 +766,13 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
         sm_chol_solve(m, kOffQ, kOffD, c);
       }
       // ---- w_d = A^T d, the pass over A
-      sm_atv<false>(A, lda, n, nullptr, kOffD, wd, -1, nullptr, c);
+      sm_atv<false, V>(A, lda, n, nullptr, kOffD, wd, -1, nullptr, c);
       ++passes;
       // ---- line search (eq. line_search)
       double gd2[2] = {c.tid < m ? L.g[c.tid] * L.d[c.tid] : 0.0, c.tid < m ? L.d[c.tid] * L.d[c.tid] : 0.0};
       bsum<2>(gd2, c);
       const double gd = gd2[0], dd = gd2[1];
-      const int ks = sm_linesearch(x, wy, wd, n, sigma, thr, den, kappa, gd, dd, o.K, o.mu, c);
+      const int ks = sm_linesearch<V>(x, wy, wd, n, sigma, thr, den, kappa, gd, dd, o.K, o.mu, c);
       if (ks < 0) {
         stalled = true;
         break;
@@ -786,7 +805,7 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
     if (need_eta || stalled || outer + 1 >= o.max_outer) {
       // ---- certificates at x (eq. kkt_res, Prop. 1): rho = A x - b is the
       // last gradient's (x = u of the last prox), q = A^T rho
-      sm_atv<false>(A, lda, n, nullptr, kOffRho, wd, -1, nullptr, c);
+      sm_atv<false, V>(A, lda, n, nullptr, kOffRho, wd, -1, nullptr, c);
       ++passes;
       double s4[4] = {0.0, 0.0, 0.0, 0.0};
       double mx = 0.0;  // |A^T rho|_inf, for the Lasso's scaled dual point
@@ -830,6 +849,11 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
     if (sigma > o.sigma_max) sigma = o.sigma_max;
   }
   if (!converged) status = nonfinite ? -2 : (bad_sigma ? -1 : (chol_bad ? -5 : (stalled ? 2 : 1)));
+  if constexpr (std::is_same<V, InLds>::value) {
+    __syncthreads();
+    GD xo = (GD)pr.x;
+    for (int64_t i = c.tid; i < n; i += c.nt) xo[i] = x[i];
+  }
   __syncthreads();  // every thread's stores of x are issued
   if (c.tid == 0) {
     SmallOut* out = pr.out;
@@ -854,22 +878,55 @@ __global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __res
   }
 }
 
-size_t small_lds_bytes(int mmax) {
-  return sizeof(SmallLds) + sizeof(double) * (size_t)mmax * (size_t)(mmax + 1) / 2;
+}  // namespace
+
+__global__ __launch_bounds__(kSmNT, 2) void k_solve_small(const SmallArgs* __restrict__ probs, SmallArgs one,
+                                                       SmallOpts o, Pub pub) {
+  SmallCtx c;
+  c.tid = threadIdx.x;
+  c.lane = c.tid & (kWave - 1);
+  c.wid = __builtin_amdgcn_readfirstlane(c.tid / kWave);
+  c.nt = blockDim.x;
+  c.nw = c.nt / kWave;
+  const SmallArgs pr = probs ? probs[blockIdx.x] : one;
+  if (pr.n <= o.nl) {
+    // the n-vectors in LDS after the Newton matrix: x, w_y, w_d, u_J (nl
+    // doubles each), then J (nl ints)
+    double* v = sm_dyn + o.vec_off;
+    const int64_t nl = o.nl;
+    solve_body<InLds>(pr, o, pub, c, (LD)v, (LD)(v + nl), (LD)(v + 2 * nl), (LD)(v + 3 * nl), (LI)(v + 4 * nl));
+  } else {
+    solve_body<InGlobal>(pr, o, pub, c, (GD)pr.x, (GD)pr.wy, (GD)pr.wd, (GD)pr.uJ, (GI)pr.J);
+  }
 }
+
+// LDS of a launch: the fixed parts and the packed Newton matrix of the
+// largest m (rounded to 16 bytes), then 36 bytes a feature for the
+// problems whose n-vectors fit (at most kSmallLdsMax in all).
+constexpr size_t kSmallLdsMax = 160 * 1024 - 1024;  // leaves room for the static LDS
+size_t small_matrix_bytes(int mmax) {
+  const size_t b = sizeof(SmallLds) + sizeof(double) * (size_t)mmax * (size_t)(mmax + 1) / 2;
+  return (b + 15) / 16 * 16;
+}
+size_t small_lds_bytes(int mmax, int64_t nl) { return small_matrix_bytes(mmax) + (size_t)nl * 36; }
 
 hipError_t small_init() {
   return hipFuncSetAttribute((const void*)k_solve_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)small_lds_bytes(kSmallMaxM));
+                             (int)kSmallLdsMax);
 }
 
-hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, int mmax, const SmallOpts& o,
-                       Pub pub, hipStream_t st) {
+hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, int mmax, int64_t nmax,
+                       const SmallOpts& o, Pub pub, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  if (mmax < 1 || mmax > kSmallMaxM || (!probs && (!one || count != 1))) return hipErrorInvalidValue;
+  if (mmax < 1 || mmax > kSmallMaxM || nmax < 1 || (!probs && (!one || count != 1))) return hipErrorInvalidValue;
   const SmallArgs a = one ? *one : SmallArgs{};
-  hipLaunchKernelGGL(k_solve_small, dim3((unsigned)count), dim3(kSmNT), small_lds_bytes(mmax), st,
-                     one ? nullptr : probs, a, o, pub);
+  SmallOpts oo = o;
+  const size_t mb = small_matrix_bytes(mmax);
+  const int64_t cap = (int64_t)((kSmallLdsMax - mb) / 36);
+  oo.vec_off = (int64_t)(mb / sizeof(double));
+  oo.nl = nmax <= cap ? nmax : cap;  // problems with n <= nl keep their n-vectors in LDS
+  hipLaunchKernelGGL(k_solve_small, dim3((unsigned)count), dim3(kSmNT), small_lds_bytes(mmax, oo.nl), st,
+                     one ? nullptr : probs, a, oo, pub);
   return hipGetLastError();
 }
 

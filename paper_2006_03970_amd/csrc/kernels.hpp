@@ -167,6 +167,7 @@ struct SmallOpts {
   double sigma_factor, sigma_max, mu;
   int max_outer, max_inner, K, no_smw;
   double s[kMaxTrials];  // trial steps delta^k, k < K
+  int64_t nl, vec_off;   // set by solve_small: n-vectors in LDS for n <= nl, at this offset (doubles)
 };
 struct SmallOut {
   int status;  // 0 converged, 1 not converged, 2 line-search stall, -1 sigma0 not a positive
@@ -193,13 +194,14 @@ struct SmallArgs {
 };
 // Raise the dynamic LDS limit of the one-workgroup solve (once per device).
 hipError_t small_init();
-size_t small_lds_bytes(int mmax);
+size_t small_lds_bytes(int mmax, int64_t nl);
 // count problems whose descriptors probs[] the device reads (device or mapped
 // pinned memory), or one problem passed by value in *one (probs ignored);
-// mmax = max m over them.  With pub.flag set (single problem), the result
-// record is published with that sequence number once written.
-hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, int mmax, const SmallOpts& o,
-                       Pub pub, hipStream_t st);
+// mmax, nmax = max m and n over them (problems whose n-vectors fit beside
+// the Newton matrix keep them in LDS).  With pub.flag set (single problem),
+// the result record is published with that sequence number once written.
+hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, int mmax, int64_t nmax,
+                       const SmallOpts& o, Pub pub, hipStream_t st);
 
 // ---- Cholesky and triangular solves (k_chol.hip) --------------------------
 // Raise the dynamic LDS limits of the Cholesky kernels (once per device).

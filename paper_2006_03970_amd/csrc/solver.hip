@@ -598,7 +598,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
     const Pub pub = next_pub(c);
     const SmallArgs a = small_args(A, lda, b, m, n, l1, l2, x0, tol, x, user_opts, w.wy, w.wd, w.uJ, w.J,
                                    reinterpret_cast<SmallOut*>(pub.dst));
-    HIPCHK(solve_small(nullptr, &a, 1, m, small_opts(o), pub, st));
+    HIPCHK(solve_small(nullptr, &a, 1, m, n, small_opts(o), pub, st));
     if (int rc = wait_pub(c, st, pub.seq, &syncs)) return rc;
     SmallOut so;
     std::memcpy(&so, hs, sizeof(so));
@@ -1171,6 +1171,7 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
   if (nsmall > 0) {
     size_t ws = 0;
     int mmax = 1;
+    int64_t nmax = 1;
     for (int i : small) {
       const ssnal_en_problem& p = problems[i];
       if (int rc = check_scalars((double*)p.x_out, p.lambda1, p.lambda2, p.tol))
@@ -1179,6 +1180,7 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
         return fail(SSNAL_EINVAL, "problem %d: sigma0 = %g is not a positive number", i, p.sigma0);
       ws += ((size_t)p.n * 28 + 255) / 256 * 256;
       mmax = std::max(mmax, (int)p.m);
+      nmax = std::max(nmax, (int64_t)p.n);
     }
     if (int rc = ensure(ctx->sm_ws, ws)) return rc;
     if (ctx->small_cap < nsmall) {
@@ -1210,7 +1212,7 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
       if (!ctx->ev_order) HIPCHK(hipEventCreateWithFlags(&ctx->ev_order, hipEventDisableTiming));
       HIPCHK(hipEventRecord(ctx->ev_order, stream));
     }
-    HIPCHK(solve_small(d_args, nullptr, nsmall, mmax, small_opts(shared), Pub{}, stream));
+    HIPCHK(solve_small(d_args, nullptr, nsmall, mmax, nmax, small_opts(shared), Pub{}, stream));
   }
   // the results of the one-workgroup solves, once the launch has finished
   auto small_results = [&]() -> int {
