@@ -51,6 +51,8 @@ typedef const double __attribute__((address_space(3)))* LCD;
 typedef double __attribute__((address_space(3)))* LD;
 typedef const int32_t __attribute__((address_space(3)))* LCI;
 typedef int32_t __attribute__((address_space(3)))* LI;
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef const d2v __attribute__((address_space(1)))* GCD2;
 
 // Where the n-vectors of a solve (x, w_y, w_d, u_J, J) live: in global
 // memory, or in LDS after the Newton matrix when they fit (36 bytes a
@@ -130,13 +132,105 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Sum over the 8 lanes of each half-row; every lane of the half gets the same
+// bits.
+__device__ __forceinline__ double row8_sum(double v) {
+  v += dpp_d<kQuadXor1>(v);
+  v += dpp_d<kQuadXor2>(v);
+  v += dpp_d<kRowHalfMirror>(v);
+  return v;
+}
+
 // out[j] = sum_{i<m} A[i, col(j)] v[i] for j < n, col(j) = J[j] (GATHER) or
 // j; v at LDS offset voff; out to global (ldsout < 0) or to LDS offset
-// ldsout.  Lane 16 q + s of a wave takes column 4 g + q of a group g and
-// rows s, s + 16, ..., s + 16 (R - 1), so each load instruction reads 128
-// contiguous bytes of 4 columns; a 16-lane sum finishes each column.  Wave w
-// takes groups w U .. w U + U - 1, then every (waves * U)-th.  With colsq, the sum
-// of |a_j|^2 over the n columns (every thread receives it).
+// ldsout.  With colsq, the sum of |a_j|^2 over the n columns (every thread
+// receives it).
+//
+// One CU streams A at the rate its loads in flight allow, and that counts
+// instructions rather than bytes (measured at m = 100: 22 bytes a cycle
+// with 8-byte loads, 43 with 16-byte loads), so when every column starts
+// 16-byte aligned (A aligned, lda even) lane 8 q + s of a wave takes
+// column 8 g + q of a group g and the row pairs (2 s, 2 s + 1) + 16 k,
+// k < R, with one 16-byte load each; an 8-lane sum finishes each column.
+// A pair that straddles m reads row m inside the padded leading dimension
+// (lda > m when m is odd and lda even) and masks it.  Other layouts take
+// 8-byte loads: lane 16 q + s takes column 4 g + q and rows s + 16 k, a
+// 16-lane sum.  Wave w takes groups w U .. w U + U - 1, then every
+// (waves * U)-th, with two rounds of loads in flight.
+template <int R, bool GATHER, class V>
+__device__ __noinline__ void sm_atv_r2(GCD A, int64_t lda, int64_t n, typename V::CI J, int voff,
+                                       typename V::D out, int ldsout, double* colsq, SmallCtx c) {
+  const int m = c.m;
+  const int q = c.lane >> 3, s = c.lane & 7;
+  double v0[R], v1[R];
+  int rr[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int row = 2 * s + 16 * k;
+    v0[k] = row < m ? sm_dyn[voff + row] : 0.0;
+    v1[k] = row + 1 < m ? sm_dyn[voff + row + 1] : 0.0;
+    rr[k] = row < m ? row : 0;  // a pair past m reads rows 0 and 1
+  }
+  // rows 2 s + 16 k + 1 < m for every k < R - 1 (16 (R - 1) < m): only the
+  // last pair can reach row m, which may hold anything
+  const bool hi_ok = 2 * s + 16 * (R - 1) + 1 < m;
+  double sq = 0.0;
+  constexpr int U = 16 / R > 8 ? 8 : (16 / R < 1 ? 1 : 16 / R);  // about 16 loads a round
+  const int64_t ngroups = (n + 7) / 8;
+  const int64_t stride = (int64_t)c.nw * U;
+  auto load = [&](d2v (&a)[U][R], int64_t g0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = 8 * (g0 + u) + q;
+      const int64_t jc = j < n ? j : n - 1;
+      const int64_t col = GATHER ? (int64_t)J[jc] : jc;
+      GCD p = A + col * lda;
+#pragma unroll
+      for (int k = 0; k < R; ++k) a[u][k] = *reinterpret_cast<GCD2>(p + rr[k]);
+    }
+  };
+  auto finish = [&](d2v (&a)[U][R], int64_t g0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = 8 * (g0 + u) + q;
+      a[u][R - 1][1] = hi_ok ? a[u][R - 1][1] : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc = fma(a[u][k][1], v1[k], fma(a[u][k][0], v0[k], acc));
+      if (colsq) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const bool ok = j < n && 2 * s + 16 * k < m;
+          sq += ok ? a[u][k][0] * a[u][k][0] + a[u][k][1] * a[u][k][1] : 0.0;
+        }
+      }
+      acc = row8_sum(acc);
+      if (s == 0 && j < n) {
+        if (ldsout >= 0)
+          sm_dyn[ldsout + j] = acc;
+        else
+          out[j] = acc;
+      }
+    }
+  };
+  d2v a0[U][R], a1[U][R];
+  int64_t g0 = (int64_t)c.wid * U;
+  if (g0 < ngroups) load(a0, g0);
+  for (; g0 < ngroups; g0 += 2 * stride) {
+    load(a1, g0 + stride);
+    finish(a0, g0);
+    if (g0 + stride >= ngroups) break;
+    load(a0, g0 + 2 * stride);
+    finish(a1, g0 + stride);
+  }
+  if (colsq) {
+    double t[1] = {sq};
+    bsum<1>(t, c);
+    *colsq = t[0];
+  }
+  __syncthreads();  // out complete for every thread
+}
+
 template <int R, bool GATHER, class V>
 __device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, typename V::CI J, int voff,
                                       typename V::D out, int ldsout, double* colsq, SmallCtx c) {
@@ -210,50 +304,93 @@ __device__ __noinline__ void sm_atv_r(GCD A, int64_t lda, int64_t n, typename V:
 template <bool GATHER, class V>
 __device__ __forceinline__ void sm_atv(GCD A, int64_t lda, int64_t n, typename V::CI J, int voff,
                                        typename V::D out, int ldsout, double* colsq, const SmallCtx& c) {
+  if ((reinterpret_cast<uintptr_t>(A) & 15) != 0 || (lda & 1) != 0) {
+    switch ((c.m + 15) / 16) {
+      case 1: sm_atv_r<1, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 2: sm_atv_r<2, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 3: sm_atv_r<3, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 4: sm_atv_r<4, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 5: sm_atv_r<5, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 6: sm_atv_r<6, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      case 7: sm_atv_r<7, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+      default: sm_atv_r<kSmRows, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    }
+    return;
+  }
   switch ((c.m + 15) / 16) {
-    case 1: sm_atv_r<1, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 2: sm_atv_r<2, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 3: sm_atv_r<3, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 4: sm_atv_r<4, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 5: sm_atv_r<5, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 6: sm_atv_r<6, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    case 7: sm_atv_r<7, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
-    default: sm_atv_r<kSmRows, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 1: sm_atv_r2<1, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 2: sm_atv_r2<2, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 3: sm_atv_r2<3, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 4: sm_atv_r2<4, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 5: sm_atv_r2<5, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 6: sm_atv_r2<6, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    case 7: sm_atv_r2<7, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
+    default: sm_atv_r2<kSmRows, GATHER, V>(A, lda, n, J, voff, out, ldsout, colsq, c); break;
   }
 }
 
 // out[i] = sum_{k<r} A[i, J[k]] coef[k] for i < m (coef an n-vector), into LDS at
-// offset ooff.  Lane l takes rows l and l + 64; wave w takes k = w, w +
-// waves, ... (eight at a time); the per-wave partial m-vectors are added in
-// wave order.
+// offset ooff.  Lane l takes rows 2 l and 2 l + 1 (16-byte loads, when
+// every column starts 16-byte aligned) or rows l and l + 64; wave w takes
+// k = w, w + waves, ... (eight at a time); the per-wave partial m-vectors
+// are added in wave order.
 template <class V>
 __device__ __noinline__ void sm_gather(GCD A, int64_t lda, typename V::CI J, typename V::CD coef, int64_t r,
                                        int ooff, SmallCtx c) {
   const int m = c.m;
-  const int l0 = c.lane, l1 = c.lane + kWave;
-  const int r0 = l0 < m ? l0 : 0, r1 = l1 < m ? l1 : 0;
-  double s0 = 0.0, s1 = 0.0;
   constexpr int U = 8;
-  for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)c.nw * U) {
-    double a0[U], a1[U], cf[U];
+  if ((reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 1) == 0) {
+    // 16-byte loads: lane l takes rows 2 l and 2 l + 1 (one load a column;
+    // a pair that straddles m reads row m inside the padded leading
+    // dimension and masks it), each row summed in the same order as below
+    const int l2 = 2 * c.lane;
+    const int rp = l2 < m ? l2 : 0;
+    const bool ok0 = l2 < m, ok1 = l2 + 1 < m;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)c.nw * U) {
+      d2v a[U];
+      double cf[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = k0 + (int64_t)c.nw * u;
-      const int64_t kc = k < r ? k : r - 1;
-      GCD col = A + (int64_t)J[kc] * lda;
-      a0[u] = col[r0];
-      a1[u] = col[r1];  // unconditional (row clamped): a load in a branch would wait at the join
-      cf[u] = coef[kc];
-      cf[u] = k < r ? cf[u] : 0.0;
-    }
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + (int64_t)c.nw * u;
+        const int64_t kc = k < r ? k : r - 1;
+        a[u] = *reinterpret_cast<GCD2>(A + (int64_t)J[kc] * lda + rp);
+        cf[u] = coef[kc];
+        cf[u] = k < r ? cf[u] : 0.0;
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      s0 = fma(l0 < m ? a0[u] : 0.0, cf[u], s0);
-      s1 = fma(l1 < m ? a1[u] : 0.0, cf[u], s1);
+      for (int u = 0; u < U; ++u) {
+        s0 = fma(ok0 ? a[u][0] : 0.0, cf[u], s0);
+        s1 = fma(ok1 ? a[u][1] : 0.0, cf[u], s1);
+      }
     }
+    sl().part[c.wid][l2] = s0;
+    sl().part[c.wid][l2 + 1] = s1;
+  } else {
+    const int l0 = c.lane, l1 = c.lane + kWave;
+    const int r0 = l0 < m ? l0 : 0, r1 = l1 < m ? l1 : 0;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k0 = c.wid; k0 < r; k0 += (int64_t)c.nw * U) {
+      double a0[U], a1[U], cf[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + (int64_t)c.nw * u;
+        const int64_t kc = k < r ? k : r - 1;
+        GCD col = A + (int64_t)J[kc] * lda;
+        a0[u] = col[r0];
+        a1[u] = col[r1];  // unconditional (row clamped): a load in a branch would wait at the join
+        cf[u] = coef[kc];
+        cf[u] = k < r ? cf[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        s0 = fma(l0 < m ? a0[u] : 0.0, cf[u], s0);
+        s1 = fma(l1 < m ? a1[u] : 0.0, cf[u], s1);
+      }
+    }
+    sl().part[c.wid][l0] = s0;
+    sl().part[c.wid][l1] = s1;
   }
-  sl().part[c.wid][l0] = s0;
-  sl().part[c.wid][l1] = s1;
   __syncthreads();
   if (c.tid < m) {
     double t = sl().part[0][c.tid];

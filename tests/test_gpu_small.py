@@ -217,6 +217,41 @@ def test_warm_start_padded_lda_aliased(gpu, ctx, orc):
     assert np.max(np.abs(x_warm.cpu().numpy() - xr)) <= 1e-8
 
 
+@pytest.mark.parametrize("m,n", [(37, 1100), (99, 1300), (119, 2000), (17, 3001)])
+def test_odd_m_even_lda_nan_padding(gpu, ctx, orc, m, n):
+    """Odd m with an even padded lda (NaN padding rows): the 16-byte passes
+    read row m of each column with the last row pair and must mask it (119 x
+    2000 runs as a batch of one).  The solve meets the oracle bar and agrees
+    with the same problem at lda = m (odd: the 8-byte passes) to 1e-9."""
+    import datagen
+    p = datagen.make_problem("c1", seed=500 + m, m=m, n=n)
+    _say("odd m, even lda", m, n)
+    A_pad, b = _upload(p, lda=m + 1)
+    A_odd, _ = _upload(p)
+    x_pad, ip = _solve1(gpu, ctx, A_pad, b, p, 1e-10, m=m)
+    x_odd, io = _solve1(gpu, ctx, A_odd, b, p, 1e-10, m=m)
+    assert ip["one_workgroup"] == 1 and io["one_workgroup"] == 1
+    _check_vs_oracle(orc, p, x_pad.cpu().numpy(), ip, 1e-10)
+    assert np.max(np.abs(x_pad.cpu().numpy() - x_odd.cpu().numpy())) <= 1e-9
+
+
+def test_unaligned_design(gpu, ctx, orc):
+    """A design that starts 8 bytes past a 16-byte boundary (even lda) takes
+    the 8-byte passes and reaches the oracle's minimiser."""
+    import datagen
+    import torch
+    p = datagen.make_problem("c1", seed=510, m=64, n=1500)
+    A, b = _upload(p)
+    buf = torch.full((A.numel() + 1,), float("nan"), dtype=torch.float64, device=A.device)
+    buf[1:] = A.reshape(-1)
+    Au = buf[1:].view(p.n, p.m)
+    assert Au.data_ptr() % 16 == 8
+    _say("unaligned design")
+    x, info = _solve1(gpu, ctx, Au, b, p, 1e-10, m=p.m)
+    assert info["one_workgroup"] == 1
+    _check_vs_oracle(orc, p, x.cpu().numpy(), info, 1e-10)
+
+
 def test_errors_and_status(gpu, ctx):
     """Non-finite b or x0: SSNAL_ENONFINITE; max_outer = 1 at a tight tol:
     SSNAL_NOT_CONVERGED with the certificates of the returned point."""
