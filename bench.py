@@ -24,9 +24,10 @@ against the FP64 peak; `concurrent`, 64 copies of the same solve through
 the batch entry on 4 and 8 workers (aggregate solves/s of independent
 solves sharing the GPU, FP32 and FP64 storage; --no-concurrent); and
 further sections (each can be skipped): the
-m=100, n=2000 single solve, alone and batched B in {1, 64, 1024}, batches
-as one launch with one workgroup a problem and, beside it, on the batch
-entry's 8 workers with the multi-kernel path (--no-c1, or --c1-only); the
+m=100, n=2000 single solve, alone (in one workgroup, and on the
+multi-kernel path) and batched B in {1, 64, 1024}, batches as one launch
+with one workgroup a problem and, beside it, on the batch entry's 8
+workers with the multi-kernel path (--no-c1, or --c1-only); the
 m=1000, n=1e6 single solve in
 FP32/BF16/FP64 (--no-c3, or --c3-only); the 100-point SNP-like path with
 gcv / e-bic at every point and 10-fold cross validation (--no-path); a
@@ -257,9 +258,10 @@ def cg_bench(reps=2, r_fixed=16000):
 
 def c1_bench(single_reps=200, batches=(1, 64, 1024)):
     """The single-solve workload (m=100, n=2000 Gaussian, FP64, tol 1e-10):
-    back-to-back single solves of one problem on one stream (the multi-kernel
-    path: m n = 2e5 is above the one-workgroup limit of a single solve), then
-    batches of B independent problems (B seeds) through ssnal_en_solve_batch:
+    back-to-back single solves of one problem on one stream (in one
+    workgroup: its n-vectors fit in LDS; and on the multi-kernel path with
+    opts.no_small for comparison), then batches of B independent problems
+    (B seeds) through ssnal_en_solve_batch:
     one launch, one workgroup a problem (the default; B = 1 is the same
     problem in one workgroup), and on 8 concurrent workers with the
     multi-kernel path (opts.no_small).  Latency-bound: the design (1.6 MB)
@@ -301,6 +303,21 @@ def c1_bench(single_reps=200, batches=(1, 64, 1024)):
            "batched": {}}
     print(f"[bench] c1 single: {1.0 / el:.0f} solves/s (one workgroup: {info['one_workgroup']})",
           file=sys.stderr, flush=True)
+    multi = binding.make_opts(no_small=1)
+    for _ in range(5):
+        binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                               x_out=q["x_out"], stream=stream, opts=multi)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(single_reps):
+        _, info = binding.ssnal_en_solve(ctx, q["A"], q["b"], q["lambda1"], q["lambda2"], tol=q["tol"],
+                                         x_out=q["x_out"], stream=stream, opts=multi)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / single_reps
+    out["single_multi_kernel"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "status": info["status"],
+                                  "iterations": [info["outer_iters"], info["newton_iters"]],
+                                  "eta": info["kkt_rel"]}
+    print(f"[bench] c1 single multi-kernel: {1.0 / el:.0f} solves/s", file=sys.stderr, flush=True)
     binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream)
     binding.ssnal_en_solve_batch(ctx, probs[:64], stream=stream, opts=binding.make_opts(no_small=1))  # workers
     # the problem descriptors are marshalled before the timed call (host-side

@@ -87,11 +87,13 @@ typedef struct {
   int32_t workers;       /* ssnal_en_solve_batch: <= 0: 8 concurrent workers (own context and
                             stream each, kept by the context); 1 = every problem in turn on
                             the caller's stream */
-  int32_t no_small;      /* 0 = a problem with A in FP64, m <= 120 and m n <= 2^17 runs its
-                            whole solve (Algorithm 1: both loops, the stopping tests, the
-                            certificates) in one workgroup, one launch and one host wait,
-                            unless trace, timing or newton_cg is asked for; a batch runs its
-                            such problems (m n <= 2^21) as one launch, one workgroup each
+  int32_t no_small;      /* 0 = a problem with A in FP64, m <= 120 and either m n <= 2^17
+                            or n <= (150112 - 16 ceil(m (m + 1) / 4)) / 36 (its n-vectors
+                            fit in LDS: n <= 3047 at m = 100) runs its whole solve
+                            (Algorithm 1: both loops, the stopping tests, the certificates)
+                            in one workgroup, one launch and one host wait, unless trace,
+                            timing or newton_cg is asked for; a batch runs its such
+                            problems (m n <= 2^21) as one launch, one workgroup each
                             (default); 1 = never */
 } ssnal_en_opts;
 
@@ -309,8 +311,9 @@ int ssnal_en_model_select(ssnal_ctx* ctx, const void* A, ssnal_dtype a_dtype, in
  * each problem's `ready` event; with opts->workers = 1, one after the other
  * on `stream` with ctx's workspace.  Every solve's result is the same bits
  * under any worker count, and the bits of the same problem solved alone when
- * both take the same path (a single solve runs in one workgroup up to
- * m n <= 2^17; see info->one_workgroup); otherwise the two agree to rounding.
+ * both take the same path (the limits of a single solve in one workgroup
+ * are at opts->no_small; see info->one_workgroup); otherwise the two agree
+ * to rounding.
  * Returns after every solve has completed.  infos: HOST, nullable, count
  * entries.  Returns the most severe status; an error stops handing out
  * problems. */

@@ -1046,6 +1046,7 @@ size_t small_matrix_bytes(int mmax) {
   return (b + 15) / 16 * 16;
 }
 size_t small_lds_bytes(int mmax, int64_t nl) { return small_matrix_bytes(mmax) + (size_t)nl * 36; }
+int64_t small_lds_cap(int mmax) { return (int64_t)((kSmallLdsMax - small_matrix_bytes(mmax)) / 36); }
 
 hipError_t small_init() {
   return hipFuncSetAttribute((const void*)k_solve_small, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1058,9 +1059,8 @@ hipError_t solve_small(const SmallArgs* probs, const SmallArgs* one, int count, 
   if (mmax < 1 || mmax > kSmallMaxM || nmax < 1 || (!probs && (!one || count != 1))) return hipErrorInvalidValue;
   const SmallArgs a = one ? *one : SmallArgs{};
   SmallOpts oo = o;
-  const size_t mb = small_matrix_bytes(mmax);
-  const int64_t cap = (int64_t)((kSmallLdsMax - mb) / 36);
-  oo.vec_off = (int64_t)(mb / sizeof(double));
+  const int64_t cap = small_lds_cap(mmax);
+  oo.vec_off = (int64_t)(small_matrix_bytes(mmax) / sizeof(double));
   oo.nl = nmax <= cap ? nmax : cap;  // problems with n <= nl keep their n-vectors in LDS
   hipLaunchKernelGGL(k_solve_small, dim3((unsigned)count), dim3(kSmNT), small_lds_bytes(mmax, oo.nl), st,
                      one ? nullptr : probs, a, oo, pub);

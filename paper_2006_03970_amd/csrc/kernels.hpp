@@ -195,6 +195,9 @@ struct SmallArgs {
 // Raise the dynamic LDS limit of the one-workgroup solve (once per device).
 hipError_t small_init();
 size_t small_lds_bytes(int mmax, int64_t nl);
+// Features whose n-vectors (36 bytes each) fit in LDS beside the Newton
+// matrix of mmax rows.
+int64_t small_lds_cap(int mmax);
 // count problems whose descriptors probs[] the device reads (device or mapped
 // pinned memory), or one problem passed by value in *one (probs ignored);
 // mmax, nmax = max m and n over them (problems whose n-vectors fit beside

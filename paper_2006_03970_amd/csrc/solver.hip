@@ -440,16 +440,21 @@ void certificate_values(const double* hs, double l1, double l2, double* eta, dou
 // ---- one-workgroup solves of small problems (k_small.hip)
 // At m <= 120 and small m n the multi-kernel path is bound by its launches
 // and its host read-back per Newton step; one workgroup runs the whole solve
-// there, streaming A at one CU's rate.  A single solve takes that path up to
-// kSmallMaxMN = m n (where the per-step passes of one CU over A catch up with
-// the launch overhead they replace); a batch, whose problems fill the CUs side
-// by side, up to kSmallBatchMaxMN.
+// there, streaming A at one CU's rate.  A single solve takes that path when
+// m n <= kSmallMaxMN or when its n-vectors fit in LDS beside the Newton
+// matrix (n <= 3047 at m = 100): past both, the per-step passes of one CU
+// over A and over the n-vectors in global memory cost more than the launches
+// they replace (measured at m = 100 to 120: n = 3000 0.65 against 0.96 ms a
+// solve, n = 4000 0.83 against 0.74, n = 5000 1.40 against 0.92).  A batch,
+// whose problems fill the CUs side by side, takes it up to kSmallBatchMaxMN.
 constexpr int64_t kSmallMaxMN = (int64_t)1 << 17;
 constexpr int64_t kSmallBatchMaxMN = (int64_t)1 << 21;
 
-bool small_ok(int dt, int64_t m, int64_t n, const ssnal_en_opts& o, int64_t max_mn) {
-  return !o.no_small && dt == kF64 && m <= kSmallMaxM && m * n <= max_mn && !o.newton_cg && !o.timing &&
-         !(o.trace && o.trace_cap > 0);
+bool small_ok(int dt, int64_t m, int64_t n, const ssnal_en_opts& o, bool single) {
+  if (o.no_small || dt != kF64 || m > kSmallMaxM || o.newton_cg || o.timing || (o.trace && o.trace_cap > 0))
+    return false;
+  if (single) return m * n <= kSmallMaxMN || n <= small_lds_cap((int)m);
+  return m * n <= kSmallBatchMaxMN;
 }
 
 SmallOpts small_opts(const ssnal_en_opts& o) {
@@ -592,7 +597,7 @@ int solve_impl(ssnal_ctx* c, const void* A, int dt, int64_t lda, const double* b
   }
   int gemv_calls = 0, syncs = 0;
   double* hs = c->h_scal;
-  if (small_ok(dt, m, n, o, kSmallMaxMN)) {
+  if (small_ok(dt, m, n, o, true)) {
     // the whole solve in one workgroup; its result record lands in the
     // pinned scalar slots with the publish flag
     const Pub pub = next_pub(c);
@@ -1158,7 +1163,7 @@ int ssnal_en_solve_batch(ssnal_ctx* ctx, const ssnal_en_problem* problems, int c
   for (int i = 0; i < count; ++i) {
     const ssnal_en_problem& p = problems[i];
     if (check_args(p.A, (int)p.a_dtype, p.lda, p.b, p.m, p.n) == 0 &&
-        small_ok((int)p.a_dtype, p.m, p.n, shared, kSmallBatchMaxMN))
+        small_ok((int)p.a_dtype, p.m, p.n, shared, false))
       small.push_back(i);
     else
       rest.push_back(i);

@@ -118,7 +118,10 @@ def _problems(gpu, n_prob, seed0=20):
     import torch
     probs, keep = [], []
     for i in range(n_prob):
-        cfg = dict(m=80 + 20 * i, n=1500 + 250 * i, design=("gauss", "toeplitz", "snp")[i % 3], k=8,
+        # the third (FP64, m = 120, n = 3000) is past the single-solve limits
+        # of the one-workgroup path (m n > 2^17, n-vectors too large for LDS)
+        cfg = dict(m=80 + 20 * i, n=(1500, 1750, 3000, 2250, 2500, 2750)[i % 6],
+                   design=("gauss", "toeplitz", "snp")[i % 3], k=8,
                    snr=5.0, alpha=0.5, c_lam=0.3 + 0.1 * (i % 3), tol=1e-8)
         p = datagen.make_problem(cfg, seed=seed0 + i, store=("f64", "f32")[i % 2])
         A, b = _upload(p)
@@ -130,8 +133,8 @@ def _problems(gpu, n_prob, seed0=20):
 
 def test_batch_matches_individual_bitwise(gpu, ctx):
     """A batch gives each problem's bits alone when both take the same path
-    (FP32 storage and small FP64 problems); an FP64 problem above the
-    single-solve limit of the one-workgroup path (m n = 2.4e5 > 2^17) runs
+    (FP32 storage and small FP64 problems); an FP64 problem past the
+    single-solve limits of the one-workgroup path (m = 120, n = 3000) runs
     in one workgroup only in the batch and agrees to 1e-9."""
     _say("batch vs individual")
     probs, _ = _problems(gpu, 4)

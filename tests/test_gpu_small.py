@@ -46,9 +46,17 @@ def _check_vs_oracle(orc, p, x, info, tol):
     return xr, ir
 
 
+def _single_one_wg(m, n):
+    """The documented single-solve rule of the one-workgroup path (FP64,
+    m <= 120): m n <= 2^17, or the n-vectors (36 bytes a feature) fit in
+    LDS beside the Newton matrix."""
+    return m <= 120 and (m * n <= 1 << 17 or n <= (150112 - 16 * (-(-m * (m + 1) // 4))) // 36)
+
+
 def _solve1(gpu, ctx, A, b, p, tol, x0=None, x_out=None, opts=None, m=None):
-    """A single solve that runs in one workgroup: ssnal_en_solve below the
-    single-solve limit (m n <= 2^17), else a batch of one (m n <= 2^21)."""
+    """A single solve that runs in one workgroup: ssnal_en_solve when
+    m n <= 2^17 (always within the single-solve rule), else a batch of one
+    (m n <= 2^21)."""
     import torch
     if p.m * p.n <= 1 << 17:
         return gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x0, x_out=x_out, tol=tol, opts=opts, m=m)
@@ -63,7 +71,8 @@ def _solve1(gpu, ctx, A, b, p, tol, x0=None, x_out=None, opts=None, m=None):
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_c1_one_workgroup_vs_oracle(gpu, ctx, orc, seed):
     """m=100, n=2000 Gaussian design, tol 1e-10, in one workgroup (a batch of
-    one: a single C1 solve is above the single-solve limit)."""
+    one); a single solve also runs in one workgroup (its n-vectors fit in
+    LDS) and gives the same bits; the multi-kernel path agrees to 1e-9."""
     import datagen
     p = datagen.make_problem("c1", seed=seed)
     _say("c1 one workgroup seed", seed)
@@ -72,10 +81,12 @@ def test_c1_one_workgroup_vs_oracle(gpu, ctx, orc, seed):
     assert info["one_workgroup"] == 1
     assert info["syncs"] == 1
     _check_vs_oracle(orc, p, x.cpu().numpy(), info, p.tol)
-    # alone it takes the multi-kernel path and reaches the same minimiser
     xs, si = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol)
-    assert si["one_workgroup"] == 0
-    assert np.max(np.abs(xs.cpu().numpy() - x.cpu().numpy())) <= 1e-9
+    assert si["one_workgroup"] == 1
+    assert np.array_equal(xs.cpu().numpy(), x.cpu().numpy())
+    xm, mi = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=p.tol, opts=gpu.make_opts(no_small=1))
+    assert mi["one_workgroup"] == 0
+    assert np.max(np.abs(xm.cpu().numpy() - x.cpu().numpy())) <= 1e-9
 
 
 def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
@@ -115,15 +126,23 @@ def test_ragged_and_maximum_shapes(gpu, ctx, orc, m, n, k, c_lam):
 
 
 def test_beyond_limits_takes_multi_kernel_path(gpu, ctx):
-    """m = 121, or m n above 2^17 for a single solve, or FP32 storage: the
-    multi-kernel path."""
+    """m = 121, or a single solve with m n above 2^17 whose n-vectors do not
+    fit in LDS (n > 3047 at m = 100, 2556 at m = 120), or FP32 storage: the
+    multi-kernel path.  Just inside the LDS rule above 2^17: one workgroup."""
     import datagen
-    for m, n, store in [(121, 1000, "f64"), (100, 1400, "f64"), (100, 1000, "f32")]:
+    for m, n, store in [(121, 1000, "f64"), (100, 3048, "f64"), (120, 2557, "f64"), (100, 1000, "f32")]:
         p = datagen.make_problem("c1", seed=3, m=m, n=n, store=store)
         A, b = _upload(p)
         _say("multi-kernel", m, n, store)
         x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-8)
         assert info["status"] == 0 and info["one_workgroup"] == 0
+        assert not _single_one_wg(m, n) or store != "f64"
+    for m, n in [(100, 3047), (120, 2556)]:
+        p = datagen.make_problem("c1", seed=3, m=m, n=n)
+        A, b = _upload(p)
+        _say("one workgroup at the LDS limit", m, n)
+        x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-8)
+        assert info["status"] == 0 and info["one_workgroup"] == 1 and _single_one_wg(m, n)
 
 
 def test_lasso_limit(gpu, ctx, orc):
@@ -292,7 +311,7 @@ def test_repeat_bitwise(gpu, ctx):
 
 def test_batch_one_launch_matches_single(gpu, ctx, orc):
     """A batch of 40 problems: 32 small FP64 ones (m from 20 to 120, m n up to
-    4.2e5, above the single-solve limit of 2^17; per-problem sigma0 on some)
+    4.2e5, some above the single-solve limits; per-problem sigma0 on some)
     run as one launch, one workgroup each, beside 8 others (m = 160, FP32
     storage) on the workers.  A small problem whose single solve also runs in
     one workgroup gives the same bits (same kernel, same summation order);
@@ -325,7 +344,7 @@ def test_batch_one_launch_matches_single(gpu, ctx, orc):
             opts = gpu.make_opts(sigma0=pr["sigma0"]) if pr["sigma0"] > 0 else None
             A, b = _upload(p)
             xs, si = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=opts)
-            assert si["one_workgroup"] == (1 if p.m * p.n <= 1 << 17 else 0), (i, si)
+            assert si["one_workgroup"] == (1 if _single_one_wg(p.m, p.n) else 0), (i, si)
             if si["one_workgroup"]:
                 assert np.array_equal(xs.cpu().numpy(), x), i
             else:

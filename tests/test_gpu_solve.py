@@ -92,14 +92,17 @@ def test_block_toeplitz_mixed(gpu, ctx, orc, store):
     print(f"[report] {store}: eta_stored={eta_stored:.3e} relobj_stored={_rel_obj(F, ir['primal_obj']):.3e}")
 
 
-def test_zero_solution(gpu, ctx, orc):
-    """lambda1 >= ||A^T b||_inf: x = 0 with r = 0 throughout."""
+@pytest.mark.parametrize("no_small", [0, 1])
+def test_zero_solution(gpu, ctx, orc, no_small):
+    """lambda1 >= ||A^T b||_inf: x = 0 with r = 0 throughout (in one workgroup
+    and on the multi-kernel path)."""
     import datagen
     p = datagen.make_problem("c1", seed=4)
     lmax = np.max(np.abs(p.AT @ p.b))
     A, b = _upload(p)
-    _say("zero solution")
-    x, info = gpu.ssnal_en_solve(ctx, A, b, lmax * 1.01, 0.3, tol=1e-10)
+    _say("zero solution", no_small)
+    x, info = gpu.ssnal_en_solve(ctx, A, b, lmax * 1.01, 0.3, tol=1e-10, opts=gpu.make_opts(no_small=no_small))
+    assert info["one_workgroup"] == 1 - no_small
     assert info["status"] == 0 and info["nnz"] == 0
     assert np.count_nonzero(x.cpu().numpy()) == 0
 
@@ -136,27 +139,34 @@ def test_edge_shapes(gpu, ctx, orc, m, n):
     assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-8
 
 
-def test_padded_lda_and_warm_start(gpu, ctx, orc):
-    """lda > m with NaN padding rows; a warm start reaches the same minimiser."""
+@pytest.mark.parametrize("no_small", [0, 1])
+def test_padded_lda_and_warm_start(gpu, ctx, orc, no_small):
+    """lda > m with NaN padding rows; a warm start reaches the same minimiser
+    (in one workgroup and on the multi-kernel path)."""
     import datagen
     p = datagen.make_problem("c1", seed=5)
     A, b = _upload(p, lda=p.m + 4)
-    _say("padded lda + warm start")
-    x_cold, ic = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, m=p.m)
-    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1 * 1.2, p.lam2 * 1.2, tol=1e-10, m=p.m)
-    x_warm, iw = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x1, tol=1e-10, m=p.m)
+    o = gpu.make_opts(no_small=no_small)
+    _say("padded lda + warm start", no_small)
+    x_cold, ic = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, m=p.m, opts=o)
+    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1 * 1.2, p.lam2 * 1.2, tol=1e-10, m=p.m, opts=o)
+    x_warm, iw = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, x0=x1, tol=1e-10, m=p.m, opts=o)
     assert ic["status"] == 0 and iw["status"] == 0
+    assert ic["one_workgroup"] == iw["one_workgroup"] == 1 - no_small
     xc, xw = x_cold.cpu().numpy(), x_warm.cpu().numpy()
     xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-11)
     assert np.max(np.abs(xc - xr)) <= 1e-8 and np.max(np.abs(xw - xr)) <= 1e-8
 
 
-def test_errors(gpu, ctx):
+@pytest.mark.parametrize("no_small", [0, 1])
+def test_errors(gpu, ctx, no_small):
+    """Invalid lambdas: SSNAL_EINVAL; non-finite b: SSNAL_ENONFINITE;
+    max_outer = 1 at a tight tol: SSNAL_NOT_CONVERGED (in one workgroup and
+    on the multi-kernel path)."""
     import datagen
-    import torch
     p = datagen.make_problem("c1", seed=6)
     A, b = _upload(p)
-    _say("errors")
+    _say("errors", no_small)
     with pytest.raises(gpu.SsnalError) as e:
         gpu.ssnal_en_solve(ctx, A, b, p.lam1, -0.1)  # lambda2 < 0 (0 is the Lasso limit)
     assert e.value.code == -1
@@ -168,17 +178,21 @@ def test_errors(gpu, ctx):
     with pytest.raises(gpu.SsnalError) as e:
         gpu.ssnal_en_solve(ctx, A, bn, p.lam1, p.lam2)
     assert e.value.code == -2
-    o = gpu.make_opts(max_outer=1)
+    o = gpu.make_opts(max_outer=1, no_small=no_small)
     x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-14, opts=o)
-    assert info["status"] == 1
+    assert info["status"] == 1 and info["one_workgroup"] == 1 - no_small
 
 
-def test_repeat_bitwise(gpu, ctx):
-    """Deterministic reductions: two solves of the same input agree bit for bit."""
+@pytest.mark.parametrize("no_small", [0, 1])
+def test_repeat_bitwise(gpu, ctx, no_small):
+    """Deterministic reductions: two solves of the same input agree bit for bit
+    (in one workgroup and on the multi-kernel path)."""
     import datagen
     p = datagen.make_problem("c1", seed=7)
     A, b = _upload(p)
-    _say("repeat")
-    x1, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
-    x2, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    o = gpu.make_opts(no_small=no_small)
+    _say("repeat", no_small)
+    x1, i1 = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=o)
+    x2, _ = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=o)
+    assert i1["one_workgroup"] == 1 - no_small
     assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
