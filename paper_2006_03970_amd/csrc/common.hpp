@@ -100,9 +100,33 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
   return t;
 }
 
+// K block sums at once (lds: K * NT / kWave entries): the bits of K calls
+// of block_sum, with one pair of barriers instead of K.
+template <int NT, int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* lds) {
+  constexpr int NW = NT / kWave;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k * NW + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = lds[k * NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) t += lds[k * NW + i];
+    v[k] = t;
+  }
+}
+
 // Sums of K components over nb partial rows part[b*K + k], by one block of
 // NT threads: thread t adds rows t, t+NT, ... (each row's K loads issued
-// together), then one tree per component.  out[k] is written by thread 0.
+// together), then one tree per component (lds: K * NT / kWave entries).
+// out[k] is written by thread 0.
 // Fixed partition and order: reproducible.
 template <int NT, int K>
 __device__ __forceinline__ void final_sums(const double* part, int nb, double* out, double* lds) {
@@ -116,10 +140,10 @@ __device__ __forceinline__ void final_sums(const double* part, int nb, double* o
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += row[k];
   }
+  block_sums<NT, K>(v, lds);
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double t = block_sum<NT>(v[k], lds);
-    if (threadIdx.x == 0) out[k] = t;
+    for (int k = 0; k < K; ++k) out[k] = v[k];
   }
 }
 

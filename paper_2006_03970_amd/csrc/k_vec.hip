@@ -48,7 +48,7 @@ template <int K>
 __global__ __launch_bounds__(kNT) void k_final(const double* __restrict__ part, int nb, double* out,
                                                const double* __restrict__ y, int m, double* yy_out,
                                                const double* scal, Pub pub) {
-  __shared__ double red[kNT / kWave];
+  __shared__ double red[K * kNT / kWave];
   final_sums<kNT, K>(part, nb, out, red);
   if (y) {
     double t = 0.0;
@@ -392,6 +392,22 @@ int gather_nchunks(int64_t r, int m) {
   return nc;
 }
 
+// sum_{c < nchunks} part[c m + row], added in chunk order, eight loads in
+// flight.
+__device__ __forceinline__ double chunk_sum(const double* __restrict__ part, int nchunks, int m, int row) {
+  double S = 0.0;
+  int c = 0;
+  for (; c + 8 <= nchunks; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + row];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) S += v[u];
+  }
+  for (; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+  return S;
+}
+
 __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict__ part,
                                                         const double* __restrict__ r_dev,
                                                         int64_t r_host, int m, int mode,
@@ -405,18 +421,7 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
   int64_t ck;
   chunk_plan(r, m, nchunks, ck);
   const int row = blockIdx.x * kNT + threadIdx.x;
-  double S = 0.0;
-  if (row < m) {
-    int c = 0;
-    for (; c + 8 <= nchunks; c += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + row];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) S += v[u];
-    }
-    for (; c < nchunks; ++c) S += part[(int64_t)c * m + row];
-  }
+  const double S = row < m ? chunk_sum(part, nchunks, m, row) : 0.0;
   double v1 = 0.0, v2 = 0.0, v3 = 0.0;
   if (row < m) {
     if (mode == 0) {  // gradient of psi (eq. grad_phy) and the primal residual A u - b
@@ -434,14 +439,13 @@ __global__ __launch_bounds__(kNT) void k_gather_finish(const double* __restrict_
     }
   }
   if (mode != 0) return;
-  __shared__ double red[kNT / kWave];
-  const double s1 = block_sum<kNT>(v1, red);
-  const double s2 = block_sum<kNT>(v2, red);
-  const double s3 = block_sum<kNT>(v3, red);
+  __shared__ double red[3 * kNT / kWave];
+  double sv[3] = {v1, v2, v3};
+  block_sums<kNT, 3>(sv, red);
   if (threadIdx.x == 0) {
-    blk[3 * blockIdx.x + 0] = s1;
-    blk[3 * blockIdx.x + 1] = s2;
-    blk[3 * blockIdx.x + 2] = s3;
+    blk[3 * blockIdx.x + 0] = sv[0];
+    blk[3 * blockIdx.x + 1] = sv[1];
+    blk[3 * blockIdx.x + 2] = sv[2];
   }
 }
 
@@ -462,16 +466,7 @@ __global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __rest
   chunk_plan((int64_t)(*r_dev), m, nchunks, ck);
   double v1 = 0.0, v2 = 0.0, v3 = 0.0;
   for (int row = threadIdx.x; row < m; row += kFin1NT) {
-    double S = 0.0;
-    int c = 0;
-    for (; c + 8 <= nchunks; c += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + u) * m + row];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) S += v[u];
-    }
-    for (; c < nchunks; ++c) S += part[(int64_t)c * m + row];
+    const double S = chunk_sum(part, nchunks, m, row);
     // gradient of psi (eq. grad_phy) and the primal residual A u - b
     const double gi = y[row] + b[row] - S;
     const double rh = S - b[row];
@@ -481,14 +476,13 @@ __global__ __launch_bounds__(kFin1NT) void k_gather_finish1(const double* __rest
     v2 += rh * rh;
     v3 += b[row] * rh;
   }
-  __shared__ double red[kFin1NT / kWave];
-  const double s1 = block_sum<kFin1NT>(v1, red);
-  const double s2 = block_sum<kFin1NT>(v2, red);
-  const double s3 = block_sum<kFin1NT>(v3, red);
+  __shared__ double red[3 * kFin1NT / kWave];
+  double sv[3] = {v1, v2, v3};
+  block_sums<kFin1NT, 3>(sv, red);
   if (threadIdx.x == 0) {
-    scal[SC_GG + 0] = s1;
-    scal[SC_GG + 1] = s2;
-    scal[SC_GG + 2] = s3;
+    scal[SC_GG + 0] = sv[0];
+    scal[SC_GG + 1] = sv[1];
+    scal[SC_GG + 2] = sv[2];
   }
   if (pub.flag) publish_block(scal, pub);
 }
