@@ -560,26 +560,41 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
           for (int k = 0; k <= i; ++k) M[tri(j0 + i) + j0 + k] = l[i][k];
         }
     }
-    // trailing update: M[i][j] -= sum_k L[i][j0+k] L[j][j0+k], j0+w <= j <= i < N
+    // trailing update M[i][j] -= sum_k L[i][j0+k] L[j][j0+k], j0+w <= j <= i < N
+    // (w = 8: only the last panel is narrower, and nothing trails it), on
+    // the FP64 matrix cores: one 16 x 16 block of the lower triangle per
+    // wave at a time, two 16x16x4 steps over the panel's 8 columns (the
+    // panel's columns are read, columns >= j0 + 8 written: no overlap)
     const int b = j0 + w, nt = N - b;
-    const int ne = nt * (nt + 1) / 2;
-    for (int e = c.tid; e < ne; e += c.nt) {
-      int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      while (i * (i + 1) / 2 > e) --i;
-      const int j = e - i * (i + 1) / 2;
-      const double* Li = M + tri(b + i) + j0;
-      const double* Lj = M + tri(b + j) + j0;
-      double s = M[tri(b + i) + b + j];
-      double li[8], lj[8];
+    const int nbk = (nt + 15) / 16;
+    const int nblk = nt > 0 ? nbk * (nbk + 1) / 2 : 0;
+    for (int blk = c.wid; blk < nblk; blk += c.nw) {
+      int bi = (int)((sqrtf(8.0f * (float)blk + 1.0f) - 1.0f) * 0.5f);
+      while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+      while (bi * (bi + 1) / 2 > blk) --bi;
+      const int bj = blk - bi * (bi + 1) / 2;
+      const int kq = c.lane >> 4, l16 = c.lane & 15;
+      // operands: A[i][k] = L[b + 16 bi + i][j0 + k], B[k][j] = L[b + 16 bj + j][j0 + k]
+      // (rows past nt clamped: they feed only outputs that are not stored)
+      const int ia = 16 * bi + l16, ja = 16 * bj + l16;
+      const double* La = M + tri(b + (ia < nt ? ia : nt - 1)) + j0;
+      const double* Lb = M + tri(b + (ja < nt ? ja : nt - 1)) + j0;
+      const double a0 = La[kq], a1 = La[kq + 4], b0 = Lb[kq], b1 = Lb[kq + 4];
+      // accumulator v: row 16 bi + kq + 4 v, column 16 bj + l16 of the trailing block
+      dbl4 acc;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        li[k] = Li[k < w ? k : w - 1];
-        lj[k] = Lj[k < w ? k : w - 1];
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * bi + kq + 4 * v, j = 16 * bj + l16;
+        const int ic = i < nt ? i : nt - 1;
+        acc[v] = M[tri(b + ic) + b + (j < ic ? j : ic)];
       }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0, b0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1, b1, acc, 0, 0, 0);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s = fma(k < w ? -li[k] : 0.0, lj[k], s);
-      M[tri(b + i) + b + j] = s;
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * bi + kq + 4 * v, j = 16 * bj + l16;
+        if (i < nt && j <= i) M[tri(b + i) + b + j] = acc[v];
+      }
     }
     __syncthreads();
   }
