@@ -402,3 +402,46 @@ def test_served_small_requests(gpu, ctx, orc):
         if p.store == "f64":
             assert info["one_workgroup"] == 1
             check_eta(orc, p.AT, p.b, x.cpu().numpy(), p.lam1, p.lam2, 1e-9, eta_gpu=info["kkt_rel"])
+
+
+def test_batch_lasso_and_not_converged(gpu, ctx, orc):
+    """A batch of one-workgroup problems mixing the Lasso (lambda2 = 0) with
+    elastic nets meets the oracle bar per problem and gives each problem's
+    single-solve bits; the same batch capped at one outer iteration at a
+    tight tol returns SSNAL_NOT_CONVERGED for every problem, with finite
+    certificates of the returned points."""
+    import datagen
+    import torch
+    probs, keep = [], []
+    for i in range(6):
+        p = datagen.make_problem("c1", seed=600 + i, m=40 + 13 * i, n=700 + 50 * i)
+        if i % 2 == 0:
+            p.lam2 = 0.0
+        A, b = _upload(p)
+        probs.append(dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=1e-10,
+                          x_out=torch.full((p.n,), float("nan"), dtype=torch.float64, device=A.device)))
+        keep.append(p)
+    _say("batch: lasso mix")
+    infos, rc = gpu.ssnal_en_solve_batch(ctx, probs)
+    assert rc == 0, infos
+    for pr, p, info in zip(probs, keep, infos):
+        assert info["one_workgroup"] == 1 and info["status"] == 0, info
+        x = pr["x_out"].cpu().numpy()
+        check_eta(orc, p.AT, p.b, x, p.lam1, p.lam2, 1e-10, eta_gpu=info["kkt_rel"])
+        xr, ir, _ = orc.en_solve(p.AT, p.b, p.lam1, p.lam2, tol=1e-11)
+        F = orc.primal_obj(p.AT, p.b, x, p.lam1, p.lam2)
+        assert _rel_obj(F, ir["primal_obj"]) <= 1e-10, (F, ir["primal_obj"])
+        assert _support_ok(x, xr)
+        xs, si = gpu.ssnal_en_solve(ctx, pr["A"], pr["b"], p.lam1, p.lam2, tol=1e-10)
+        assert si["one_workgroup"] == 1
+        assert np.array_equal(xs.cpu().numpy(), x)
+    _say("batch: max_outer = 1")
+    for pr in probs:
+        pr["tol"] = 1e-14
+        pr["x_out"].fill_(float("nan"))
+    infos, rc = gpu.ssnal_en_solve_batch(ctx, probs, opts=gpu.make_opts(max_outer=1))
+    assert rc == 1
+    for pr, info in zip(probs, infos):
+        assert info["one_workgroup"] == 1 and info["status"] == 1 and info["outer_iters"] == 1, info
+        assert np.isfinite(info["kkt_rel"]) and info["kkt_rel"] > 1e-14
+        assert bool(torch.isfinite(pr["x_out"]).all())
