@@ -403,7 +403,14 @@ __device__ __noinline__ void sm_gather(GCD A, int64_t lda, typename V::CI J, typ
 // Newton matrix into M (lower triangle), FP64 MFMA 16x16x4 straight from A:
 //   form 0: M = I_m + kappa A_J A_J^T      (N = m, contraction over the r columns)
 //   form 1: M = I_r / kappa + A_J^T A_J    (N = r, contraction over the m rows)
-// 16 x 16 blocks of the lower triangle round-robin over the waves.
+// 16 x 16 blocks of the lower triangle round-robin over the waves.  In form
+// 1 with every column 16-byte aligned (A aligned, lda even), a lane loads
+// the row pair (8 t + 2 q, 8 t + 2 q + 1), q = lane / 16, of its column
+// with one 16-byte load and feeds the two rows to two 16x16x4 steps (the
+// contraction taken in that fixed order, the same for both operands): half
+// the load instructions, which bound one CU's rate from the caches.  A
+// pair that straddles an odd m reads row m inside the padded leading
+// dimension and masks it.
 template <class V>
 __device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64_t r, int form, double kappa,
                                      SmallCtx c) {
@@ -413,6 +420,7 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64
   const int64_t K = form ? (int64_t)m : r;
   const int nbk = (N + 15) / 16;
   const int nblk = nbk * (nbk + 1) / 2;
+  const bool pairs = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 1) == 0;
   for (int blk = c.wid; blk < nblk; blk += c.nw) {
     int bi = (int)((sqrtf(8.0f * (float)blk + 1.0f) - 1.0f) * 0.5f);
     while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
@@ -454,7 +462,33 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64
         }
       }
     };
-    if (form)
+    // form 1, aligned columns: row pairs by 16-byte loads
+    auto contract_pairs = [&]() {
+      constexpr int U2 = 8;
+      const int q2 = 2 * (c.lane / 16);
+      for (int64_t k0 = 0; k0 < K; k0 += 8 * U2) {
+        d2v av[U2], bv[U2];
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const int64_t row = k0 + 8 * u + q2;
+          const int64_t rc = row < K ? row : 0;
+          av[u] = *reinterpret_cast<GCD2>(ca + rc);
+          bv[u] = *reinterpret_cast<GCD2>(cb + rc);
+        }
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const int64_t row = k0 + 8 * u + q2;
+          const bool ok0 = row < K, ok1 = row + 1 < K;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok0 & oka) ? av[u][0] : 0.0, (ok0 & okb) ? bv[u][0] : 0.0,
+                                                     acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok1 & oka) ? av[u][1] : 0.0, (ok1 & okb) ? bv[u][1] : 0.0,
+                                                     acc, 0, 0, 0);
+        }
+      }
+    };
+    if (form && pairs)
+      contract_pairs();
+    else if (form)
       contract(std::false_type{});
     else
       contract(std::true_type{});
