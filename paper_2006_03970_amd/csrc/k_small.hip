@@ -754,21 +754,32 @@ __device__ __noinline__ int64_t sm_prox(typename V::D x, typename V::D wy, typen
   const int64_t S = ((n + c.nt - 1) / c.nt) * kWave;
   const int64_t lo = (int64_t)c.wid * S;
   const int64_t hi = lo + S < n ? lo + S : n;
+  // both passes take four chunks of 64 at a time, their loads issued
+  // together (indices clamped into the slab)
+  constexpr int Q = 4;
   int cnt = 0;
-  for (int64_t i0 = lo; i0 < hi; i0 += kWave) {
-    const int64_t i = i0 + c.lane;
-    const bool in = i < hi;
-    const int64_t ic = in ? i : hi - 1;
-    double w = wy[ic];
-    const double dw = wd[ic];  // unconditional: a load in a branch would wait at the join
-    const double xi = x[ic];
-    if (s != 0.0) {
-      w = fma(s, dw, w);
-      if (in) wy[i] = w;
+  for (int64_t i0 = lo; i0 < hi; i0 += Q * kWave) {
+    double w[Q], dw[Q], xi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = i0 + q * kWave + c.lane;
+      const int64_t ic = i < hi ? i : hi - 1;
+      w[q] = wy[ic];
+      dw[q] = wd[ic];  // unconditional: a load in a branch would wait at the join
+      xi[q] = x[ic];
     }
-    const double t = fma(-sigma, w, xi);
-    const bool act = in & ((t > thr) | (t < -thr));
-    cnt += __builtin_popcountll(__builtin_amdgcn_ballot_w64(act));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = i0 + q * kWave + c.lane;
+      const bool in = i < hi;
+      if (s != 0.0) {
+        w[q] = fma(s, dw[q], w[q]);
+        if (in) wy[i] = w[q];
+      }
+      const double t = fma(-sigma, w[q], xi[q]);
+      const bool act = in & ((t > thr) | (t < -thr));
+      cnt += __builtin_popcountll(__builtin_amdgcn_ballot_w64(act));
+    }
   }
   if (c.lane == 0) sl().cnt[c.wid] = cnt;
   __syncthreads();
@@ -778,19 +789,29 @@ __device__ __noinline__ int64_t sm_prox(typename V::D x, typename V::D wy, typen
     base += w2 < c.wid ? v : 0;
     r += v;
   }
-  for (int64_t i0 = lo; i0 < hi; i0 += kWave) {
-    const int64_t i = i0 + c.lane;
-    const bool in = i < hi;
-    const int64_t ic = in ? i : hi - 1;
-    const double t = fma(-sigma, wy[ic], x[ic]);
-    const bool act = in & ((t > thr) | (t < -thr));
-    const uint64_t bal = __builtin_amdgcn_ballot_w64(act);
-    if (act) {
-      const int pos = base + __builtin_popcountll(bal & ((1ull << c.lane) - 1ull));
-      J[pos] = (int32_t)i;
-      uJ[pos] = prox_en(t, thr, den);
+  for (int64_t i0 = lo; i0 < hi; i0 += Q * kWave) {
+    double w[Q], xi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = i0 + q * kWave + c.lane;
+      const int64_t ic = i < hi ? i : hi - 1;
+      w[q] = wy[ic];
+      xi[q] = x[ic];
     }
-    base += __builtin_popcountll(bal);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = i0 + q * kWave + c.lane;
+      const bool in = i < hi;
+      const double t = fma(-sigma, w[q], xi[q]);
+      const bool act = in & ((t > thr) | (t < -thr));
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(act);
+      if (act) {
+        const int pos = base + __builtin_popcountll(bal & ((1ull << c.lane) - 1ull));
+        J[pos] = (int32_t)i;
+        uJ[pos] = prox_en(t, thr, den);
+      }
+      base += __builtin_popcountll(bal);
+    }
   }
   __syncthreads();  // J and u_J complete for every thread; cnt read
   return r;
@@ -816,10 +837,18 @@ __device__ __noinline__ int sm_linesearch(typename V::CD x, typename V::CD wy, t
     double sk[kSmLsChunk];
 #pragma unroll
     for (int k = 0; k < kSmLsChunk; ++k) sk[k] = k0 + k < K ? ts[k0 + k] : 0.0;
+    // each iteration loads the next feature's values first (index clamped),
+    // so the loads overlap the current feature's work
+    int64_t ic = c.tid < n ? c.tid : n - 1;
+    double xn = x[ic], yn = wy[ic], dn = wd[ic];
 #pragma unroll 1
     for (int64_t i = c.tid; i < n; i += c.nt) {
-      const double t0 = fma(-sigma, wy[i], x[i]);
-      const double wi = wd[i];
+      const double t0 = fma(-sigma, yn, xn);
+      const double wi = dn;
+      ic = i + c.nt < n ? i + c.nt : n - 1;
+      xn = x[ic];
+      yn = wy[ic];
+      dn = wd[ic];
       const double a0 = fabs(t0);
       const double reach = smax * sigma * fabs(wi) * (1.0 + 1e-12);
       if (a0 + reach < thr) continue;  // inactive for every trial step
