@@ -110,12 +110,15 @@ def test_agrees_with_multi_kernel_path(gpu, ctx, orc):
 
 
 @pytest.mark.parametrize("m,n,k,c_lam", [(37, 2001, 5, 0.5), (120, 1092, 12, 0.5), (64, 513, 40, 0.05),
-                                         (100, 40, 8, 0.5), (120, 17000, 12, 0.5)])
+                                         (100, 40, 8, 0.5), (120, 17000, 12, 0.5), (120, 2000, 90, 0.5),
+                                         (120, 2000, 60, 0.45)])
 def test_ragged_and_maximum_shapes(gpu, ctx, orc, m, n, k, c_lam):
     """m off the 16-row MFMA blocks and the 8-column Cholesky panels, n off the
     feature slabs, the largest m (120) at the single-solve limit m n <= 2^17
-    and near the batch limit 2^21 (a batch of one), m > n, and an active set
-    larger than m (160 of 513 at m = 64: the m x m system)."""
+    and near the batch limit 2^21 (a batch of one), m > n, an active set
+    larger than m (160 of 513 at m = 64: the m x m system), and many active
+    features at m = 120 (r x r systems of 86 to 151 rows: past 64, two rows
+    a lane in the one-wave triangular solves)."""
     import datagen
     p = datagen.make_problem("c1", seed=m + n, m=m, n=n, k=k, c_lam=c_lam)
     A, b = _upload(p)
