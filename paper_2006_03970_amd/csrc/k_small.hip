@@ -11,19 +11,21 @@
 //
 // One workgroup of 256 threads per problem, single or batched (the same
 // summation orders, so a batched problem gives its single solve's bits);
-// at most 256 registers a lane and 69 KB of LDS at m = 120 (the Newton
-// matrix packed as a lower triangle), so two problems can share a CU.
-// A (FP64, column-major, lda >= m) and the n-vectors (x, w_y = A^T y, w_d = A^T d,
-// the active set J and u_J) stay in global memory (cache-resident at these
-// sizes); the m-vectors (y, g, d, rho, b), the Newton matrix and its
-// Cholesky factor live in LDS.  Per Newton step, in the order of the
+// at most 256 registers a lane.  A (FP64, column-major, lda >= m) stays in
+// global memory (cache-resident at these sizes); the m-vectors (y, g, d,
+// rho, b), the Newton matrix (packed as a lower triangle: 58 KB at m = 120)
+// and its Cholesky factor live in LDS, and so do the n-vectors (x,
+// w_y = A^T y, w_d = A^T d, the active set J and u_J: 36 bytes a feature)
+// when they fit beside them, else they stay in global memory (two problems
+// can then share a CU).  Per Newton step, in the order of the
 // multi-kernel path (and of eq. grad_phy, eq. AJ_system / eq. smw_formula,
 // eq. line_search):
 //   t = x - sigma w_y, J = {|t| > sigma lambda1} in index order, u_J =
 //   prox(t)_J (eq. prox_elastic); g = y + b - A_J u_J; kkt1 (eq. kkt_res);
 //   the Newton matrix I + kappa A_J A_J^T (r >= m) or I/kappa + A_J^T A_J
 //   (r < m) on FP64 MFMA straight from A; its Cholesky in LDS (8-column
-//   panels); d; w_d = A^T d; the trial steps of the line search;
+//   panels, the trailing updates on FP64 MFMA); the triangular solves in
+//   one wave; d; w_d = A^T d; the trial steps of the line search;
 //   y += s d, w_y += s w_d.
 // The multiplier update, kkt3 and the certificate eta (with F and D of
 // Prop. 1) follow each inner loop as in the multi-kernel path.  Every sum is
