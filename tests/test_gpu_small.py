@@ -448,3 +448,29 @@ def test_batch_lasso_and_not_converged(gpu, ctx, orc):
         assert info["one_workgroup"] == 1 and info["status"] == 1 and info["outer_iters"] == 1, info
         assert np.isfinite(info["kkt_rel"]) and info["kkt_rel"] > 1e-14
         assert bool(torch.isfinite(pr["x_out"]).all())
+
+
+@pytest.mark.parametrize("bad", [float("inf"), float("nan")])
+def test_nonfinite_design(gpu, ctx, bad):
+    """An Inf or NaN entry of A is refused with SSNAL_ENONFINITE by the single
+    solve in one workgroup, by a batch of one, and by the multi-kernel path;
+    the context keeps working afterwards."""
+    import datagen
+    import torch
+    p = datagen.make_problem("c1", seed=700, n=1000)
+    A, b = _upload(p)
+    A[7, 5] = bad  # row 7 of the (n, lda) array: column 7 of A, row 5
+    _say("non-finite design", bad)
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert e.value.code == -2
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10, opts=gpu.make_opts(no_small=1))
+    assert e.value.code == -2
+    x = torch.empty(p.n, dtype=torch.float64, device=A.device)
+    with pytest.raises(gpu.SsnalError) as e:
+        gpu.ssnal_en_solve_batch(ctx, [dict(A=A, b=b, lambda1=p.lam1, lambda2=p.lam2, tol=1e-10, x_out=x)])
+    assert e.value.code == -2
+    A[7, 5] = float(p.AT[7, 5])
+    x, info = gpu.ssnal_en_solve(ctx, A, b, p.lam1, p.lam2, tol=1e-10)
+    assert info["status"] == 0 and info["one_workgroup"] == 1
