@@ -105,26 +105,6 @@ struct SmallCtx {
   int m;
 };
 
-// Sum of K values over the block (every thread receives the K sums; waves
-// are combined in index order).
-template <int K>
-__device__ __forceinline__ void bsum(double (&v)[K], const SmallCtx& c) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (c.lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) sl().red[c.wid * K + k] = v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double t = sl().red[k];
-    for (int w = 1; w < c.nw; ++w) t += sl().red[w * K + k];
-    v[k] = t;
-  }
-}
-
 // Sum over the 16 lanes of each row; every lane of the row gets the same bits.
 __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<kQuadXor1>(v);
@@ -132,6 +112,34 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<kRowHalfMirror>(v);
   v += dpp_d<kRowMirror>(v);
   return v;
+}
+
+// Sum of K values over the block (every thread receives the K sums): each
+// 16-lane row sums with DPP, the first lane of every row stores its row's
+// K sums, lane k of every wave adds value k's 16 row sums in (wave, row)
+// order, and readlane hands value k from lane k to the wave.  A broadcast
+// through a scalar register costs about 70 cycles before its first use;
+// this takes K of them in one batch, against 4 K for a wave-wide sum per
+// value.
+template <int K>
+__device__ __forceinline__ void bsum(double (&v)[K], const SmallCtx& c) {
+  constexpr int kRows = kSmWaves * 4;
+  static_assert(K * kRows <= kSmWaves * 36 && K <= kWave, "row sums fit the reduction buffer");
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = row16_sum(v[k]);
+  __syncthreads();
+  if ((c.lane & 15) == 0) {
+    const int row = c.wid * 4 + (c.lane >> 4);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sl().red[row * K + k] = v[k];
+  }
+  __syncthreads();
+  const int kk = c.lane < K ? c.lane : K - 1;
+  double t = sl().red[kk];
+#pragma unroll
+  for (int i = 1; i < kRows; ++i) t += sl().red[i * K + kk];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = readlane_d(t, k);
 }
 
 // Sum over the 8 lanes of each half-row; every lane of the half gets the same
