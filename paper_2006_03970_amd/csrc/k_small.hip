@@ -651,7 +651,10 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
 // l + 64 of the right-hand side; at column k the lane holding row k scales
 // it, readlane hands the value to every lane, and each lane takes its
 // row's term.  The entries of L a lane needs are loaded eight columns ahead
-// (unconditional, indices clamped into the row, terms masked).  Forward,
+// (unconditional, indices clamped into the row) and zeroed where the row
+// takes no term, so a step is a multiply, a broadcast and an FMA; a row's
+// value stops changing once its column has passed, so the values handed
+// out are recomputed at the end with the same operation.  Forward,
 // each row adds its terms in column order; backward (L^T x = y, row k of
 // L^T is column k of L, a contiguous row slice across the lanes), in
 // descending column order.  The other waves wait at the closing barrier.
@@ -676,8 +679,12 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
       for (int u = 0; u < 8; ++u) {
         const int k = k0 + u;
         ib[u] = idg[k < N ? k : N - 1];
-        a0[u] = M[b0 + (k < q0 ? k : 0)];
-        if (TWO) a1[u] = M[b1 + (k < q1 ? k : 0)];
+        const double v0 = M[b0 + (k < q0 ? k : 0)];
+        a0[u] = k < r0 ? v0 : 0.0;  // zero where the row takes no term: -0 y leaves it as it is
+        if (TWO) {
+          const double v1 = M[b1 + (k < q1 ? k : 0)];
+          a1[u] = k < r1 ? v1 : 0.0;
+        }
       }
     };
     auto step = [&](const double (&a0)[8], const double (&a1)[8], const double (&ib)[8], int k0) {
@@ -686,8 +693,8 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
         const int k = k0 + u;  // k >= N: no row takes a term
         const double t = (TWO && k >= kWave ? z1 : z0) * ib[u];
         const double y = readlane_d(t, k & (kWave - 1));
-        z0 = k < r0 ? fma(-a0[u], y, z0) : z0;
-        if (TWO) z1 = k < r1 ? fma(-a1[u], y, z1) : z1;
+        z0 = fma(-a0[u], y, z0);
+        if (TWO) z1 = fma(-a1[u], y, z1);
       }
     };
     double a0[8], a1[8], ib[8], c0[8], c1[8], cb[8];
@@ -705,14 +712,17 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
   if (TWO) z1 *= idg[q1];
   // backward: L^T x = y; row i takes -L_ki x_k for k > i, k descending
   {
-    double x0 = 0.0, x1 = 0.0;
     auto load = [&](double (&a0)[8], double (&a1)[8], double (&ib)[8], int k0) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int k = k0 - u < 0 ? 0 : k0 - u;
         ib[u] = idg[k];
-        a0[u] = M[tri(k) + (r0 < k ? r0 : k)];
-        if (TWO) a1[u] = M[tri(k) + (r1 < k ? r1 : k)];
+        const double v0 = M[tri(k) + (r0 < k ? r0 : k)];
+        a0[u] = r0 < k0 - u ? v0 : 0.0;  // k0 - u < 0: no row takes a term
+        if (TWO) {
+          const double v1 = M[tri(k) + (r1 < k ? r1 : k)];
+          a1[u] = r1 < k0 - u ? v1 : 0.0;
+        }
       }
     };
     auto step = [&](const double (&a0)[8], const double (&a1)[8], const double (&ib)[8], int k0) {
@@ -721,10 +731,8 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
         const int k = k0 - u;  // k < 0: no row takes a term
         const double t = (TWO && k >= kWave ? z1 : z0) * ib[u];
         const double x = readlane_d(t, k & (kWave - 1));
-        x0 = r0 == k ? x : x0;
-        if (TWO) x1 = r1 == k ? x : x1;
-        z0 = r0 < k ? fma(-a0[u], x, z0) : z0;
-        if (TWO) z1 = r1 < k ? fma(-a1[u], x, z1) : z1;
+        z0 = fma(-a0[u], x, z0);
+        if (TWO) z1 = fma(-a1[u], x, z1);
       }
     };
     double a0[8], a1[8], ib[8], c0[8], c1[8], cb[8];
@@ -737,8 +745,10 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
       load(a0, a1, ib, k0 - 16);
       step(c0, c1, cb, k0 - 8);
     }
-    if (r0 < N) sm_dyn[x_off + r0] = x0;
-    if (TWO && r1 < N) sm_dyn[x_off + r1] = x1;
+    // a row's value stops changing once its column has passed: x_i is the
+    // value the sweep handed out at column i, recomputed here
+    if (r0 < N) sm_dyn[x_off + r0] = z0 * idg[q0];
+    if (TWO && r1 < N) sm_dyn[x_off + r1] = z1 * idg[q1];
   }
 }
 
