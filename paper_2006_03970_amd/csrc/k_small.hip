@@ -594,11 +594,14 @@ __device__ __noinline__ int sm_cholesky(int N, SmallCtx c) {
         if (k < w) M[tri(R) + j0 + k] = x[k];
     }
     __syncthreads();
-    // the pivot block's L and 1 / L_kk (compile-time row index: l stays in registers)
-    if (c.tid < w) {
+    // the pivot block's L and 1 / L_kk (compile-time row index: l stays in
+    // registers), by the first lanes of the last wave, which takes the
+    // fewest trailing blocks below
+    const int pl = c.tid - (c.nt - kWave);
+    if (pl >= 0 && pl < w) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        if (c.tid == i) {
+        if (pl == i) {
           sl().idg[j0 + i] = rl[i];
 #pragma unroll
           for (int k = 0; k <= i; ++k) M[tri(j0 + i) + j0 + k] = l[i][k];
