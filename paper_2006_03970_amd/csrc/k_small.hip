@@ -675,13 +675,15 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
   const int b0 = tri(q0), b1 = tri(q1);
   double z0 = r0 < N ? sm_dyn[rhs_off + r0] : 0.0;
   double z1 = TWO && r1 < N ? sm_dyn[rhs_off + r1] : 0.0;
+  // each lane scales its own rows (1 / L_ii in a register), so the lane
+  // that owns column k hands out z_k / L_kk with no broadcast load
+  const double d0 = idg[q0], d1 = TWO ? idg[q1] : 0.0;
   // forward: L y = rhs; row i takes -L_ik y_k for k < i
   {
-    auto load = [&](double (&a0)[8], double (&a1)[8], double (&ib)[8], int k0) {
+    auto load = [&](double (&a0)[8], double (&a1)[8], int k0) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int k = k0 + u;
-        ib[u] = idg[k < N ? k : N - 1];
         const double v0 = M[b0 + (k < q0 ? k : 0)];
         a0[u] = k < r0 ? v0 : 0.0;  // zero where the row takes no term: -0 y leaves it as it is
         if (TWO) {
@@ -690,36 +692,35 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
         }
       }
     };
-    auto step = [&](const double (&a0)[8], const double (&a1)[8], const double (&ib)[8], int k0) {
+    auto step = [&](const double (&a0)[8], const double (&a1)[8], int k0) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int k = k0 + u;  // k >= N: no row takes a term
-        const double t = (TWO && k >= kWave ? z1 : z0) * ib[u];
+        const double t = TWO && k >= kWave ? z1 * d1 : z0 * d0;
         const double y = readlane_d(t, k & (kWave - 1));
         z0 = fma(-a0[u], y, z0);
         if (TWO) z1 = fma(-a1[u], y, z1);
       }
     };
-    double a0[8], a1[8], ib[8], c0[8], c1[8], cb[8];
-    load(a0, a1, ib, 0);
+    double a0[8], a1[8], c0[8], c1[8];
+    load(a0, a1, 0);
     for (int k0 = 0; k0 < N; k0 += 16) {
-      load(c0, c1, cb, k0 + 8);
-      step(a0, a1, ib, k0);
+      load(c0, c1, k0 + 8);
+      step(a0, a1, k0);
       if (k0 + 8 >= N) break;
-      load(a0, a1, ib, k0 + 16);
-      step(c0, c1, cb, k0 + 8);
+      load(a0, a1, k0 + 16);
+      step(c0, c1, k0 + 8);
     }
   }
   // y_i = z_i / L_ii (the value the sweep handed out at column i)
-  z0 *= idg[q0];
-  if (TWO) z1 *= idg[q1];
+  z0 *= d0;
+  if (TWO) z1 *= d1;
   // backward: L^T x = y; row i takes -L_ki x_k for k > i, k descending
   {
-    auto load = [&](double (&a0)[8], double (&a1)[8], double (&ib)[8], int k0) {
+    auto load = [&](double (&a0)[8], double (&a1)[8], int k0) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int k = k0 - u < 0 ? 0 : k0 - u;
-        ib[u] = idg[k];
         const double v0 = M[tri(k) + (r0 < k ? r0 : k)];
         a0[u] = r0 < k0 - u ? v0 : 0.0;  // k0 - u < 0: no row takes a term
         if (TWO) {
@@ -728,30 +729,30 @@ __device__ __forceinline__ void chol_solve_wave(int N, int rhs_off, int x_off, i
         }
       }
     };
-    auto step = [&](const double (&a0)[8], const double (&a1)[8], const double (&ib)[8], int k0) {
+    auto step = [&](const double (&a0)[8], const double (&a1)[8], int k0) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int k = k0 - u;  // k < 0: no row takes a term
-        const double t = (TWO && k >= kWave ? z1 : z0) * ib[u];
+        const double t = TWO && k >= kWave ? z1 * d1 : z0 * d0;
         const double x = readlane_d(t, k & (kWave - 1));
         z0 = fma(-a0[u], x, z0);
         if (TWO) z1 = fma(-a1[u], x, z1);
       }
     };
-    double a0[8], a1[8], ib[8], c0[8], c1[8], cb[8];
+    double a0[8], a1[8], c0[8], c1[8];
     const int top = N - 1;
-    load(a0, a1, ib, top);
+    load(a0, a1, top);
     for (int k0 = top; k0 >= 0; k0 -= 16) {
-      load(c0, c1, cb, k0 - 8);
-      step(a0, a1, ib, k0);
+      load(c0, c1, k0 - 8);
+      step(a0, a1, k0);
       if (k0 - 8 < 0) break;
-      load(a0, a1, ib, k0 - 16);
-      step(c0, c1, cb, k0 - 8);
+      load(a0, a1, k0 - 16);
+      step(c0, c1, k0 - 8);
     }
     // a row's value stops changing once its column has passed: x_i is the
     // value the sweep handed out at column i, recomputed here
-    if (r0 < N) sm_dyn[x_off + r0] = z0 * idg[q0];
-    if (TWO && r1 < N) sm_dyn[x_off + r1] = z1 * idg[q1];
+    if (r0 < N) sm_dyn[x_off + r0] = z0 * d0;
+    if (TWO && r1 < N) sm_dyn[x_off + r1] = z1 * d1;
   }
 }
 
