@@ -476,6 +476,9 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64
     auto contract_pairs = [&]() {
       constexpr int U2 = 8;
       const int q2 = 2 * (c.lane / 16);
+      // the second row of each pair goes to a second accumulator, added at
+      // the end: two dependent MFMA chains of half the length
+      dbl4 acc2 = dbl4{0, 0, 0, 0};
       for (int64_t k0 = 0; k0 < K; k0 += 8 * U2) {
         d2v av[U2], bv[U2];
 #pragma unroll
@@ -491,10 +494,11 @@ __device__ __noinline__ void sm_gram(GCD A, int64_t lda, typename V::CI J, int64
           const bool ok0 = row < K, ok1 = row + 1 < K;
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok0 & oka) ? av[u][0] : 0.0, (ok0 & okb) ? bv[u][0] : 0.0,
                                                      acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok1 & oka) ? av[u][1] : 0.0, (ok1 & okb) ? bv[u][1] : 0.0,
-                                                     acc, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64((ok1 & oka) ? av[u][1] : 0.0, (ok1 & okb) ? bv[u][1] : 0.0,
+                                                      acc2, 0, 0, 0);
         }
       }
+      acc += acc2;
     };
     if (form && pairs)
       contract_pairs();
