@@ -14,8 +14,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // ---------------------------------------------------------------- reductions
 // Wave sums on DPP lane permutations (no LDS traffic): xor-1 and xor-2
 // inside quads, then the half-row and row mirrors, which leaves every lane of
-// a 16-lane row holding the row sum; the four row sums are read out and
-// added in a fixed order.  At each step a lane adds the same two values as
+// a 16-lane row holding the row sum; the four row sums are then combined
+// across rows with permlane swaps in a fixed order.  At each step a lane adds
+// the same two values as
 // its partner (a + b == b + a), so every lane ends with the same bits and
 // the result is reproducible run to run.  All 64 lanes must be active.
 template <int CTRL>
@@ -43,38 +44,73 @@ constexpr int kQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 
+// Cross-row steps of the wave sums (gfx950 permlane swaps, plain vector
+// operations): with a value per 16-lane row r0..r3 in every lane of its row,
+// pair_rows gives every lane r(2p) + r(2p + 1) of its row pair and then
+// pair_halves (lower 32 lanes + upper 32 lanes) gives (r0 + r1) + (r2 + r3)
+// in every lane: the operands and order of a sum of the four rows' first
+// lanes, without a broadcast through a scalar register (about 70 cycles
+// before its first use).
+__device__ __forceinline__ double pair_rows(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double pair_halves(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ float pair_rows(float v) {
+  const auto x = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float((int)x[0]) + __int_as_float((int)x[1]);
+}
+__device__ __forceinline__ float pair_halves(float v) {
+  const auto x = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float((int)x[0]) + __int_as_float((int)x[1]);
+}
+__device__ __forceinline__ int pair_rows(int v) {
+  const auto x = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (int)x[0] + (int)x[1];
+}
+__device__ __forceinline__ int pair_halves(int v) {
+  const auto x = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (int)x[0] + (int)x[1];
+}
+
+// Sum over the wave; every lane receives the same bits.
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_d<kQuadXor1>(v);
   v += dpp_d<kQuadXor2>(v);
   v += dpp_d<kRowHalfMirror>(v);
   v += dpp_d<kRowMirror>(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  return pair_halves(pair_rows(v));
 }
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f<kQuadXor1>(v);
   v += dpp_f<kQuadXor2>(v);
   v += dpp_f<kRowHalfMirror>(v);
   v += dpp_f<kRowMirror>(v);
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+  return pair_halves(pair_rows(v));
 }
 __device__ __forceinline__ int wave_sum(int v) {
   v += dpp_i<kQuadXor1>(v);
   v += dpp_i<kQuadXor2>(v);
   v += dpp_i<kRowHalfMirror>(v);
   v += dpp_i<kRowMirror>(v);
-  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
-         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+  return pair_halves(pair_rows(v));
 }
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_d<kQuadXor1>(v));
   v = fmax(v, dpp_d<kQuadXor2>(v));
   v = fmax(v, dpp_d<kRowHalfMirror>(v));
   v = fmax(v, dpp_d<kRowMirror>(v));
-  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+  auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  v = fmax(__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1]));
+  lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return fmax(__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1]));
 }
 // Sum over aligned groups of 8 lanes (every lane of a group gets the sum);
 // only the lanes of each group need to be active.
