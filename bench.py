@@ -73,19 +73,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def _traffic_from_profile(kernel_src, store):
+def _traffic_from_profile(kernel_srcs, store):
     """HBM bytes per A^T v launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
+    if it was taken on the current kernel sources (the kernel file and the
+    device helpers it includes; else None)."""
     path = os.path.join(ROOT, "profiles", f"gemv_t_block_toeplitz_m500_n100000_{store}_pmc.txt")
     if not os.path.exists(path):
         return None
-    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for src in kernel_srcs:
+        h.update(open(src, "rb").read())
+    digest = h.hexdigest()
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != digest:
+    if vals.get("kernel_sources_sha256") != digest:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -913,7 +917,8 @@ def main():
         """Effective solve bandwidth: full A^T v passes per solve x m n s_A / solve time."""
         passes = sum(i["gemv_calls"] for i in infos) / len(infos)
         return passes * float(p64.m) * p64.n * s_a / (el / args.steps) / 1e9, passes
-    traffic = _traffic_from_profile(os.path.join(ROOT, "paper_2006_03970_amd", "csrc", "k_gemv.hip"), "f32")
+    csrc = os.path.join(ROOT, "paper_2006_03970_amd", "csrc")
+    traffic = _traffic_from_profile([os.path.join(csrc, "k_gemv.hip"), os.path.join(csrc, "common.hpp")], "f32")
 
     out = {
         "metric": "EN solves/s at KKT<=1e-6 (mixed FP32 storage)",
